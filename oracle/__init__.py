@@ -1,0 +1,215 @@
+"""CPU oracle for the MERBIT hot path -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the package smoke check and the benchmark's CPU-baseline leg
+may import this module.  The product path never calls it.  It wraps the plain
+sequential C in ``merbit_oracle.c`` (built with gcc, no OpenMP) plus a few
+numpy helpers that restate the paper's closed forms.
+
+Every function cites the part of the paper ("MERBIT: A GPU-Based SpMV Method
+for Iterative Workloads") it follows.  Functions and their pins:
+
+* ``spmv`` (Sec. 3.1) -- pinned by dense brute force and special matrices.
+* ``path_coords`` (Sec. 3.3 walk) and ``merge_search`` (Algorithm 1) -- two
+  derivations pinned against each other on every diagonal and against the
+  step string built row by row.
+* ``plan`` (Sec. 4.1) -- pinned by the worked example of Sec. 4.1.1, by the
+  closed forms for tile_num / lane_num / field widths, by invariants and by
+  ``plan_replay`` reproducing ``spmv`` bit for bit.
+* ``pagerank`` (Sec. 5.5.1) -- pinned by closed-form cases, by a dense direct
+  solve of the stationary equation and by the mass / contraction invariants.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "merbit_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_i32 = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_u32 = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+_f64 = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+
+
+def build() -> str:
+    """Compile the oracle with gcc (single threaded, -O2)."""
+    tmp = _LIB + ".tmp"
+    subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC,
+                    "-lm"], check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    c_i64, c_int, c_dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    lib.or_spmv.restype = None
+    lib.or_spmv.argtypes = [c_i64, _i32, _i32, _f64, _f64, _f64]
+    lib.or_abs_spmv.restype = None
+    lib.or_abs_spmv.argtypes = [c_i64, _i32, _i32, _f64, _f64, _f64]
+    lib.or_path_coords.restype = None
+    lib.or_path_coords.argtypes = [c_i64, _i32, _i32, _i32]
+    lib.or_merge_search.restype = None
+    lib.or_merge_search.argtypes = [c_i64, _i32, c_i64, ctypes.POINTER(c_i64),
+                                    ctypes.POINTER(c_i64)]
+    lib.or_offset_bits.restype = c_int
+    lib.or_offset_bits.argtypes = [c_int, c_int]
+    lib.or_plan.restype = c_int
+    lib.or_plan.argtypes = [c_i64, _i32, c_int, c_int, _i32, _u32, _u32]
+    lib.or_plan_replay.restype = c_int
+    lib.or_plan_replay.argtypes = [c_i64, c_i64, c_int, c_int, _i32, _u32, _u32, _i32, _f64,
+                                   _f64, _f64, ctypes.c_void_p]
+    lib.or_pagerank.restype = c_int
+    lib.or_pagerank.argtypes = [c_i64, _i32, _i32, _f64, c_dbl, c_int, _f64, _f64,
+                                ctypes.c_void_p, ctypes.c_void_p]
+    _lib = lib
+    return lib
+
+
+def _i32a(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _f64a(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ------------------------------------------------------------------ SpMV --
+
+def spmv(row_ptr, col, values, x) -> np.ndarray:
+    """Sec. 3.1: y = A x with y[r] = sum_k values[k] x[col[k]] (long double)."""
+    row_ptr = _i32a(row_ptr)
+    n = len(row_ptr) - 1
+    y = np.empty(max(n, 1), np.float64)
+    _load().or_spmv(n, row_ptr, _i32a(col), _f64a(values), _f64a(x) if len(x) else np.zeros(1),
+                    y)
+    return y[:n]
+
+
+def abs_spmv(row_ptr, col, values, x) -> np.ndarray:
+    """(|A| |x|)[r]: the per-row scale of the SpMV parity tolerance."""
+    row_ptr = _i32a(row_ptr)
+    n = len(row_ptr) - 1
+    y = np.empty(max(n, 1), np.float64)
+    _load().or_abs_spmv(n, row_ptr, _i32a(col), _f64a(values),
+                        _f64a(x) if len(x) else np.zeros(1), y)
+    return y[:n]
+
+
+# ------------------------------------------------------------ merge path --
+
+def path_coords(row_ptr):
+    """Sec. 3.3: coordinates (xs[d], ys[d]) after d steps, d = 0 .. m + n."""
+    row_ptr = _i32a(row_ptr)
+    n = len(row_ptr) - 1
+    L = int(row_ptr[-1]) + n
+    xs = np.empty(L + 1, np.int32)
+    ys = np.empty(L + 1, np.int32)
+    _load().or_path_coords(n, row_ptr, xs, ys)
+    return xs, ys
+
+
+def merge_search(row_ptr, diag: int):
+    """Algorithm 1 (merge_search): path coordinate on diagonal `diag`."""
+    row_ptr = _i32a(row_ptr)
+    xo, yo = ctypes.c_int64(), ctypes.c_int64()
+    _load().or_merge_search(len(row_ptr) - 1, row_ptr, int(diag), ctypes.byref(xo),
+                            ctypes.byref(yo))
+    return xo.value, yo.value
+
+
+def offset_bits(omega: int, sigma: int) -> int:
+    """Sec. 4.1.1: b = ceil(log2(omega sigma)) bits per offset field."""
+    return int(_load().or_offset_bits(omega, sigma))
+
+
+def plan_sizes(n_rows: int, nnz: int, omega: int, sigma: int):
+    """Sec. 4.1.1: (tile_num, lane_num) = (ceil((m+n)/(omega sigma)), ceil((m+n)/sigma))."""
+    L = nnz + n_rows
+    return -(-L // (omega * sigma)), -(-L // sigma)
+
+
+def plan(row_ptr, omega: int, sigma: int):
+    """Sec. 4.1: TILE = (tile_x int32[T+1], tile_y uint32[T+1], lane_desc uint32[lanes])."""
+    row_ptr = _i32a(row_ptr)
+    n = len(row_ptr) - 1
+    T, lanes = plan_sizes(n, int(row_ptr[-1]), omega, sigma)
+    tile_x = np.empty(T + 1, np.int32)
+    tile_y = np.empty(T + 1, np.uint32)
+    lane_desc = np.empty(max(lanes, 1), np.uint32)
+    rc = _load().or_plan(n, row_ptr, omega, sigma, tile_x, tile_y, lane_desc)
+    if rc != 0:
+        raise ValueError(f"descriptor does not fit: 2*{offset_bits(omega, sigma)}+{sigma} > 32")
+    return tile_x, tile_y, lane_desc[:lanes]
+
+
+def unpack_desc(lane_desc, omega: int, sigma: int):
+    """Sec. 4.1.1: split descriptors into (x_offset, y_offset, bit_flag)."""
+    b = offset_bits(omega, sigma)
+    d = np.asarray(lane_desc, np.uint64)
+    mask = (1 << b) - 1
+    return (d & mask).astype(np.int64), ((d >> b) & mask).astype(np.int64), (d >> (2 * b)).astype(
+        np.int64)
+
+
+def plan_replay(row_ptr, col, values, x, tile, omega: int, sigma: int):
+    """Sec. 4.1.1 decode + replay of every lane; returns (y, row of each nnz)."""
+    tile_x, tile_y, lane_desc = tile
+    row_ptr = _i32a(row_ptr)
+    n = len(row_ptr) - 1
+    m = int(row_ptr[-1])
+    y = np.empty(max(n, 1), np.float64)
+    nnz_row = np.full(max(m, 1), -1, np.int32)
+    rc = _load().or_plan_replay(n, m, omega, sigma, _i32a(tile_x),
+                                np.ascontiguousarray(tile_y, np.uint32),
+                                np.ascontiguousarray(lane_desc if len(lane_desc) else [0],
+                                                     np.uint32),
+                                _i32a(col) if m else np.zeros(1, np.int32),
+                                _f64a(values) if m else np.zeros(1),
+                                _f64a(x) if len(x) else np.zeros(1), y,
+                                nnz_row.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise ValueError(f"plan replay failed ({rc})")
+    return y[:n], nnz_row[:m]
+
+
+def tile_mem_bytes(n_rows: int, nnz: int, omega: int, sigma: int, r_f: float) -> float:
+    """Sec. 4.3: mem_sigma = 8 (ceil((m+n)/(omega sigma)) + 1) + 4 ceil((m+n)/sigma) (1 - r_f)."""
+    L = nnz + n_rows
+    return 8 * (math.ceil(L / (omega * sigma)) + 1) + 4 * math.ceil(L / sigma) * (1 - r_f)
+
+
+def smem_bytes(block_lanes: int, sigma: int, value_size: int) -> int:
+    """Sec. 4.3: smem_sigma = (b + 1) sigma sizeof(value) per block."""
+    return (block_lanes + 1) * sigma * value_size
+
+
+# -------------------------------------------------------------- PageRank --
+
+def pagerank(row_ptr, col, values, alpha: float, iters: int, x0, *, history: bool = False):
+    """Sec. 5.5.1: power method, damping alpha, dangling mass spread
+    uniformly.  Returns (x_iters, resid[iters], hist or None)."""
+    row_ptr = _i32a(row_ptr)
+    n = len(row_ptr) - 1
+    x_out = np.empty(max(n, 1), np.float64)
+    resid = np.empty(max(iters, 1), np.float64)
+    hist = np.empty((max(iters, 1), max(n, 1)), np.float64) if history else None
+    rc = _load().or_pagerank(n, row_ptr, _i32a(col) if len(col) else np.zeros(1, np.int32),
+                             _f64a(values) if len(values) else np.zeros(1), float(alpha),
+                             int(iters), _f64a(x0), x_out,
+                             hist.ctypes.data_as(ctypes.c_void_p) if history else None,
+                             resid.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise MemoryError("or_pagerank failed")
+    return x_out[:n], resid[:iters], (hist[:iters, :n] if history else None)

@@ -1,0 +1,249 @@
+/*
+ * CPU oracle for the MERBIT hot path.  TEST INFRASTRUCTURE ONLY: only the
+ * test-suite, the package smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  It shares no code with the HIP library.
+ *
+ * Plain, sequential and slow on purpose.  Every function names the part of
+ * the paper ("MERBIT: A GPU-Based SpMV Method for Iterative Workloads") it
+ * writes out.
+ *
+ *   or_spmv          y = A x, the definition of Sec. 3.1, summed in long double
+ *   or_abs_spmv      (|A| |x|)[r], the scale used by the parity tolerance
+ *   or_path_coords   the merge path of Sec. 3.3 walked step by step
+ *   or_merge_search  the diagonal binary search of Algorithm 1 (merge_search)
+ *   or_plan          the TILE arrays of Sec. 4.1.1 / 4.1.2 from one sequential walk
+ *   or_plan_replay   decode TILE (Sec. 4.1.1 coordinate formula) and redo y = A x
+ *   or_pagerank      power method of Sec. 5.5.1, damping alpha, dangling mass
+ *                    spread uniformly
+ *
+ * Conventions.  CSR: row_ptr has n_rows + 1 entries (Sec. 3.1 says "length n";
+ * the algorithms read offset[y + 1], so the array has n + 1 entries), col and
+ * values have m = row_ptr[n_rows] entries.  Merge-path coordinates are
+ * (x, y) = (nonzeros consumed, rows finished).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+/* ---------------------------------------------------------------- SpMV -- */
+
+/* Sec. 3.1: y[r] = sum over k in [row_ptr[r], row_ptr[r+1]) of
+ * values[k] * x[col[k]].  Products and sums in long double (64-bit
+ * significand); an empty row gives exactly 0. */
+void or_spmv(int64_t n_rows, const int32_t* row_ptr, const int32_t* col,
+             const double* values, const double* x, double* y) {
+    for (int64_t r = 0; r < n_rows; ++r) {
+        long double s = 0.0L;
+        for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k)
+            s += (long double)values[k] * (long double)x[col[k]];
+        y[r] = (double)s;
+    }
+}
+
+/* (|A| |x|)[r] = sum |values[k]| |x[col[k]]|, the per-row scale of the
+ * parity tolerance (a rounding-error bound for any summation order is a
+ * multiple of it). */
+void or_abs_spmv(int64_t n_rows, const int32_t* row_ptr, const int32_t* col,
+                 const double* values, const double* x, double* y) {
+    for (int64_t r = 0; r < n_rows; ++r) {
+        long double s = 0.0L;
+        for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k)
+            s += fabsl((long double)values[k]) * fabsl((long double)x[col[k]]);
+        y[r] = (double)s;
+    }
+}
+
+/* ----------------------------------------------------------- merge path -- */
+
+/* Sec. 3.3: the merge path runs from (0, 0) to (m, n).  From (x, y) it steps
+ * right (consume nonzero x of row y) while x < row_ptr[y + 1], otherwise down
+ * (row y is complete).  Writes the coordinate after each of the first d
+ * steps, d = 0 .. m + n, into xs[d], ys[d]. */
+void or_path_coords(int64_t n_rows, const int32_t* row_ptr, int32_t* xs, int32_t* ys) {
+    const int64_t m = row_ptr[n_rows];
+    const int64_t L = m + n_rows;
+    int64_t x = 0, y = 0;
+    xs[0] = 0;
+    ys[0] = 0;
+    for (int64_t d = 0; d < L; ++d) {
+        if (x < row_ptr[y + 1]) ++x; else ++y;
+        xs[d + 1] = (int32_t)x;
+        ys[d + 1] = (int32_t)y;
+    }
+}
+
+/* Algorithm 1 (merge_search): binary search along the diagonal x + y = diag
+ * for the point where it crosses the merge path.  y ends as the number of
+ * rows r whose end offset satisfies row_ptr[r + 1] <= diag - r - 1. */
+void or_merge_search(int64_t n_rows, const int32_t* row_ptr, int64_t diag,
+                     int64_t* x_out, int64_t* y_out) {
+    const int64_t m = row_ptr[n_rows];
+    int64_t lo = diag - m > 0 ? diag - m : 0;
+    int64_t hi = diag < n_rows ? diag : n_rows;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)row_ptr[mid + 1] <= diag - mid - 1) lo = mid + 1;
+        else hi = mid;
+    }
+    *x_out = diag - lo;
+    *y_out = lo < n_rows ? lo : n_rows;
+}
+
+/* b = ceil(log2(omega * sigma)): the width of each offset field (Sec. 4.1.1). */
+int or_offset_bits(int omega, int sigma) {
+    int64_t v = (int64_t)omega * sigma;
+    int b = 0;
+    while (((int64_t)1 << b) < v) ++b;
+    return b;
+}
+
+/* Sec. 4.1.1 / 4.1.2: the TILE format.
+ *   tile_num = ceil((m + n) / (omega sigma)), lane_num = ceil((m + n) / sigma)
+ *   tile_x, tile_y [tile_num + 1]: start of tile i = the path coordinate after
+ *       i * omega * sigma steps; last entry (m, n).  Bit 31 of tile_y[i] is set
+ *       when no step of tile i goes down (the whole tile lies in one row).
+ *   lane_desc [lane_num]: lane j covers steps [j sigma, min((j+1) sigma, m+n));
+ *       its start minus its tile's start gives (x_off, y_off); bit k of the
+ *       flag word is 1 when step k of the lane goes down.  Packed as
+ *       flags << 2b | y_off << b | x_off.
+ * Built here from a single sequential walk of the path (no search).
+ * Returns 0, or -1 when 2b + sigma > 32 (the descriptor does not fit). */
+int or_plan(int64_t n_rows, const int32_t* row_ptr, int omega, int sigma,
+            int32_t* tile_x, uint32_t* tile_y, uint32_t* lane_desc) {
+    const int64_t m = row_ptr[n_rows];
+    const int64_t L = m + n_rows;
+    const int64_t ws = (int64_t)omega * sigma;
+    const int64_t tile_num = (L + ws - 1) / ws;
+    const int64_t lane_num = (L + sigma - 1) / sigma;
+    const int b = or_offset_bits(omega, sigma);
+    if (2 * b + sigma > 32) return -1;
+
+    int64_t x = 0, y = 0;            /* current path coordinate */
+    int64_t tx = 0, ty = 0;          /* start of the current tile */
+    int tile_has_down = 0;
+    uint32_t flags = 0;
+    uint32_t lane_x_off = 0, lane_y_off = 0;
+    for (int64_t d = 0; d < L; ++d) {
+        if (d % ws == 0) {           /* a tile starts here */
+            tx = x;
+            ty = y;
+            tile_has_down = 0;
+        }
+        if (d % sigma == 0) {        /* a lane starts here */
+            lane_x_off = (uint32_t)(x - tx);
+            lane_y_off = (uint32_t)(y - ty);
+            flags = 0;
+        }
+        const int k = (int)(d % sigma);
+        if (x < row_ptr[y + 1]) {
+            ++x;
+        } else {
+            ++y;
+            flags |= 1u << k;
+            tile_has_down = 1;
+        }
+        if (k == sigma - 1 || d == L - 1) {   /* lane ends after this step */
+            const int64_t j = d / sigma;
+            lane_desc[j] = (flags << (2 * b)) | (lane_y_off << b) | lane_x_off;
+        }
+        if ((d + 1) % ws == 0 || d == L - 1) { /* tile ends after this step */
+            const int64_t i = d / ws;
+            tile_x[i] = (int32_t)tx;
+            tile_y[i] = (uint32_t)ty | (tile_has_down ? 0u : 0x80000000u);
+        }
+    }
+    (void)lane_num;
+    tile_x[tile_num] = (int32_t)m;
+    tile_y[tile_num] = (uint32_t)n_rows;
+    return 0;
+}
+
+/* Sec. 4.1.1: the coordinate of step k of lane j in tile i is
+ *   (tile_x[i] + x_off + k_x, ROW(tile_y[i]) + y_off + k_y)
+ * with k_x, k_y the right and down steps among the first k flag bits.
+ * Decodes every lane and replays it: a right step adds values[x] * x[col[x]]
+ * to the running sum of the current row, a down step stores it.  Sums are kept
+ * per row in path order, so for a correct TILE the result equals or_spmv bit
+ * for bit.  nnz_row (optional) receives the row of every nonzero.
+ * Returns 0, or a negative code when the descriptors are inconsistent
+ * (a step leaves the matrix). */
+int or_plan_replay(int64_t n_rows, int64_t m, int omega, int sigma,
+                   const int32_t* tile_x, const uint32_t* tile_y, const uint32_t* lane_desc,
+                   const int32_t* col, const double* values, const double* xv,
+                   double* y, int32_t* nnz_row) {
+    const int64_t L = m + n_rows;
+    const int64_t lane_num = (L + sigma - 1) / sigma;
+    const int b = or_offset_bits(omega, sigma);
+    const uint32_t fmask = (b > 0) ? ((1u << b) - 1u) : 0u;
+    long double* acc = (long double*)calloc((size_t)(n_rows > 0 ? n_rows : 1), sizeof(long double));
+    if (!acc) return -2;
+    for (int64_t j = 0; j < lane_num; ++j) {
+        const int64_t i = j / omega;
+        const uint32_t desc = lane_desc[j];
+        int64_t x = (int64_t)tile_x[i] + (desc & fmask);
+        int64_t yy = (int64_t)(tile_y[i] & 0x7FFFFFFFu) + ((desc >> b) & fmask);
+        const uint32_t flags = desc >> (2 * b);
+        const int64_t steps = (L - j * sigma) < sigma ? (L - j * sigma) : sigma;
+        for (int64_t k = 0; k < steps; ++k) {
+            if ((flags >> k) & 1u) {
+                if (yy >= n_rows) { free(acc); return -3; }
+                ++yy;                      /* row yy is complete */
+            } else {
+                if (x >= m || yy >= n_rows) { free(acc); return -4; }
+                acc[yy] += (long double)values[x] * (long double)xv[col[x]];
+                if (nnz_row) nnz_row[x] = (int32_t)yy;
+                ++x;
+            }
+        }
+    }
+    for (int64_t r = 0; r < n_rows; ++r) y[r] = (double)acc[r];
+    free(acc);
+    return 0;
+}
+
+/* ------------------------------------------------------------ PageRank -- */
+
+/* Sec. 5.5.1: PageRank by the power method with damping alpha.  The matrix is
+ * the column-stochastic transition matrix P stored with rows = destinations
+ * (P[v][u] = 1 / outdeg(u) for an edge u -> v).  A column without nonzeros is
+ * a dangling vertex; its mass is spread uniformly:
+ *     x_{t+1} = alpha P x_t + (alpha * sum_{u dangling} x_t[u] + 1 - alpha) / n.
+ * Iterates are kept in long double; x_out gets the last one.  hist (optional,
+ * iters * n) receives every iterate, resid (optional, iters) the l1 change
+ * ||x_{t+1} - x_t||_1 of every step. */
+int or_pagerank(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* values,
+                double alpha, int iters, const double* x0, double* x_out,
+                double* hist, double* resid) {
+    const int64_t m = row_ptr[n];
+    unsigned char* has_out = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    long double* x = (long double*)malloc(sizeof(long double) * (size_t)(n > 0 ? n : 1));
+    long double* xn = (long double*)malloc(sizeof(long double) * (size_t)(n > 0 ? n : 1));
+    if (!has_out || !x || !xn) { free(has_out); free(x); free(xn); return -2; }
+    for (int64_t k = 0; k < m; ++k) has_out[col[k]] = 1;
+    for (int64_t i = 0; i < n; ++i) x[i] = x0[i];
+    const long double a = alpha;
+    for (int t = 0; t < iters; ++t) {
+        long double dangling = 0.0L;
+        for (int64_t u = 0; u < n; ++u)
+            if (!has_out[u]) dangling += x[u];
+        const long double teleport = (a * dangling + 1.0L - a) / (long double)n;
+        long double change = 0.0L;
+        for (int64_t r = 0; r < n; ++r) {
+            long double s = 0.0L;
+            for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k)
+                s += (long double)values[k] * x[col[k]];
+            xn[r] = a * s + teleport;
+            change += fabsl(xn[r] - x[r]);
+        }
+        long double* tmp = x; x = xn; xn = tmp;
+        if (resid) resid[t] = (double)change;
+        if (hist)
+            for (int64_t r = 0; r < n; ++r) hist[(int64_t)t * n + r] = (double)x[r];
+    }
+    for (int64_t r = 0; r < n; ++r) x_out[r] = (double)x[r];
+    free(has_out);
+    free(x);
+    free(xn);
+    return 0;
+}
