@@ -1,0 +1,217 @@
+"""Benchmark: repeated merge-path SpMV inside PageRank power iterations on one
+MI355X, R-MAT scale 22 (4,194,304 rows, ~65.2M nonzeros after merging).
+
+A step is one PageRank iteration: the fused SpMV kernel (y = P x) plus the
+update kernel (x' = alpha y + teleport, dangling mass and l1 change).  The
+plan is built once and timed separately.  `value` is nonzeros processed per
+second over the timed steps (GNZ/s).  The roofline block reports the fused
+SpMV kernel: algorithmic bytes per launch / mean launch time from HIP events,
+against the MI355X HBM peak.  The CPU baseline is the oracle (single thread)
+timed on a bounded number of iterations of the same workload.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "SpMV GNZ/s and % of HBM peak (FP32/FP64); batched + adjoint vs plain"
+SPMV_SRC = os.path.join(ROOT, "paper_2605_07391_amd", "csrc", "merbit_spmv.hip")
+
+
+def spmv_source_hash() -> str:
+    with open(SPMV_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(info: dict, value_size: int) -> float:
+    """Bytes one SpMV must move: values + col_ind once, x once, y once, the
+    tile starts and the descriptors of the non-fast tiles (paper Sec. 4.3's
+    TILE footprint)."""
+    m, n_rows, n_cols = info["nnz"], info["n_rows"], info["n_cols"]
+    T, lanes = info["tile_num"], info["lane_num"]
+    r_f = info["fast_tiles"] / T if T else 0.0
+    return (m * (value_size + 4) + n_cols * value_size + n_rows * value_size + 8 * (T + 1)
+            + 4 * lanes * (1.0 - r_f))
+
+
+def load_traffic(workload: str, dtype: str):
+    """Measured HBM bytes per launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"spmv_traffic_{workload}_{dtype}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("spmv_source_sha256_16") != spmv_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes: int,
+            alpha: float):
+    import numpy as np
+    import torch
+
+    import paper_2605_07391_amd as pkg
+
+    dev = torch.device("cuda:0")
+    dtype = torch.float32 if dtype_name == "f32" else torch.float64
+    vsize = 4 if dtype == torch.float32 else 8
+    n = w["n_rows"]
+    r = torch.from_numpy(w["row_ptr"]).to(dev)
+    c = torch.from_numpy(w["col"]).to(dev)
+    v = torch.from_numpy(w["values"]).to(dtype).to(dev)
+    torch.cuda.synchronize()
+    # plan build, timed on its own (kernel + allocation of TILE)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan = pkg.Plan(r, c, v, n, sigma=sigma, block_lanes=block_lanes, validate=False)
+    e1.record()
+    torch.cuda.synchronize()
+    plan_ms = e0.elapsed_time(e1)
+    info = plan.info()
+    x = torch.full((n,), 1.0 / n, dtype=dtype, device=dev)
+    if warmup > 0:
+        plan.pagerank(x, alpha, tol=0.0, max_iter=warmup)
+    x.fill_(1.0 / n)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record()
+    iters, resid, _ = plan.pagerank(x, alpha, tol=0.0, max_iter=steps)
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    step_ms = t0.elapsed_time(t1) / steps
+    mass = float(x.double().sum().item())
+    # roofline pass: same steps, fused SpMV launches bracketed by HIP events
+    x.fill_(1.0 / n)
+    plan.profile_enable(True)
+    plan.pagerank(x, alpha, tol=0.0, max_iter=steps)
+    launches, kernel_ms = plan.profile_read()
+    plan.profile_enable(False)
+    spmv_ms = kernel_ms / max(launches, 1)
+    abytes = algorithmic_bytes(info, vsize)
+    achieved = abytes / (spmv_ms * 1e-3) / 1e9
+    plan.close()
+    nnz = info["nnz"]
+    return {
+        "iters": iters, "resid": resid, "mass": mass, "step_ms": step_ms, "wall_s": wall,
+        "plan_ms": plan_ms, "spmv_ms": spmv_ms, "launches": launches, "info": info,
+        "alg_bytes": abytes, "achieved_gbs": achieved,
+        "value_gnzs": nnz * steps / (step_ms * steps * 1e-3) / 1e9,
+        "spmv_gnzs": nnz / (spmv_ms * 1e-3) / 1e9,
+    }
+
+
+def cpu_baseline(w, iters: int, alpha: float):
+    import numpy as np
+
+    import oracle
+    n = w["n_rows"]
+    vals = w["values"].astype(np.float32).astype(np.float64)
+    x0 = np.full(n, np.float32(1.0 / n), np.float64)
+    t = time.perf_counter()
+    oracle.pagerank(w["row_ptr"], w["col"], vals, alpha, iters, x0)
+    dt = time.perf_counter() - t
+    return {"value": round(w["nnz"] * iters / dt / 1e9, 5), "unit": "GNZ/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{iters} PageRank iterations of the full workload matrix "
+                      f"(single-threaded C, long-double sums), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="rmat22")
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--sigma", type=int, default=0)
+    ap.add_argument("--block-lanes", type=int, default=0)
+    ap.add_argument("--alpha", type=float, default=0.85)
+    ap.add_argument("--cpu-iters", type=int, default=15)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-f64", action="store_true", help="skip the FP64 companion run")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import graphgen
+    t = time.perf_counter()
+    w = graphgen.workload(args.workload)
+    gen_s = time.perf_counter() - t
+    print(f"[bench] workload {args.workload}: n={w['n_rows']} nnz={w['nnz']} "
+          f"generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
+
+    main_run = run_gpu(w, args.dtype, args.steps, args.warmup, args.sigma, args.block_lanes,
+                       args.alpha)
+    info = main_run["info"]
+    print(f"[bench] {args.dtype}: step {main_run['step_ms'] * 1e3:.1f} us, spmv "
+          f"{main_run['spmv_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
+    extra = None
+    if not args.no_f64 and args.dtype == "f32":
+        r64 = run_gpu(w, "f64", args.steps, args.warmup, 0, args.block_lanes, args.alpha)
+        extra = {
+            "value": round(r64["value_gnzs"], 3), "ms_per_step": round(r64["step_ms"], 5),
+            "spmv_us": round(r64["spmv_ms"] * 1e3, 2), "spmv_gnzs": round(r64["spmv_gnzs"], 3),
+            "achieved_gbs": round(r64["achieved_gbs"], 1),
+            "pct_hbm_peak": round(100 * r64["achieved_gbs"] / HBM_PEAK_GBS, 2),
+            "plan_ms": round(r64["plan_ms"], 3), "sigma": r64["info"]["sigma"],
+            "traffic": load_traffic(args.workload, "f64"),
+        }
+        print(f"[bench] f64: step {r64['step_ms'] * 1e3:.1f} us, spmv "
+              f"{r64['spmv_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, args.cpu_iters, args.alpha)
+    ach = main_run["achieved_gbs"]
+    out = {
+        "metric": METRIC,
+        "value": round(main_run["value_gnzs"], 3),
+        "unit": "GNZ/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_run["step_ms"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic (seeded R-MAT, values 1/outdeg)",
+        "config": {"workload": f"{args.workload}_pagerank", "n": info["n_rows"],
+                   "nnz": info["nnz"], "sigma": info["sigma"],
+                   "block_lanes": info["block_lanes"], "alpha": args.alpha,
+                   "seed": w["meta"].get("seed"), "x0": "1/n"},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic(args.workload, args.dtype),
+                     "kernel": "merbit::spmv_kernel",
+                     "alg_bytes_per_launch": int(main_run["alg_bytes"]),
+                     "mean_launch_us": round(main_run["spmv_ms"] * 1e3, 2),
+                     "launches_timed": main_run["launches"]},
+        "cpu_baseline": cpu,
+        "spmv_gnzs": round(main_run["spmv_gnzs"], 3),
+        "plan_ms": round(main_run["plan_ms"], 3),
+        "fast_tile_fraction": round(info["fast_tiles"] / max(info["tile_num"], 1), 4),
+        "rank_mass": round(main_run["mass"], 7),
+        "f64": extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

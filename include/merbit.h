@@ -1,0 +1,159 @@
+/*
+ * merbit.h -- C ABI of libmerbit.so: merge-path SpMV with bit-field lane
+ * descriptors (MERBIT) for AMD Instinct MI355X (gfx950, 64-lane wavefronts).
+ *
+ * Method: "MERBIT: A GPU-Based SpMV Method for Iterative Workloads".
+ *   - Sec. 3.3 / Algorithm 1   merge path over row ends and nonzeros, diagonal search
+ *   - Sec. 4.1                 TILE storage format and its one-time generation
+ *   - Sec. 4.2                 fused SpMV kernel (staged products, descriptor scan,
+ *                              wavefront segmented sum, long-row fast tiles,
+ *                              block-buffered commit, dual output buffers)
+ *   - Sec. 4.3                 the segment length sigma
+ *   - Sec. 5.5.1               PageRank by the power method
+ *
+ * Conventions shared by every entry point
+ *   - Matrix A is n_rows x n_cols in CSR: row_ptr int32[n_rows + 1] (row_ptr[0] = 0,
+ *     non-decreasing, row_ptr[n_rows] = nnz), col_ind int32[nnz] in [0, n_cols),
+ *     values float or double [nnz].  Column order inside a row is free.
+ *   - All array pointers are DEVICE pointers (hipMalloc or equivalent) unless
+ *     the comment says "host".  The caller owns them and keeps them alive.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls are asynchronous on that stream unless the comment says otherwise.
+ *   - Every call returns a merbit_status; nothing aborts or throws across the
+ *     ABI.  On failure merbit_last_error() returns a message (thread local).
+ *   - Limits: n_rows + nnz < 2^31 (32-bit coordinates and the tile_y mark bit).
+ *   - A plan is not safe for concurrent use from two streams or threads.
+ */
+#ifndef MERBIT_H
+#define MERBIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MERBIT_OK = 0,
+    MERBIT_EINVAL = -1,       /* bad argument or failed CSR validation        */
+    MERBIT_ENOMEM = -2,       /* device allocation failed                      */
+    MERBIT_EHIP = -3,         /* a HIP runtime call failed (message has it)    */
+    MERBIT_EUNSUPPORTED = -4, /* dtype / sigma / block size not built          */
+    MERBIT_NOT_CONVERGED = 1  /* merbit_pagerank reached max_iter above tol    */
+} merbit_status;
+
+typedef enum { MERBIT_F32 = 0, MERBIT_F64 = 1 } merbit_dtype;
+
+typedef struct merbit_plan merbit_plan;
+
+/* Read-only description of a plan (merbit_plan_info). */
+typedef struct {
+    int64_t n_rows, n_cols, nnz;
+    int64_t tile_num;      /* ceil((nnz + n_rows) / (omega sigma))          Sec. 4.1.1 */
+    int64_t lane_num;      /* ceil((nnz + n_rows) / sigma)                  Sec. 4.1.1 */
+    int64_t fast_tiles;    /* tiles with the long-row mark (MSB of tile_y)  Sec. 4.2 (1) */
+    int64_t block_num;     /* thread blocks of one SpMV launch                          */
+    int32_t omega;         /* lanes per tile = wavefront size = 64                      */
+    int32_t sigma;         /* merge-path steps per lane                     Sec. 4.3    */
+    int32_t block_lanes;   /* lanes (threads) per block, b of Sec. 4.3                  */
+    int32_t offset_bits;   /* ceil(log2(omega sigma)), width of x_offset / y_offset     */
+    int32_t dtype;         /* merbit_dtype                                              */
+    int32_t lds_bytes;     /* (b sigma + 1) sizeof(value): products + partial sums      */
+} merbit_plan_info_t;
+
+/* Build a reusable plan (Sec. 4.1.2, Algorithm generate_tile: merge search
+ * per lane, sigma-step walk, descriptor packing, long-row tile mark).
+ *   n_rows, n_cols, nnz  matrix shape; n_rows + nnz < 2^31
+ *   row_ptr, col_ind     device CSR arrays.  row_ptr is read only during this
+ *                        call's work on `stream`; col_ind and values are
+ *                        borrowed and must stay valid for the plan's life.
+ *   values               device float[nnz] or double[nnz] per dtype (may be
+ *                        replaced later with merbit_plan_set_values)
+ *   dtype                MERBIT_F32 or MERBIT_F64
+ *   sigma                steps per lane; 0 = default (12 for F32, 7 for F64).
+ *                        Must satisfy 2 ceil(log2(64 sigma)) + sigma <= 32 and be
+ *                        one of the built values 1..12.
+ *   block_lanes          lanes per thread block; 0 = default 256.  Built: 128,
+ *                        256, 512.
+ *   validate             nonzero: check the CSR on the device first (one host
+ *                        synchronisation); MERBIT_EINVAL if it is malformed.
+ *   out                  host pointer; receives the plan.  Free with
+ *                        merbit_plan_destroy.
+ * The plan owns TILE = {tile_x int32[T+1], tile_y uint32[T+1],
+ * lane_desc uint32[lane_num]} and its work buffers. */
+int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                       const int32_t* row_ptr, const int32_t* col_ind, const void* values,
+                       int dtype, int sigma, int block_lanes, int validate,
+                       void* stream, merbit_plan** out);
+
+/* Replace the borrowed values pointer (same sparsity pattern, same dtype).
+ * The TILE arrays depend only on row_ptr, so nothing is rebuilt. */
+int merbit_plan_set_values(merbit_plan* plan, const void* values);
+
+/* Fill *info (host pointer).  Counts the long-row tiles on the device and
+ * synchronises the plan's last stream. */
+int merbit_plan_info(merbit_plan* plan, merbit_plan_info_t* info);
+
+/* Copy TILE to host buffers (Sec. 4.1.1 layout).  Any output pointer may be
+ * NULL; tile_x / tile_y need tile_num + 1 entries, lane_desc lane_num entries.
+ * tile_num / lane_num (host, optional) receive the sizes.  Synchronous. */
+int merbit_plan_export(merbit_plan* plan, int32_t* tile_x, uint32_t* tile_y,
+                       uint32_t* lane_desc, int64_t* tile_num, int64_t* lane_num);
+
+/* y <- A x (Sec. 4.2, Algorithm "MERBIT SpMV"), overwriting y whatever it
+ * held.  x: device [n_cols], y: device [n_rows], both of the plan's dtype, not
+ * aliased.  Two launches: a scatter that zeroes y at the block-boundary rows,
+ * then the fused kernel. */
+int merbit_spmv(merbit_plan* plan, const void* x, void* y, void* stream);
+
+/* Dual-buffer form (Sec. 4.2, optimisation (3)): one launch.
+ * Requires y to be zero at the plan's block-boundary rows on entry (true for a
+ * buffer last used as `z` here, or after merbit_zero_boundary); computes
+ * y <- A x and zeroes z at the same rows, so z can be the next call's y.
+ * y and z: device [n_rows], distinct, not aliased with x. */
+int merbit_spmv_dual(merbit_plan* plan, const void* x, void* y, void* z, void* stream);
+
+/* Zero v (device [n_rows]) at the plan's block-boundary rows. */
+int merbit_zero_boundary(merbit_plan* plan, void* v, void* stream);
+
+/* PageRank by the power method (Sec. 5.5.1) on the plan's matrix, which must
+ * be square and column stochastic with rows = destinations (P[v][u] =
+ * 1/outdeg(u) for an edge u -> v).  Columns without nonzeros are dangling; their
+ * mass is spread uniformly:
+ *     x_{t+1} = alpha P x_t + (alpha sum_{u dangling} x_t[u] + 1 - alpha) / n.
+ *   alpha      damping in [0, 1]
+ *   tol        stop when ||x_{t+1} - x_t||_1 < tol; tested every check_every
+ *              iterations (one host synchronisation each); tol <= 0 runs exactly
+ *              max_iter iterations with a single synchronisation at the end
+ *   max_iter   iteration cap (>= 0)
+ *   x_inout    device [n] of the plan's dtype: x_0 on entry, the ranks on exit
+ *   iters_out  host, optional: iterations performed
+ *   resid_out  host, optional: ||x_iters - x_{iters-1}||_1 of the last iteration
+ * Returns MERBIT_OK, or MERBIT_NOT_CONVERGED when tol > 0 was not reached.
+ * Synchronises `stream` before returning. */
+int merbit_pagerank(merbit_plan* plan, double alpha, double tol, int max_iter,
+                    int check_every, void* x_inout, int* iters_out, double* resid_out,
+                    void* stream);
+
+/* Kernel timing for the SpMV launches of this plan.  While enabled, every
+ * fused SpMV launch (from merbit_spmv, merbit_spmv_dual and merbit_pagerank)
+ * is bracketed by HIP events on its stream.  merbit_profile_read (synchronous)
+ * returns the number of timed launches and their summed duration in ms, then
+ * clears the record.  Host pointers. */
+int merbit_profile_enable(merbit_plan* plan, int enable);
+int merbit_profile_read(merbit_plan* plan, int64_t* launches, double* total_ms);
+
+/* Release the plan and everything it owns (waits for its pending work). */
+void merbit_plan_destroy(merbit_plan* plan);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* merbit_last_error(void);
+
+/* Library version string. */
+const char* merbit_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MERBIT_H */

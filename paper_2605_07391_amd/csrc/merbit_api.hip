@@ -1,0 +1,418 @@
+// C ABI of libmerbit (declared in include/merbit.h): plan object, argument
+// checks, dispatch to the kernels, PageRank driver loop, error reporting.
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/merbit.h"
+#include "merbit_internal.hpp"
+
+using namespace merbit;
+
+struct merbit_plan {
+  int64_t n_rows = 0, n_cols = 0, nnz = 0;
+  int dtype = 0, sigma = 0, block_lanes = 0, waves = 0, bits = 0;
+  int device = 0;
+  int64_t tile_num = 0, lane_num = 0, block_num = 0;
+  int32_t* tile_x = nullptr;
+  uint32_t* tile_y = nullptr;
+  uint32_t* lane_desc = nullptr;
+  const int32_t* col = nullptr;
+  const void* values = nullptr;
+  hipStream_t last_stream = nullptr;
+  // small device scratch: [0] validation flags / fast-tile count
+  unsigned long long* scratch = nullptr;
+  // PageRank state
+  uint32_t* dmask = nullptr;
+  void* ybuf[2] = {nullptr, nullptr};
+  void* xwork = nullptr;
+  double* acc = nullptr;       // 2 slots x (dangling mass, l1 change)
+  double* partials = nullptr;  // 2 per reduction block
+  unsigned* counter = nullptr;
+  int reduce_grid = 0;
+  int zeroed_buf = -1;  // which ybuf is zero at the boundary rows, -1 if none
+  // kernel timing
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used = 0;
+};
+
+static thread_local std::string g_last_error;
+
+static int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+static int fail_hip(const char* what, hipError_t e) {
+  return fail(e == hipErrorOutOfMemory ? MERBIT_ENOMEM : MERBIT_EHIP,
+              std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) return fail_hip(#expr, _e);  \
+  } while (0)
+
+static size_t vsize(int dtype) { return dtype == MERBIT_F64 ? sizeof(double) : sizeof(float); }
+
+static void plan_free_all(merbit_plan* p) {
+  if (!p) return;
+  (void)hipDeviceSynchronize();
+  void* bufs[] = {p->tile_x, p->tile_y, p->lane_desc, p->scratch, p->dmask, p->ybuf[0],
+                  p->ybuf[1], p->xwork, p->acc, p->partials, p->counter};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  for (auto& ev : p->events) {
+    (void)hipEventDestroy(ev.first);
+    (void)hipEventDestroy(ev.second);
+  }
+  delete p;
+}
+
+static SpmvArgs spmv_args(const merbit_plan* p, const void* x, void* y, void* z) {
+  SpmvArgs a;
+  a.tile_x = p->tile_x;
+  a.tile_y = p->tile_y;
+  a.lane_desc = p->lane_desc;
+  a.col = p->col;
+  a.val = p->values;
+  a.x = x;
+  a.y = y;
+  a.z = z;
+  a.tile_num = (int32_t)p->tile_num;
+  a.lane_num = (int32_t)p->lane_num;
+  a.path_len = (int32_t)(p->nnz + p->n_rows);
+  a.n_rows = (int32_t)p->n_rows;
+  a.block_num = (int32_t)p->block_num;
+  return a;
+}
+
+// Launch the fused kernel, bracketed by events when profiling is on.
+static int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st) {
+  if (p->block_num == 0) return MERBIT_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (p->profiling) {
+    if (p->events_used == p->events.size()) {
+      hipEvent_t a, b;
+      HIP_TRY(hipEventCreate(&a));
+      HIP_TRY(hipEventCreate(&b));
+      p->events.emplace_back(a, b);
+    }
+    e0 = p->events[p->events_used].first;
+    e1 = p->events[p->events_used].second;
+    ++p->events_used;
+    HIP_TRY(hipEventRecord(e0, st));
+  }
+  HIP_TRY(launch_spmv(p->dtype, p->sigma, p->waves, spmv_args(p, x, y, z), st));
+  if (p->profiling) HIP_TRY(hipEventRecord(e1, st));
+  p->last_stream = st;
+  return MERBIT_OK;
+}
+
+extern "C" {
+
+const char* merbit_last_error(void) { return g_last_error.c_str(); }
+
+const char* merbit_version(void) { return "merbit-mi355x 0.1 (gfx950, wave64)"; }
+
+int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* row_ptr,
+                       const int32_t* col_ind, const void* values, int dtype, int sigma,
+                       int block_lanes, int validate, void* stream, merbit_plan** out) {
+  g_last_error.clear();
+  if (!out) return fail(MERBIT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (dtype != MERBIT_F32 && dtype != MERBIT_F64) return fail(MERBIT_EUNSUPPORTED, "dtype");
+  if (n_rows < 0 || n_cols < 0 || nnz < 0) return fail(MERBIT_EINVAL, "negative size");
+  if (n_rows + nnz >= ((int64_t)1 << 31))
+    return fail(MERBIT_EINVAL, "n_rows + nnz must be < 2^31");
+  if (n_cols >= ((int64_t)1 << 31)) return fail(MERBIT_EINVAL, "n_cols must be < 2^31");
+  if (n_rows > 0 && !row_ptr) return fail(MERBIT_EINVAL, "row_ptr is NULL");
+  if (nnz > 0 && (!col_ind || !values)) return fail(MERBIT_EINVAL, "col_ind/values NULL");
+  if (nnz > 0 && n_rows == 0) return fail(MERBIT_EINVAL, "nonzeros without rows");
+  if (sigma == 0) sigma = dtype == MERBIT_F32 ? 12 : 7;
+  if (block_lanes == 0) block_lanes = 256;
+  if (sigma < 1 || sigma > kMaxSigma)
+    return fail(MERBIT_EUNSUPPORTED, "sigma must be in 1..12");
+  const int bits = ceil_log2(kOmega * sigma);
+  if (2 * bits + sigma > 32) return fail(MERBIT_EUNSUPPORTED, "descriptor exceeds 32 bits");
+  if (block_lanes % kOmega != 0) return fail(MERBIT_EINVAL, "block_lanes % 64 != 0");
+  const int waves = block_lanes / kOmega;
+  if (!spmv_supported(dtype, sigma, waves))
+    return fail(MERBIT_EUNSUPPORTED, "block_lanes must be 128, 256 or 512");
+
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  merbit_plan* p = new merbit_plan();
+  p->n_rows = n_rows;
+  p->n_cols = n_cols;
+  p->nnz = nnz;
+  p->dtype = dtype;
+  p->sigma = sigma;
+  p->block_lanes = block_lanes;
+  p->waves = waves;
+  p->bits = bits;
+  p->col = col_ind;
+  p->values = values;
+  p->last_stream = st;
+  (void)hipGetDevice(&p->device);
+  const int64_t L = nnz + n_rows;
+  p->tile_num = (L + (int64_t)kOmega * sigma - 1) / ((int64_t)kOmega * sigma);
+  p->lane_num = (L + sigma - 1) / sigma;
+  p->block_num = (p->tile_num + waves - 1) / waves;
+
+  hipError_t e;
+#define CREATE_TRY(expr)                       \
+  do {                                         \
+    e = (expr);                                \
+    if (e != hipSuccess) {                     \
+      int rc = fail_hip(#expr, e);             \
+      plan_free_all(p);                        \
+      return rc;                               \
+    }                                          \
+  } while (0)
+
+  CREATE_TRY(hipMalloc(&p->scratch, 64));
+  CREATE_TRY(hipMalloc(&p->tile_x, sizeof(int32_t) * (size_t)(p->tile_num + 1)));
+  CREATE_TRY(hipMalloc(&p->tile_y, sizeof(uint32_t) * (size_t)(p->tile_num + 1)));
+  CREATE_TRY(hipMalloc(&p->lane_desc, sizeof(uint32_t) * (size_t)(p->lane_num > 0 ? p->lane_num : 1)));
+
+  if (validate && (n_rows > 0 || nnz > 0)) {
+    CREATE_TRY(hipMemsetAsync(p->scratch, 0, 64, st));
+    CREATE_TRY(launch_validate(row_ptr, col_ind, n_rows, n_cols, nnz,
+                               reinterpret_cast<unsigned*>(p->scratch), st));
+    unsigned flags = 0;
+    CREATE_TRY(hipMemcpyAsync(&flags, p->scratch, sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    CREATE_TRY(hipStreamSynchronize(st));
+    if (flags) {
+      char buf[160];
+      snprintf(buf, sizeof buf, "CSR validation failed:%s%s%s%s",
+               (flags & 1) ? " row_ptr[0]!=0" : "", (flags & 2) ? " row_ptr[n]!=nnz" : "",
+               (flags & 4) ? " row_ptr decreasing" : "", (flags & 8) ? " column out of range" : "");
+      plan_free_all(p);
+      return fail(MERBIT_EINVAL, buf);
+    }
+  }
+  if (n_rows == 0) {
+    // empty path: TILE = {[0], [0]}
+    CREATE_TRY(hipMemsetAsync(p->tile_x, 0, sizeof(int32_t), st));
+    CREATE_TRY(hipMemsetAsync(p->tile_y, 0, sizeof(uint32_t), st));
+  } else {
+    PlanArgs pa;
+    pa.row_ptr = row_ptr;
+    pa.n_rows = (int32_t)n_rows;
+    pa.nnz = (int32_t)nnz;
+    pa.sigma = sigma;
+    pa.bits = bits;
+    pa.lane_num = p->lane_num;
+    pa.tile_num = p->tile_num;
+    pa.tile_x = p->tile_x;
+    pa.tile_y = p->tile_y;
+    pa.lane_desc = p->lane_desc;
+    CREATE_TRY(launch_plan(pa, st));
+  }
+#undef CREATE_TRY
+  *out = p;
+  return MERBIT_OK;
+}
+
+int merbit_plan_set_values(merbit_plan* p, const void* values) {
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->nnz > 0 && !values) return fail(MERBIT_EINVAL, "values is NULL");
+  p->values = values;
+  return MERBIT_OK;
+}
+
+int merbit_plan_info(merbit_plan* p, merbit_plan_info_t* info) {
+  if (!p || !info) return fail(MERBIT_EINVAL, "NULL argument");
+  memset(info, 0, sizeof *info);
+  info->n_rows = p->n_rows;
+  info->n_cols = p->n_cols;
+  info->nnz = p->nnz;
+  info->tile_num = p->tile_num;
+  info->lane_num = p->lane_num;
+  info->block_num = p->block_num;
+  info->omega = kOmega;
+  info->sigma = p->sigma;
+  info->block_lanes = p->block_lanes;
+  info->offset_bits = p->bits;
+  info->dtype = p->dtype;
+  info->lds_bytes = (int32_t)(((int64_t)p->block_lanes * p->sigma + 1) * (int64_t)vsize(p->dtype));
+  if (p->tile_num > 0) {
+    hipStream_t st = p->last_stream;
+    unsigned long long cnt = 0;
+    HIP_TRY(hipMemsetAsync(p->scratch, 0, sizeof(unsigned long long), st));
+    HIP_TRY(launch_count_fast(p->tile_y, p->tile_num, p->scratch, st));
+    HIP_TRY(hipMemcpyAsync(&cnt, p->scratch, sizeof cnt, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    info->fast_tiles = (int64_t)cnt;
+  }
+  return MERBIT_OK;
+}
+
+int merbit_plan_export(merbit_plan* p, int32_t* tile_x, uint32_t* tile_y, uint32_t* lane_desc,
+                       int64_t* tile_num, int64_t* lane_num) {
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (tile_num) *tile_num = p->tile_num;
+  if (lane_num) *lane_num = p->lane_num;
+  hipStream_t st = p->last_stream;
+  HIP_TRY(hipStreamSynchronize(st));
+  if (tile_x)
+    HIP_TRY(hipMemcpy(tile_x, p->tile_x, sizeof(int32_t) * (size_t)(p->tile_num + 1),
+                      hipMemcpyDeviceToHost));
+  if (tile_y)
+    HIP_TRY(hipMemcpy(tile_y, p->tile_y, sizeof(uint32_t) * (size_t)(p->tile_num + 1),
+                      hipMemcpyDeviceToHost));
+  if (lane_desc && p->lane_num > 0)
+    HIP_TRY(hipMemcpy(lane_desc, p->lane_desc, sizeof(uint32_t) * (size_t)p->lane_num,
+                      hipMemcpyDeviceToHost));
+  return MERBIT_OK;
+}
+
+int merbit_zero_boundary(merbit_plan* p, void* v, void* stream) {
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->block_num == 0) return MERBIT_OK;
+  if (!v) return fail(MERBIT_EINVAL, "vector is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->block_num, p->waves, v, st));
+  p->last_stream = st;
+  return MERBIT_OK;
+}
+
+int merbit_spmv(merbit_plan* p, const void* x, void* y, void* stream) {
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->n_rows == 0) return MERBIT_OK;
+  if (!y || (p->nnz > 0 && !x)) return fail(MERBIT_EINVAL, "x or y is NULL");
+  if (x == y) return fail(MERBIT_EINVAL, "x and y alias");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->block_num, p->waves, y, st));
+  return run_fused(p, x, y, nullptr, st);
+}
+
+int merbit_spmv_dual(merbit_plan* p, const void* x, void* y, void* z, void* stream) {
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->n_rows == 0) return MERBIT_OK;
+  if (!y || !z || (p->nnz > 0 && !x)) return fail(MERBIT_EINVAL, "x, y or z is NULL");
+  if (x == y || y == z || x == z) return fail(MERBIT_EINVAL, "x, y, z must be distinct");
+  return run_fused(p, x, y, z, static_cast<hipStream_t>(stream));
+}
+
+static int ensure_pagerank_state(merbit_plan* p, hipStream_t st) {
+  const size_t vb = vsize(p->dtype) * (size_t)p->n_rows;
+  if (!p->dmask) {
+    unsigned char* bytes = nullptr;
+    HIP_TRY(hipMalloc(&p->dmask, sizeof(uint32_t) * (size_t)((p->n_cols + 31) / 32 + 1)));
+    HIP_TRY(hipMalloc(&bytes, (size_t)(p->n_cols > 0 ? p->n_cols : 1)));
+    hipError_t e = launch_dangling_mask(p->col, p->nnz, p->n_cols, bytes, p->dmask, st);
+    hipError_t e2 = hipStreamSynchronize(st);
+    (void)hipFree(bytes);
+    if (e != hipSuccess) return fail_hip("dangling mask", e);
+    if (e2 != hipSuccess) return fail_hip("dangling mask sync", e2);
+  }
+  if (!p->ybuf[0]) {
+    HIP_TRY(hipMalloc(&p->ybuf[0], vb));
+    HIP_TRY(hipMalloc(&p->ybuf[1], vb));
+    HIP_TRY(hipMalloc(&p->xwork, vb));
+    p->zeroed_buf = -1;
+  }
+  if (!p->acc) {
+    p->reduce_grid = pr_reduce_grid(p->n_rows);
+    HIP_TRY(hipMalloc(&p->acc, 4 * sizeof(double)));
+    HIP_TRY(hipMalloc(&p->partials, 2 * sizeof(double) * (size_t)p->reduce_grid));
+    HIP_TRY(hipMalloc(&p->counter, sizeof(unsigned)));
+    HIP_TRY(hipMemsetAsync(p->counter, 0, sizeof(unsigned), st));
+    HIP_TRY(hipMemsetAsync(p->acc, 0, 4 * sizeof(double), st));
+  }
+  return MERBIT_OK;
+}
+
+int merbit_pagerank(merbit_plan* p, double alpha, double tol, int max_iter, int check_every,
+                    void* x_inout, int* iters_out, double* resid_out, void* stream) {
+  if (iters_out) *iters_out = 0;
+  if (resid_out) *resid_out = 0.0;
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->n_rows != p->n_cols) return fail(MERBIT_EINVAL, "PageRank needs a square matrix");
+  if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(MERBIT_EINVAL, "alpha must be in [0, 1]");
+  if (max_iter < 0) return fail(MERBIT_EINVAL, "max_iter < 0");
+  if (p->n_rows == 0 || max_iter == 0) return MERBIT_OK;
+  if (!x_inout) return fail(MERBIT_EINVAL, "x is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = ensure_pagerank_state(p, st);
+  if (rc != MERBIT_OK) return rc;
+  if (check_every <= 0) check_every = 10;
+  const int64_t n = p->n_rows;
+  const size_t vb = vsize(p->dtype) * (size_t)n;
+
+  // delta_0 = dangling mass of x_0 into acc slot 0
+  HIP_TRY(launch_dangling_sum(p->dtype, x_inout, p->dmask, n, p->partials, p->counter, p->acc,
+                              p->reduce_grid, st));
+  int yb = p->zeroed_buf;
+  if (yb < 0) {
+    yb = 0;
+    HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->block_num, p->waves,
+                                 p->ybuf[0], st));
+  }
+  void* xs[2] = {x_inout, p->xwork};
+  int t = 0;
+  double resid = 0.0;
+  bool converged = false;
+  while (t < max_iter) {
+    const int cur = t & 1;
+    rc = run_fused(p, xs[cur], p->ybuf[yb], p->ybuf[yb ^ 1], st);
+    if (rc != MERBIT_OK) return rc;
+    HIP_TRY(launch_pr_update(p->dtype, p->ybuf[yb], xs[cur], xs[cur ^ 1], p->dmask, n, alpha,
+                             p->acc + 2 * cur, p->partials, p->counter, p->acc + 2 * (cur ^ 1),
+                             p->reduce_grid, st));
+    yb ^= 1;
+    ++t;
+    const bool at_check = tol > 0.0 && (t % check_every == 0 || t == max_iter);
+    if (at_check || t == max_iter) {
+      double slot[2];
+      HIP_TRY(hipMemcpyAsync(slot, p->acc + 2 * (t & 1), sizeof slot, hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      resid = slot[1];
+      if (tol > 0.0 && resid < tol) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  p->zeroed_buf = yb;
+  p->last_stream = st;
+  if (t & 1) HIP_TRY(hipMemcpyAsync(x_inout, p->xwork, vb, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (iters_out) *iters_out = t;
+  if (resid_out) *resid_out = resid;
+  return (tol > 0.0 && !converged) ? MERBIT_NOT_CONVERGED : MERBIT_OK;
+}
+
+int merbit_profile_enable(merbit_plan* p, int enable) {
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  p->profiling = enable != 0;
+  return MERBIT_OK;
+}
+
+int merbit_profile_read(merbit_plan* p, int64_t* launches, double* total_ms) {
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  double total = 0.0;
+  for (size_t k = 0; k < p->events_used; ++k) {
+    HIP_TRY(hipEventSynchronize(p->events[k].second));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, p->events[k].first, p->events[k].second));
+    total += ms;
+  }
+  if (launches) *launches = (int64_t)p->events_used;
+  if (total_ms) *total_ms = total;
+  p->events_used = 0;
+  return MERBIT_OK;
+}
+
+void merbit_plan_destroy(merbit_plan* p) { plan_free_all(p); }
+
+}  // extern "C"

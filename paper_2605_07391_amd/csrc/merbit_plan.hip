@@ -1,0 +1,126 @@
+// One-time preprocessing: CSR validation and TILE generation
+// (Sec. 4.1.2 of the MERBIT paper; merge_search is Algorithm 1).
+//
+// One thread per lane, one 64-lane wavefront per tile (omega = 64).  Each
+// thread finds its lane's start on the merge path by a binary search along
+// its diagonal j * sigma, takes the tile start from lane 0 of its wavefront,
+// walks its sigma steps recording a 1 bit per down step, packs the
+// descriptor, and the wavefront votes whether any of its lanes left the tile's
+// start row (if none did, the tile is a single-row "fast" tile and bit 31 of
+// tile_y is set).  Cost O(lane_num (log n + sigma)); the row_ptr reads are
+// served from L2 after the first probes.
+#include "merbit_internal.hpp"
+
+namespace merbit {
+
+__global__ void validate_kernel(const int32_t* __restrict__ row_ptr,
+                                const int32_t* __restrict__ col, int64_t n_rows, int64_t n_cols,
+                                int64_t nnz, unsigned* __restrict__ flags) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned f = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n_rows; i += stride) {
+    const int32_t v = row_ptr[i];
+    if (i == 0 && v != 0) f |= 1u;
+    if (i == n_rows && (int64_t)v != nnz) f |= 2u;
+    if (i < n_rows && v > row_ptr[i + 1]) f |= 4u;
+  }
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += stride) {
+    const int32_t c = col[k];
+    if (c < 0 || (int64_t)c >= n_cols) f |= 8u;
+  }
+  if (f) atomicOr(flags, f);
+}
+
+hipError_t launch_validate(const int32_t* row_ptr, const int32_t* col, int64_t n_rows,
+                           int64_t n_cols, int64_t nnz, unsigned* flags, hipStream_t st) {
+  const int64_t work = (n_rows + 1 > nnz ? n_rows + 1 : nnz);
+  int64_t grid = (work + 255) / 256;
+  if (grid > 4096) grid = 4096;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(validate_kernel, dim3((unsigned)grid), dim3(256), 0, st, row_ptr, col,
+                     n_rows, n_cols, nnz, flags);
+  return hipGetLastError();
+}
+
+// Algorithm 1: number of rows finished when the path crosses diagonal `diag`.
+// Row r is finished after diagonal row_ptr[r + 1] + r + 1, which increases
+// strictly with r, so a binary search over r finds the crossing.
+__device__ __forceinline__ int32_t merge_search_rows(const int32_t* __restrict__ row_ptr,
+                                                     int32_t n_rows, int32_t nnz, int32_t diag) {
+  int32_t lo = diag - nnz > 0 ? diag - nnz : 0;
+  int32_t hi = diag < n_rows ? diag : n_rows;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi) >> 1;
+    if (row_ptr[mid + 1] <= diag - mid - 1) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(256) void plan_kernel(PlanArgs a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lid = threadIdx.x & (kOmega - 1);
+  const int32_t L = a.nnz + a.n_rows;
+  if (j < a.lane_num) {
+    const int32_t diag = (int32_t)j * a.sigma;
+    int32_t cy = merge_search_rows(a.row_ptr, a.n_rows, a.nnz, diag);
+    int32_t cx = diag - cy;
+    // lane 0 of the wavefront starts the tile (it is active whenever any
+    // lane of this wavefront is)
+    const int32_t tx = __shfl(cx, 0, kOmega);
+    const int32_t ty = __shfl(cy, 0, kOmega);
+    const uint32_t x_off = (uint32_t)(cx - tx);
+    const uint32_t y_off = (uint32_t)(cy - ty);
+    const int32_t steps = (L - diag) < a.sigma ? (L - diag) : a.sigma;
+    uint32_t flags = 0;
+    for (int32_t k = 0; k < steps; ++k) {
+      if (cy >= a.n_rows) break;  // only reachable for a malformed row_ptr
+      if (cx < a.row_ptr[cy + 1]) {
+        ++cx;
+      } else {
+        flags |= 1u << k;
+        ++cy;
+      }
+    }
+    a.lane_desc[j] = (flags << (2 * a.bits)) | (y_off << a.bits) | x_off;
+    const unsigned long long active = __ballot(1);
+    const unsigned long long stayed = __ballot(cy == ty);
+    if (lid == 0) {
+      const int64_t i = j / kOmega;
+      a.tile_x[i] = tx;
+      a.tile_y[i] = (uint32_t)ty | (stayed == active ? kFastBit : 0u);
+    }
+  } else if (j == a.lane_num) {
+    a.tile_x[a.tile_num] = a.nnz;
+    a.tile_y[a.tile_num] = (uint32_t)a.n_rows;
+  }
+}
+
+hipError_t launch_plan(const PlanArgs& a, hipStream_t st) {
+  const int64_t threads = a.lane_num + 1;
+  const int64_t grid = (threads + 255) / 256;
+  hipLaunchKernelGGL(plan_kernel, dim3((unsigned)grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+__global__ void count_fast_kernel(const uint32_t* __restrict__ tile_y, int64_t tile_num,
+                                  unsigned long long* __restrict__ count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tile_num; i += stride)
+    c += (tile_y[i] >> 31) & 1u;
+  c = wave_sum(c);
+  if ((threadIdx.x & (kOmega - 1)) == 0 && c) atomicAdd(count, c);
+}
+
+hipError_t launch_count_fast(const uint32_t* tile_y, int64_t tile_num, unsigned long long* count,
+                             hipStream_t st) {
+  int64_t grid = (tile_num + 255) / 256;
+  if (grid > 2048) grid = 2048;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(count_fast_kernel, dim3((unsigned)grid), dim3(256), 0, st, tile_y,
+                     tile_num, count);
+  return hipGetLastError();
+}
+
+}  // namespace merbit

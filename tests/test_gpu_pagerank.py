@@ -1,0 +1,150 @@
+"""GPU PageRank (Sec. 5.5.1) against the oracle, iterate by iterate, and
+against invariants (mass 1, stationarity, closed forms)."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+from helpers import workload, PR_TOL, host_values, require_gpu, to_device
+
+pytestmark = pytest.mark.gpu
+ALPHA = 0.85
+DTYPES = [torch.float32, torch.float64]
+
+
+def _plan(w, dtype, dev, **kw):
+    import paper_2605_07391_amd as pkg
+    r, c, v = to_device(w["row_ptr"], w["col"], w["values"], dtype, dev)
+    return pkg.Plan(r, c, v, w["n_cols"], **kw), (r, c, v)
+
+
+def _x0(n, dtype, dev):
+    x0 = np.full(n, 1.0 / n).astype(np.float32 if dtype == torch.float32 else np.float64)
+    return x0.astype(np.float64), torch.from_numpy(x0).to(dev)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+def test_chung_lu_20_iterations_iterate_by_iterate(dtype):
+    dev = require_gpu()
+    w = workload("chung_lu_10k")
+    n = w["n_rows"]
+    plan, keep = _plan(w, dtype, dev)
+    x0_64, x0 = _x0(n, dtype, dev)
+    vals = host_values(w["values"], dtype)
+    _, resid_ref, hist = oracle.pagerank(w["row_ptr"], w["col"], vals, ALPHA, 20, x0_64,
+                                         history=True)
+    for t in range(1, 21):
+        x = x0.clone()
+        iters, resid, conv = plan.pagerank(x, ALPHA, tol=0.0, max_iter=t)
+        assert iters == t and conv
+        got = x.double().cpu().numpy()
+        ref = hist[t - 1]
+        rel = np.abs(got - ref) / ref
+        assert rel.max() <= PR_TOL[dtype], f"iteration {t}: {rel.max():.3e}"
+        assert abs(resid - resid_ref[t - 1]) <= 1e-3 * resid_ref[t - 1] + 1e-7
+        assert abs(got.sum() - 1.0) <= (1e-5 if dtype == torch.float32 else 1e-12)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+def test_converges_to_stationary_vector(dtype):
+    dev = require_gpu()
+    w = workload("chung_lu_10k")
+    n = w["n_rows"]
+    plan, keep = _plan(w, dtype, dev)
+    x0_64, x0 = _x0(n, dtype, dev)
+    tol = 1e-6 if dtype == torch.float32 else 1e-13
+    x = x0.clone()
+    iters, resid, conv = plan.pagerank(x, ALPHA, tol=tol, max_iter=500, check_every=5)
+    assert conv and resid < tol and iters < 500 and iters % 5 == 0
+    x_star, _, _ = oracle.pagerank(w["row_ptr"], w["col"], host_values(w["values"], dtype),
+                                   ALPHA, 230, x0_64)
+    got = x.double().cpu().numpy()
+    # ||x_t - x*||_1 <= ||x_t - x_{t+1}||_1 / (1 - alpha) for a contraction
+    bound = 5 * tol / (1 - ALPHA) + (1e-4 if dtype == torch.float32 else 1e-12)
+    assert np.abs(got - x_star).sum() <= bound
+    assert abs(got.sum() - 1.0) <= (1e-5 if dtype == torch.float32 else 1e-12)
+    # not converged within the cap -> status says so
+    x = x0.clone()
+    iters, resid, conv = plan.pagerank(x, ALPHA, tol=1e-30, max_iter=3, check_every=1)
+    assert not conv and iters == 3
+    plan.close()
+
+
+def _edges_matrix(n, edges):
+    edges = sorted(set(edges), key=lambda e: (e[1], e[0]))
+    outdeg = np.zeros(n)
+    for u, _ in edges:
+        outdeg[u] += 1
+    rp = np.zeros(n + 1, np.int64)
+    for _, v in edges:
+        rp[v + 1] += 1
+    rp = np.cumsum(rp).astype(np.int32)
+    col = np.array([u for u, _ in edges], np.int32)
+    vals = np.array([1.0 / outdeg[u] for u, _ in edges])
+    return {"row_ptr": rp, "col": col, "values": vals, "n_rows": n, "n_cols": n}
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+def test_closed_forms(dtype):
+    dev = require_gpu()
+    n = 5000
+    tolr = 1e-6 if dtype == torch.float32 else 1e-13
+    rng = np.random.default_rng(1)
+    x0h = rng.dirichlet(np.ones(n))
+    # directed cycle: converges to uniform
+    w = _edges_matrix(n, [(i, (i + 1) % n) for i in range(n)])
+    plan, keep = _plan(w, dtype, dev)
+    x = torch.from_numpy(x0h).to(dtype).to(dev)
+    plan.pagerank(x, ALPHA, tol=0.0, max_iter=250)
+    got = x.double().cpu().numpy()
+    assert np.all(np.abs(got * n - 1.0) <= 10 * tolr + 2 * ALPHA ** 250 * n)
+    plan.close()
+    # no edges: every vertex dangling -> uniform after one step
+    w = {"row_ptr": np.zeros(n + 1, np.int32), "col": np.zeros(0, np.int32),
+         "values": np.zeros(0), "n_rows": n, "n_cols": n}
+    plan, keep = _plan(w, dtype, dev)
+    x = torch.from_numpy(x0h).to(dtype).to(dev)
+    plan.pagerank(x, ALPHA, tol=0.0, max_iter=1)
+    assert np.all(np.abs(x.double().cpu().numpy() * n - 1.0) <= 10 * tolr)
+    plan.close()
+    # alpha = 0: pure teleport
+    w = _edges_matrix(n, [(i, (7 * i + 3) % n) for i in range(n)] + [(0, 5), (9, 5)])
+    plan, keep = _plan(w, dtype, dev)
+    x = torch.from_numpy(x0h).to(dtype).to(dev)
+    plan.pagerank(x, 0.0, tol=0.0, max_iter=1)
+    assert np.all(np.abs(x.double().cpu().numpy() * n - 1.0) <= 10 * tolr)
+    plan.close()
+
+
+def test_rejects_non_square():
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    r, c, v = to_device(np.array([0, 1, 2], np.int32), np.array([0, 2], np.int32), np.ones(2),
+                        torch.float32, dev)
+    plan = pkg.Plan(r, c, v, 3)
+    with pytest.raises(pkg.MerbitError):
+        plan.pagerank(torch.ones(2, device=dev), ALPHA, 0.0, 5)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+def test_rmat22_pagerank_iterates(dtype):
+    """Full-size R-MAT scale 22: 6 iterations from x0 = 1/n vs the oracle."""
+    dev = require_gpu()
+    w = workload("rmat22")
+    n = w["n_rows"]
+    plan, keep = _plan(w, dtype, dev)
+    x0_64, x0 = _x0(n, dtype, dev)
+    x = x0.clone()
+    iters, resid, _ = plan.pagerank(x, ALPHA, tol=0.0, max_iter=6)
+    assert iters == 6
+    ref, resid_ref, _ = oracle.pagerank(w["row_ptr"], w["col"], host_values(w["values"], dtype),
+                                        ALPHA, 6, x0_64)
+    got = x.double().cpu().numpy()
+    rel = np.abs(got - ref) / ref
+    assert rel.max() <= PR_TOL[dtype], f"{rel.max():.3e} at {int(rel.argmax())}"
+    assert abs(got.sum() - 1.0) <= (1e-4 if dtype == torch.float32 else 1e-12)
+    assert abs(resid - resid_ref[-1]) <= 1e-3 * resid_ref[-1]
+    plan.close()

@@ -1,0 +1,246 @@
+"""GPU parity of the plan (bit exact) and of y = A x (|A||x|-normalised
+tolerance) against the CPU oracle, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import graphgen
+import oracle
+from helpers import (workload, OMEGA, SPMV_TOL, check_spmv, host_values, require_gpu, seeded_x,
+                     to_device)
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float32, torch.float64]
+
+
+def _boundary_rows(sigma, block_lanes):
+    """Row lengths that make rows end exactly at lane, tile and block ends
+    (a row of length k takes k + 1 merge-path steps)."""
+    lens = [sigma - 1] * 70 + [OMEGA * sigma - 1] * 3 + [block_lanes * sigma - 1] * 2
+    lens += [0, 0, 1, sigma, OMEGA * sigma, block_lanes * sigma + 5]
+    return lens
+
+
+def _cases():
+    cases = {}
+    cases["one_row"] = (np.array([0, 1], np.int32), 3)
+    cases["all_rows_empty"] = (np.zeros(301, np.int32), 4)
+    cases["single_long_row"] = (np.array([0, 20000], np.int32), 20000)
+    cases["long_then_empty"] = (np.array([0, 2000, 2000, 2000, 2001, 4500] + [4500] * 700,
+                                         np.int32), 3000)
+    for seed, (n, nc, dens, emp) in enumerate([(50, 40, 0.3, 0.2), (700, 300, 0.02, 0.5),
+                                               (1200, 800, 0.02, 0.1), (333, 64, 0.02, 0.0),
+                                               (200, 3000, 0.01, 0.3), (3000, 50, 0.05, 0.2)]):
+        rp, _, _ = graphgen.random_csr(n, nc, dens, seed, empty_frac=emp, long_rows=(n // 3,))
+        cases[f"random{seed}_{n}x{nc}"] = (rp, nc)
+    cases["one_column"] = (np.arange(1001, dtype=np.int32), 1)
+    rp, _ = graphgen.chung_lu_pattern(10_000, 100_000, 2.1, 0.1, seed=1)
+    cases["chung_lu_10k"] = (rp, 10_000)
+    # fuzz: random sizes, densities, empty fractions
+    rng = np.random.default_rng(2024)
+    for f in range(6):
+        n = int(rng.integers(1, 4000))
+        nc = int(rng.integers(1, 4000))
+        dens = float(rng.uniform(0.0005, 0.02))
+        rp, _, _ = graphgen.random_csr(n, nc, dens, 100 + f, empty_frac=float(rng.uniform(0, .7)))
+        cases[f"fuzz{f}_{n}x{nc}"] = (rp, nc)
+    return cases
+
+
+CASES = _cases()
+
+
+def _matrix(name, seed=0):
+    rp, nc = CASES[name]
+    m = int(rp[-1])
+    rng = np.random.default_rng(seed)
+    col = rng.integers(0, nc, m).astype(np.int32)
+    # sort each row's columns so the pattern is a valid CSR (order is free anyway)
+    vals = rng.uniform(-1, 1, m)
+    return rp, col, vals, nc
+
+
+@pytest.mark.parametrize("sigma", [1, 4, 7, 12])
+@pytest.mark.parametrize("name", list(CASES))
+def test_plan_bit_exact(name, sigma):
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    rp, col, vals, nc = _matrix(name)
+    r, c, v = to_device(rp, col, vals, torch.float32, dev)
+    plan = pkg.Plan(r, c, v, nc, sigma=sigma)
+    tx, ty, ld = plan.export()
+    ox, oy, od = oracle.plan(rp, OMEGA, sigma)
+    assert np.array_equal(tx, ox)
+    assert np.array_equal(ty, oy)
+    assert np.array_equal(ld, od)
+    info = plan.info()
+    assert info["tile_num"] == len(ox) - 1 and info["lane_num"] == len(od)
+    assert info["fast_tiles"] == int((oy[:-1] >> 31).sum())
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+@pytest.mark.parametrize("sigma,block_lanes", [(1, 256), (4, 128), (7, 256), (12, 256),
+                                                 (12, 512), (7, 512), (3, 128)])
+@pytest.mark.parametrize("name", list(CASES))
+def test_spmv_parity(name, sigma, block_lanes, dtype):
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    rp, col, vals, nc = _matrix(name, seed=sigma)
+    r, c, v = to_device(rp, col, vals, dtype, dev)
+    x64 = seeded_x(nc, sigma, dtype)
+    x = torch.from_numpy(x64).to(dtype).to(dev)
+    plan = pkg.Plan(r, c, v, nc, sigma=sigma, block_lanes=block_lanes)
+    y = torch.full((len(rp) - 1,), float("nan"), dtype=dtype, device=dev)
+    plan.spmv(x, out=y)
+    torch.cuda.synchronize()
+    check_spmv(y, rp, col, host_values(vals, dtype), x64, dtype,
+               f"{name} sigma={sigma} b={block_lanes}")
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+@pytest.mark.parametrize("sigma", [4, 7, 12])
+def test_rows_ending_on_lane_tile_block_boundaries(sigma, dtype):
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    for block_lanes in (128, 256, 512):
+        lens = _boundary_rows(sigma, block_lanes)
+        nc = max(lens) + 1
+        rp, col, vals = graphgen.csr_from_lengths(lens, nc, seed=sigma + block_lanes)
+        r, c, v = to_device(rp, col, vals, dtype, dev)
+        x64 = seeded_x(nc, 3, dtype)
+        x = torch.from_numpy(x64).to(dtype).to(dev)
+        plan = pkg.Plan(r, c, v, nc, sigma=sigma, block_lanes=block_lanes)
+        tx, ty, ld = plan.export()
+        ox, oy, od = oracle.plan(rp, OMEGA, sigma)
+        assert np.array_equal(ty, oy) and np.array_equal(ld, od) and np.array_equal(tx, ox)
+        y = plan.spmv(x)
+        torch.cuda.synchronize()
+        check_spmv(y, rp, col, host_values(vals, dtype), x64, dtype, f"b={block_lanes}")
+        plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+def test_dual_buffer_chain(dtype):
+    """Alternating outputs: each call needs y zero at the boundary rows and
+    leaves z zero there (Sec. 4.2, optimisation (3))."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    rp, col, vals, nc = _matrix("chung_lu_10k", seed=5)
+    r, c, v = to_device(rp, col, vals, dtype, dev)
+    plan = pkg.Plan(r, c, v, nc)
+    n = len(rp) - 1
+    bufs = [torch.full((n,), float("nan"), dtype=dtype, device=dev) for _ in range(2)]
+    plan.zero_boundary(bufs[0])
+    for it in range(5):
+        x64 = seeded_x(nc, 10 + it, dtype)
+        x = torch.from_numpy(x64).to(dtype).to(dev)
+        plan.spmv_dual(x, bufs[it % 2], bufs[(it + 1) % 2])
+        torch.cuda.synchronize()
+        check_spmv(bufs[it % 2], rp, col, host_values(vals, dtype), x64, dtype, f"iter {it}")
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+def test_set_values_and_repeat(dtype):
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    rp, col, vals, nc = _matrix("random2_1200x800", seed=1)
+    r, c, v = to_device(rp, col, vals, dtype, dev)
+    plan = pkg.Plan(r, c, v, nc)
+    x64 = seeded_x(nc, 4, dtype)
+    x = torch.from_numpy(x64).to(dtype).to(dev)
+    y1 = plan.spmv(x)
+    y2 = plan.spmv(x, out=torch.full_like(y1, 7.0))
+    torch.cuda.synchronize()
+    check_spmv(y1, rp, col, host_values(vals, dtype), x64, dtype)
+    check_spmv(y2, rp, col, host_values(vals, dtype), x64, dtype)
+    vals2 = vals * -2.5
+    v2 = torch.from_numpy(vals2).to(dtype).to(dev)
+    plan.set_values(v2)
+    y3 = plan.spmv(x)
+    torch.cuda.synchronize()
+    check_spmv(y3, rp, col, host_values(vals2, dtype), x64, dtype)
+    plan.close()
+
+
+def test_validation_and_degenerate_shapes():
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    f = torch.float32
+    # decreasing row_ptr
+    r, c, v = to_device(np.array([0, 3, 2, 4], np.int32), np.zeros(4, np.int32), np.ones(4), f,
+                        dev)
+    with pytest.raises(pkg.MerbitError):
+        pkg.Plan(r, c, v, 2)
+    # column out of range
+    r, c, v = to_device(np.array([0, 2], np.int32), np.array([0, 5], np.int32), np.ones(2), f,
+                        dev)
+    with pytest.raises(pkg.MerbitError):
+        pkg.Plan(r, c, v, 3)
+    # row_ptr[n] != nnz
+    r, c, v = to_device(np.array([0, 1], np.int32), np.array([0, 0], np.int32), np.ones(2), f,
+                        dev)
+    with pytest.raises(pkg.MerbitError):
+        pkg.Plan(r, c, v, 3)
+    # no rows at all
+    r, c, v = to_device(np.array([0], np.int32), np.zeros(0, np.int32), np.zeros(0), f, dev)
+    plan = pkg.Plan(r, c, v, 5)
+    y = plan.spmv(torch.ones(5, dtype=f, device=dev))
+    assert y.numel() == 0
+    tx, ty, ld = plan.export()
+    assert list(tx) == [0] and list(ty) == [0] and len(ld) == 0
+    plan.close()
+    # rows but no nonzeros: y = 0 whatever it held
+    r, c, v = to_device(np.zeros(1000, np.int32), np.zeros(0, np.int32), np.zeros(0), f, dev)
+    plan = pkg.Plan(r, c, v, 0)
+    y = plan.spmv(torch.zeros(0, dtype=f, device=dev),
+                  out=torch.full((999,), float("nan"), dtype=f, device=dev))
+    torch.cuda.synchronize()
+    assert torch.all(y == 0)
+    plan.close()
+
+
+def test_profile_counts_launches():
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    rp, col, vals, nc = _matrix("chung_lu_10k")
+    r, c, v = to_device(rp, col, vals, torch.float32, dev)
+    plan = pkg.Plan(r, c, v, nc)
+    x = torch.ones(nc, device=dev)
+    plan.profile_enable(True)
+    for _ in range(3):
+        plan.spmv(x)
+    n, ms = plan.profile_read()
+    assert n == 3 and ms > 0
+    plan.profile_enable(False)
+    plan.spmv(x)
+    assert plan.profile_read()[0] == 0
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype,sigma", [(torch.float32, 12), (torch.float64, 7)],
+                         ids=["f32s12", "f64s7"])
+def test_rmat22_full_size(dtype, sigma):
+    """R-MAT scale 22 (the benchmark matrix) at full size: plan bit exact and
+    every row of y within tolerance, in the benchmark's launch configuration."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    w = workload("rmat22")
+    rp, col, vals, n = w["row_ptr"], w["col"], w["values"], w["n_rows"]
+    r, c, v = to_device(rp, col, vals, dtype, dev)
+    plan = pkg.Plan(r, c, v, n, sigma=sigma)
+    tx, ty, ld = plan.export()
+    ox, oy, od = oracle.plan(rp, OMEGA, sigma)
+    assert np.array_equal(tx, ox) and np.array_equal(ty, oy) and np.array_equal(ld, od)
+    # x: a PageRank-like positive vector plus a mixed-sign one
+    for k, x64 in enumerate([np.full(n, 1.0 / n), seeded_x(n, 22, dtype)]):
+        x64 = x64.astype(np.float32 if dtype == torch.float32 else np.float64).astype(np.float64)
+        x = torch.from_numpy(x64).to(dtype).to(dev)
+        y = torch.full((n,), float("nan"), dtype=dtype, device=dev)
+        plan.spmv(x, out=y)
+        torch.cuda.synchronize()
+        check_spmv(y, rp, col, host_values(vals, dtype), x64, dtype, f"rmat22 x{k}")
+    plan.close()

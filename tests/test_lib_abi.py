@@ -1,0 +1,68 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol that
+include/merbit.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+
+def _declared():
+    with open(os.path.join(ROOT, "include", "merbit.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(merbit_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for required in ("merbit_plan_create", "merbit_spmv", "merbit_pagerank",
+                     "merbit_plan_destroy", "merbit_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2605_07391_amd as pkg
+    lib = pkg.load()
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert set(_declared()) == set(pkg.EXPORTED)
+    assert "gfx950" in pkg.version()
+
+
+def test_argument_errors_without_gpu():
+    import paper_2605_07391_amd.merbit as mb
+    lib = mb.load()
+    out = ctypes.c_void_p()
+    vp = ctypes.c_void_p
+    # NULL out pointer
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, 0, 0, 0, None, None) == mb.EINVAL
+    # unsupported dtype
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 7, 0, 0, 0, None,
+                                  ctypes.byref(out)) == mb.EUNSUPPORTED
+    # sigma 13 does not fit a 32-bit descriptor at omega = 64
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, 13, 0, 0, None,
+                                  ctypes.byref(out)) == mb.EUNSUPPORTED
+    assert b"sigma" in lib.merbit_last_error()
+    # size limit n_rows + nnz < 2^31
+    assert lib.merbit_plan_create(1 << 30, 1, 1 << 30, vp(8), vp(8), vp(8), 0, 0, 0, 0, None,
+                                  ctypes.byref(out)) == mb.EINVAL
+    # block size not built
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, 0, 192, 0, None,
+                                  ctypes.byref(out)) == mb.EUNSUPPORTED
+    assert not out.value
+    # calls on a NULL plan
+    assert lib.merbit_spmv(None, None, None, None) == mb.EINVAL
+    assert lib.merbit_pagerank(None, 0.85, 0.0, 1, 1, None, None, None, None) == mb.EINVAL
+
+
+def test_oracle_is_not_imported_by_the_package():
+    pkg_dir = os.path.join(ROOT, "paper_2605_07391_amd")
+    for dirpath, _, files in os.walk(pkg_dir):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                with open(os.path.join(dirpath, fn)) as f:
+                    src = f.read()
+                assert "import oracle" not in src and "from oracle" not in src, fn
+                assert "merbit_oracle" not in src, fn
