@@ -32,9 +32,8 @@ struct merbit_plan {
   uint32_t* dmask = nullptr;
   void* ybuf[2] = {nullptr, nullptr};
   void* xwork = nullptr;
-  double* acc = nullptr;       // 2 slots x (dangling mass, l1 change)
-  double* partials = nullptr;  // 2 per reduction block
-  unsigned* counter = nullptr;
+  // per-block (dangling mass, l1 change) pairs of the last two reductions
+  double* partials[2] = {nullptr, nullptr};
   int reduce_grid = 0;
   int zeroed_buf = -1;  // which ybuf is zero at the boundary rows, -1 if none
   // kernel timing
@@ -67,7 +66,7 @@ static void plan_free_all(merbit_plan* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
   void* bufs[] = {p->tile_x, p->tile_y, p->lane_desc, p->scratch, p->dmask, p->ybuf[0],
-                  p->ybuf[1], p->xwork, p->acc, p->partials, p->counter};
+                  p->ybuf[1], p->xwork, p->partials[0], p->partials[1]};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& ev : p->events) {
@@ -321,13 +320,10 @@ static int ensure_pagerank_state(merbit_plan* p, hipStream_t st) {
     HIP_TRY(hipMalloc(&p->xwork, vb));
     p->zeroed_buf = -1;
   }
-  if (!p->acc) {
+  if (!p->partials[0]) {
     p->reduce_grid = pr_reduce_grid(p->n_rows);
-    HIP_TRY(hipMalloc(&p->acc, 4 * sizeof(double)));
-    HIP_TRY(hipMalloc(&p->partials, 2 * sizeof(double) * (size_t)p->reduce_grid));
-    HIP_TRY(hipMalloc(&p->counter, sizeof(unsigned)));
-    HIP_TRY(hipMemsetAsync(p->counter, 0, sizeof(unsigned), st));
-    HIP_TRY(hipMemsetAsync(p->acc, 0, 4 * sizeof(double), st));
+    HIP_TRY(hipMalloc(&p->partials[0], 2 * sizeof(double) * (size_t)p->reduce_grid));
+    HIP_TRY(hipMalloc(&p->partials[1], 2 * sizeof(double) * (size_t)p->reduce_grid));
   }
   return MERBIT_OK;
 }
@@ -349,9 +345,9 @@ int merbit_pagerank(merbit_plan* p, double alpha, double tol, int max_iter, int 
   const int64_t n = p->n_rows;
   const size_t vb = vsize(p->dtype) * (size_t)n;
 
-  // delta_0 = dangling mass of x_0 into acc slot 0
-  HIP_TRY(launch_dangling_sum(p->dtype, x_inout, p->dmask, n, p->partials, p->counter, p->acc,
-                              p->reduce_grid, st));
+  // delta_0: per-block dangling mass of x_0 into partials[0]
+  HIP_TRY(launch_dangling_sum(p->dtype, x_inout, p->dmask, n, p->partials[0], p->reduce_grid,
+                              st));
   int yb = p->zeroed_buf;
   if (yb < 0) {
     yb = 0;
@@ -359,6 +355,7 @@ int merbit_pagerank(merbit_plan* p, double alpha, double tol, int max_iter, int 
                                  p->ybuf[0], st));
   }
   void* xs[2] = {x_inout, p->xwork};
+  std::vector<double> host_pairs(2 * (size_t)p->reduce_grid);
   int t = 0;
   double resid = 0.0;
   bool converged = false;
@@ -367,16 +364,18 @@ int merbit_pagerank(merbit_plan* p, double alpha, double tol, int max_iter, int 
     rc = run_fused(p, xs[cur], p->ybuf[yb], p->ybuf[yb ^ 1], st);
     if (rc != MERBIT_OK) return rc;
     HIP_TRY(launch_pr_update(p->dtype, p->ybuf[yb], xs[cur], xs[cur ^ 1], p->dmask, n, alpha,
-                             p->acc + 2 * cur, p->partials, p->counter, p->acc + 2 * (cur ^ 1),
+                             p->partials[cur], p->reduce_grid, p->partials[cur ^ 1],
                              p->reduce_grid, st));
     yb ^= 1;
     ++t;
     const bool at_check = tol > 0.0 && (t % check_every == 0 || t == max_iter);
     if (at_check || t == max_iter) {
-      double slot[2];
-      HIP_TRY(hipMemcpyAsync(slot, p->acc + 2 * (t & 1), sizeof slot, hipMemcpyDeviceToHost, st));
+      // l1 change of this iteration: sum of the blocks' second components
+      HIP_TRY(hipMemcpyAsync(host_pairs.data(), p->partials[t & 1],
+                             sizeof(double) * host_pairs.size(), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
-      resid = slot[1];
+      resid = 0.0;
+      for (int b = 0; b < p->reduce_grid; ++b) resid += host_pairs[2 * (size_t)b + 1];
       if (tol > 0.0 && resid < tol) {
         converged = true;
         break;

@@ -85,11 +85,10 @@ hipError_t launch_zero_boundary(int dtype, const uint32_t* tile_y, int32_t block
 hipError_t launch_dangling_mask(const int32_t* col, int64_t nnz, int64_t n,
                                 unsigned char* scratch_bytes, uint32_t* dmask, hipStream_t st);
 hipError_t launch_dangling_sum(int dtype, const void* x, const uint32_t* dmask, int64_t n,
-                               double* partials, unsigned* counter, double* out, int grid,
-                               hipStream_t st);
+                               double* partials_out, int grid, hipStream_t st);
 hipError_t launch_pr_update(int dtype, const void* y, const void* x_old, void* x_new,
-                            const uint32_t* dmask, int64_t n, double alpha, const double* acc_in,
-                            double* partials, unsigned* counter, double* acc_out, int grid,
+                            const uint32_t* dmask, int64_t n, double alpha,
+                            const double* partials_in, int n_in, double* partials_out, int grid,
                             hipStream_t st);
 int pr_reduce_grid(int64_t n);
 

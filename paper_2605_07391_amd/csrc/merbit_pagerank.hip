@@ -6,9 +6,9 @@
 //   pr_update(y, x_t -> x_{t+1})   x_{t+1} = alpha y + (alpha delta_t + 1 - alpha) / n
 // and the update also produces delta_{t+1} = sum of x_{t+1} over dangling
 // vertices and r_{t+1} = ||x_{t+1} - x_t||_1 for the next step.  Both sums
-// are reduced in double, per block and then by the last block to finish, in
-// a fixed order (so they are deterministic); the last block also resets the
-// arrival counter, so no memset is needed between launches.
+// are reduced in double: per block in the update kernel, then over the blocks
+// by the next update kernel (delta) or by the host (r), always in the same
+// order, so they are deterministic.
 #include "merbit_internal.hpp"
 
 namespace merbit {
@@ -60,16 +60,20 @@ hipError_t launch_dangling_mask(const int32_t* col, int64_t nnz, int64_t n,
 }
 
 // ------------------------------------------------ two-value reduction ----
+//
+// Each block of a reduction kernel writes its pair of sums to partials[2b],
+// partials[2b+1] with plain stores; the kernel that consumes the total (the
+// next update, or the host) sums the pairs in block order.  Kernel boundaries
+// order the writes before the reads, so no device-scope fence is needed, and
+// every consumer block computes the same bits.
 
-// Reduce (a, b) over the grid.  Every block writes its pair to partials; the
-// last block to arrive sums all pairs in block order and writes out[0..1].
-__device__ void grid_reduce2(double a, double b, double* __restrict__ partials,
-                             unsigned* __restrict__ counter, double* __restrict__ out) {
+// Sum (a, b) over the block in a fixed order; thread 0 gets the totals.
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
   __shared__ double sa[kReduceThreads / kOmega], sb[kReduceThreads / kOmega];
-  __shared__ int is_last;
   const int tid = threadIdx.x, lid = tid & (kOmega - 1), wid = tid / kOmega;
   a = wave_sum(a);
   b = wave_sum(b);
+  __syncthreads();  // sa/sb may still be read from a previous call
   if (lid == 0) {
     sa[wid] = a;
     sb[wid] = b;
@@ -81,44 +85,25 @@ __device__ void grid_reduce2(double a, double b, double* __restrict__ partials,
       ta += sa[w];
       tb += sb[w];
     }
-    __hip_atomic_store(&partials[2 * blockIdx.x], ta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&partials[2 * blockIdx.x + 1], tb, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    const unsigned prev =
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == gridDim.x - 1);
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __atomic_thread_fence(__ATOMIC_ACQUIRE);
-  double pa = 0.0, pb = 0.0;
-  for (unsigned k = tid; k < gridDim.x; k += kReduceThreads) {
-    pa += __hip_atomic_load(&partials[2 * k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    pb += __hip_atomic_load(&partials[2 * k + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  pa = wave_sum(pa);
-  pb = wave_sum(pb);
-  __syncthreads();
-  if (lid == 0) {
-    sa[wid] = pa;
-    sb[wid] = pb;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double ta = 0.0, tb = 0.0;
-    for (int w = 0; w < kReduceThreads / kOmega; ++w) {
-      ta += sa[w];
-      tb += sb[w];
-    }
-    out[0] = ta;
-    out[1] = tb;
-    __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    a = ta;
+    b = tb;
   }
 }
 
+// Total of the first components of n_in pairs, identical in every block.
+__device__ __forceinline__ double sum_partials_first(const double* __restrict__ p, int n_in) {
+  __shared__ double total;
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < n_in; k += kReduceThreads) a += p[2 * k];
+  block_sum2(a, b);
+  if (threadIdx.x == 0) total = a;
+  __syncthreads();
+  return total;
+}
+
 int pr_reduce_grid(int64_t n) {
-  int64_t g = (n + kReduceThreads * 8 - 1) / (kReduceThreads * 8);
-  if (g > 2048) g = 2048;
+  int64_t g = (n + kReduceThreads * 16 - 1) / (kReduceThreads * 16);
+  if (g > 1024) g = 1024;
   if (g < 1) g = 1;
   return (int)g;
 }
@@ -126,62 +111,86 @@ int pr_reduce_grid(int64_t n) {
 template <typename V>
 __global__ __launch_bounds__(kReduceThreads) void dangling_sum_kernel(
     const V* __restrict__ x, const uint32_t* __restrict__ dmask, int64_t n,
-    double* __restrict__ partials, unsigned* __restrict__ counter, double* __restrict__ out) {
+    double* __restrict__ partials_out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  double d = 0.0;
+  double d = 0.0, z = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
     if ((dmask[i >> 5] >> (i & 31)) & 1u) d += (double)x[i];
-  grid_reduce2(d, 0.0, partials, counter, out);
+  block_sum2(d, z);
+  if (threadIdx.x == 0) {
+    partials_out[2 * blockIdx.x] = d;
+    partials_out[2 * blockIdx.x + 1] = 0.0;
+  }
 }
 
 hipError_t launch_dangling_sum(int dtype, const void* x, const uint32_t* dmask, int64_t n,
-                               double* partials, unsigned* counter, double* out, int grid,
-                               hipStream_t st) {
+                               double* partials_out, int grid, hipStream_t st) {
   if (dtype == 0)
     hipLaunchKernelGGL(dangling_sum_kernel<float>, dim3(grid), dim3(kReduceThreads), 0, st,
-                       static_cast<const float*>(x), dmask, n, partials, counter, out);
+                       static_cast<const float*>(x), dmask, n, partials_out);
   else
     hipLaunchKernelGGL(dangling_sum_kernel<double>, dim3(grid), dim3(kReduceThreads), 0, st,
-                       static_cast<const double*>(x), dmask, n, partials, counter, out);
+                       static_cast<const double*>(x), dmask, n, partials_out);
   return hipGetLastError();
 }
 
-// x_new = alpha y + (alpha delta + 1 - alpha) / n; accumulates the dangling
-// mass of x_new and ||x_new - x_old||_1 into acc_out[0], acc_out[1].
+// x_new = alpha y + (alpha delta + 1 - alpha) / n, with delta the dangling
+// mass of x_old (summed from the previous kernel's partials).  Writes this
+// block's dangling mass of x_new and ||x_new - x_old||_1 to partials_out.
 template <typename V>
 __global__ __launch_bounds__(kReduceThreads) void pr_update_kernel(
     const V* __restrict__ y, const V* __restrict__ x_old, V* __restrict__ x_new,
     const uint32_t* __restrict__ dmask, int64_t n, double alpha,
-    const double* __restrict__ acc_in, double* __restrict__ partials,
-    unsigned* __restrict__ counter, double* __restrict__ acc_out) {
-  const double delta = acc_in[0];
+    const double* __restrict__ partials_in, int n_in, double* __restrict__ partials_out) {
+  constexpr int ILP = 4;
+  const double delta = sum_partials_first(partials_in, n_in);
   const V teleport = (V)((alpha * delta + 1.0 - alpha) / (double)n);
   const V a = (V)alpha;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * ILP;
   double dsum = 0.0, rsum = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const V xn = a * y[i] + teleport;
-    x_new[i] = xn;
-    rsum += fabs((double)xn - (double)x_old[i]);
-    if ((dmask[i >> 5] >> (i & 31)) & 1u) dsum += (double)xn;
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x * ILP + threadIdx.x; base < n;
+       base += stride) {
+    V yv[ILP], xo[ILP];
+    uint32_t mw[ILP];
+#pragma unroll
+    for (int u = 0; u < ILP; ++u) {
+      const int64_t i = min(base + (int64_t)u * kReduceThreads, n - 1);
+      yv[u] = y[i];
+      xo[u] = x_old[i];
+      mw[u] = dmask[i >> 5];
+    }
+#pragma unroll
+    for (int u = 0; u < ILP; ++u) {
+      const int64_t i = base + (int64_t)u * kReduceThreads;
+      if (i < n) {
+        const V xn = a * yv[u] + teleport;
+        x_new[i] = xn;
+        rsum += fabs((double)xn - (double)xo[u]);
+        if ((mw[u] >> (i & 31)) & 1u) dsum += (double)xn;
+      }
+    }
   }
-  grid_reduce2(dsum, rsum, partials, counter, acc_out);
+  block_sum2(dsum, rsum);
+  if (threadIdx.x == 0) {
+    partials_out[2 * blockIdx.x] = dsum;
+    partials_out[2 * blockIdx.x + 1] = rsum;
+  }
 }
 
 hipError_t launch_pr_update(int dtype, const void* y, const void* x_old, void* x_new,
-                            const uint32_t* dmask, int64_t n, double alpha, const double* acc_in,
-                            double* partials, unsigned* counter, double* acc_out, int grid,
+                            const uint32_t* dmask, int64_t n, double alpha,
+                            const double* partials_in, int n_in, double* partials_out, int grid,
                             hipStream_t st) {
   if (dtype == 0)
     hipLaunchKernelGGL(pr_update_kernel<float>, dim3(grid), dim3(kReduceThreads), 0, st,
                        static_cast<const float*>(y), static_cast<const float*>(x_old),
-                       static_cast<float*>(x_new), dmask, n, alpha, acc_in, partials, counter,
-                       acc_out);
+                       static_cast<float*>(x_new), dmask, n, alpha, partials_in, n_in,
+                       partials_out);
   else
     hipLaunchKernelGGL(pr_update_kernel<double>, dim3(grid), dim3(kReduceThreads), 0, st,
                        static_cast<const double*>(y), static_cast<const double*>(x_old),
-                       static_cast<double*>(x_new), dmask, n, alpha, acc_in, partials, counter,
-                       acc_out);
+                       static_cast<double*>(x_new), dmask, n, alpha, partials_in, n_in,
+                       partials_out);
   return hipGetLastError();
 }
 

@@ -50,110 +50,122 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_kernel(SpmvArgs a) {
   const int bs = blockIdx.x * WAVES;
   const int be = min(bs + WAVES, a.tile_num);
 
+  // block and tile bounds, all read before any wait (Algorithm "MERBIT SpMV",
+  // prologue); a wavefront past the last tile works on a clamped copy and
+  // does nothing with it
   const int x_bs = tile_x[bs];
   const int x_be = tile_x[be];
   const int y_bs = (int)(tile_y[bs] & kRowMask);
   const int y_be = (int)(tile_y[be] & kRowMask);
   const int y_se = y_be - y_bs;
+  const int i = min(bs + wid, be - 1);
+  const bool own_tile = bs + wid < be;
+  const int x_ws = tile_x[i];
+  const int x_we = tile_x[i + 1];
+  const uint32_t tyw = tile_y[i];
+  const int end_slot = (int)(tile_y[i + 1] & kRowMask) - y_bs;
+  const int x_se = x_we - x_ws;
+  const bool active = own_tile && x_se > 0;
+  const bool fast = (tyw & kFastBit) != 0u;
+  const int y_bw = (int)(tyw & kRowMask) - y_bs;
+  const int x_bw = x_ws - x_bs;
   V* s_y = s_data + (x_be - x_bs);
+
+  // descriptor of this lane (normal tiles only), issued early
+  const int j = i * kOmega + lid;
+  uint32_t desc = 0;
+  if (active && !fast) desc = a.lane_desc[min(j, a.lane_num - 1)];
+
+  // the tile's nonzeros: coalesced streaming loads, then the x gathers; all
+  // loads are unconditional (indices clamped into the tile) so every one of
+  // them is in flight before the first use
+  V prod[SIGMA];
+  if (active) {
+    const int32_t* __restrict__ tc = col + x_ws;
+    const V* __restrict__ tv = val + x_ws;
+    int cc[SIGMA];
+    V vv[SIGMA];
+#pragma unroll
+    for (int it = 0; it < SIGMA; ++it) {
+      const int k = min(lid + it * kOmega, x_se - 1);
+      cc[it] = __builtin_nontemporal_load(tc + k);
+      vv[it] = __builtin_nontemporal_load(tv + k);
+    }
+#pragma unroll
+    for (int it = 0; it < SIGMA; ++it) prod[it] = vv[it] * x[cc[it]];
+  }
 
   for (int r = tid; r <= y_se; r += NT) s_y[r] = V(0);
   __syncthreads();
 
-  const int i = bs + wid;
-  if (i < be) {
-    const int x_ws = tile_x[i];
-    const int x_we = tile_x[i + 1];
-    if (x_ws < x_we) {
-      const uint32_t tyw = tile_y[i];
-      const int y_bw = (int)(tyw & kRowMask) - y_bs;
-      const int x_bw = x_ws - x_bs;
-      const int x_se = x_we - x_ws;
-      const int32_t* __restrict__ tc = col + x_ws;
-      const V* __restrict__ tv = val + x_ws;
-      int cc[SIGMA];
-      V vv[SIGMA];
+  if (active) {
+    if (fast) {
+      // single-row tile (Sec. 4.2 opt. (1)): no descriptor, no staging
+      V acc = V(0);
+#pragma unroll
+      for (int it = 0; it < SIGMA; ++it)
+        if (lid + it * kOmega < x_se) acc += prod[it];
+      acc = wave_sum(acc);
+      if (lid == 0) atomicAdd(&s_y[y_bw], acc);
+    } else {
+      // stage the products (coalesced by lane)
 #pragma unroll
       for (int it = 0; it < SIGMA; ++it) {
         const int k = lid + it * kOmega;
-        if (k < x_se) {
-          cc[it] = __builtin_nontemporal_load(tc + k);
-          vv[it] = __builtin_nontemporal_load(tv + k);
-        }
+        if (k < x_se) s_data[x_bw + k] = prod[it];
       }
-      if (tyw & kFastBit) {
-        // single-row tile: no descriptor, no staging
-        V acc = V(0);
+      wave_lds_sync();
+      // per-lane walk of its sigma steps (Algorithm tile_normal_tackle)
+      V sum = V(0);
+      bool head = (lid == 0);
+      int start_slot = 0;
+      if (j < a.lane_num) {
+        int xo = x_bw + (int)(desc & FMASK);
+        int yo = y_bw + (int)((desc >> BITS) & FMASK);
+        start_slot = yo;
+        const uint32_t flags = desc >> (2 * BITS);
+        const int steps = min(SIGMA, a.path_len - j * SIGMA);
+        bool first = true;
 #pragma unroll
-        for (int it = 0; it < SIGMA; ++it) {
-          const int k = lid + it * kOmega;
-          if (k < x_se) acc += vv[it] * x[cc[it]];
-        }
-        acc = wave_sum(acc);
-        if (lid == 0) atomicAdd(&s_y[y_bw], acc);
-      } else {
-        // stage the tile's products (coalesced by lane)
-#pragma unroll
-        for (int it = 0; it < SIGMA; ++it) {
-          const int k = lid + it * kOmega;
-          if (k < x_se) s_data[x_bw + k] = vv[it] * x[cc[it]];
-        }
-        wave_lds_sync();
-        // per-lane walk of its sigma steps
-        const int j = i * kOmega + lid;
-        V sum = V(0);
-        bool head = (lid == 0);
-        int start_slot = 0;
-        if (j < a.lane_num) {
-          const uint32_t d = a.lane_desc[j];
-          int xo = x_bw + (int)(d & FMASK);
-          int yo = y_bw + (int)((d >> BITS) & FMASK);
-          start_slot = yo;
-          const uint32_t flags = d >> (2 * BITS);
-          const int steps = min(SIGMA, a.path_len - j * SIGMA);
-          bool first = true;
-#pragma unroll
-          for (int k = 0; k < SIGMA; ++k) {
-            if (k < steps) {
-              if ((flags >> k) & 1u) {
-                if (first) {
-                  atomicAdd(&s_y[yo], sum);  // row may also get other lanes' sums
-                  first = false;
-                } else {
-                  s_y[yo] = sum;  // row lies wholly inside this lane
-                }
-                sum = V(0);
-                ++yo;
+        for (int k = 0; k < SIGMA; ++k) {
+          if (k < steps) {
+            if ((flags >> k) & 1u) {
+              if (first) {
+                atomicAdd(&s_y[yo], sum);  // row may also get other lanes' sums
+                first = false;
               } else {
-                sum += s_data[xo];
-                ++xo;
+                s_y[yo] = sum;  // row lies wholly inside this lane
               }
+              sum = V(0);
+              ++yo;
+            } else {
+              sum += s_data[xo];
+              ++xo;
             }
           }
-          head = head || !first;
         }
-        // segmented inclusive scan of trailing sums; heads start segments
-        const unsigned long long heads = __ballot(head);
-        V v = sum;
+        head = head || !first;
+      }
+      // segmented inclusive scan of trailing sums; heads start segments
+      const unsigned long long heads = __ballot(head);
+      V v = sum;
 #pragma unroll
-        for (int dist = 1; dist < kOmega; dist <<= 1) {
-          const V t = __shfl_up(v, dist, kOmega);
-          bool take = lid >= dist;
-          if (take) {
-            const unsigned long long window = ((1ull << dist) - 1ull) << (lid - dist + 1);
-            take = (heads & window) == 0ull;
-          }
-          if (take) v += t;
+      for (int dist = 1; dist < kOmega; dist <<= 1) {
+        const V t = __shfl_up(v, dist, kOmega);
+        bool take = lid >= dist;
+        if (take) {
+          const unsigned long long window = ((1ull << dist) - 1ull) << (lid - dist + 1);
+          take = (heads & window) == 0ull;
         }
-        const V carry = __shfl_up(v, 1, kOmega);
-        const V tail = __shfl(v, kOmega - 1, kOmega);
-        if (lid == 0) {
-          // the last segment ends the tile: it belongs to the tile's end row
-          const int end_slot = (int)(tile_y[i + 1] & kRowMask) - y_bs;
-          atomicAdd(&s_y[end_slot], tail);
-        } else if (head) {
-          atomicAdd(&s_y[start_slot], carry);
-        }
+        if (take) v += t;
+      }
+      const V carry = __shfl_up(v, 1, kOmega);
+      const V tail = __shfl(v, kOmega - 1, kOmega);
+      if (lid == 0) {
+        // the last segment ends the tile: it belongs to the tile's end row
+        atomicAdd(&s_y[end_slot], tail);
+      } else if (head) {
+        atomicAdd(&s_y[start_slot], carry);
       }
     }
   }
