@@ -58,7 +58,7 @@ def load_traffic(workload: str, dtype: str):
 
 
 def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes: int,
-            alpha: float):
+            alpha: float, hot_columns: int = -1, commit: str = "auto", blocks_per_cu: int = 0):
     import numpy as np
     import torch
 
@@ -75,7 +75,8 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
     # plan build, timed on its own (kernel + allocation of TILE)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    plan = pkg.Plan(r, c, v, n, sigma=sigma, block_lanes=block_lanes, validate=False)
+    plan = pkg.Plan(r, c, v, n, sigma=sigma, block_lanes=block_lanes, hot_columns=hot_columns,
+                    commit=commit, blocks_per_cu=blocks_per_cu, validate=False)
     e1.record()
     torch.cuda.synchronize()
     plan_ms = e0.elapsed_time(e1)
@@ -140,6 +141,10 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--sigma", type=int, default=0)
     ap.add_argument("--block-lanes", type=int, default=0)
+    ap.add_argument("--hot-columns", type=int, default=-1,
+                    help="LDS x cache size in columns: -1 automatic, 0 off")
+    ap.add_argument("--commit", default="auto", choices=["auto", "block", "wave"])
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--alpha", type=float, default=0.85)
     ap.add_argument("--cpu-iters", type=int, default=15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -171,19 +176,22 @@ def main():
           f"generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
     main_run = run_gpu(w, args.dtype, args.steps, args.warmup, args.sigma, args.block_lanes,
-                       args.alpha)
+                       args.alpha, args.hot_columns, args.commit, args.blocks_per_cu)
     info = main_run["info"]
     print(f"[bench] {args.dtype}: step {main_run['step_ms'] * 1e3:.1f} us, spmv "
           f"{main_run['spmv_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
     extra = None
     if not args.no_f64 and args.dtype == "f32":
-        r64 = run_gpu(w, "f64", args.steps, args.warmup, 0, args.block_lanes, args.alpha)
+        r64 = run_gpu(w, "f64", args.steps, args.warmup, 0, args.block_lanes, args.alpha,
+                      args.hot_columns, args.commit, args.blocks_per_cu)
         extra = {
             "value": round(r64["value_gnzs"], 3), "ms_per_step": round(r64["step_ms"], 5),
             "spmv_us": round(r64["spmv_ms"] * 1e3, 2), "spmv_gnzs": round(r64["spmv_gnzs"], 3),
             "achieved_gbs": round(r64["achieved_gbs"], 1),
             "pct_hbm_peak": round(100 * r64["achieved_gbs"] / HBM_PEAK_GBS, 2),
             "plan_ms": round(r64["plan_ms"], 3), "sigma": r64["info"]["sigma"],
+            "hot_columns": r64["info"]["hot_columns"],
+            "hot_coverage": round(r64["info"]["hot_coverage"], 4),
             "traffic": load_traffic(args.workload, "f64"),
         }
         print(f"[bench] f64: step {r64['step_ms'] * 1e3:.1f} us, spmv "
@@ -207,7 +215,11 @@ def main():
         "data": "synthetic (seeded R-MAT, values 1/outdeg)",
         "config": {"workload": f"{args.workload}_pagerank", "n": info["n_rows"],
                    "nnz": info["nnz"], "sigma": info["sigma"],
-                   "block_lanes": info["block_lanes"], "alpha": args.alpha,
+                   "block_lanes": info["block_lanes"],
+                   "commit": {1: "block", 2: "wave"}[info["commit"]],
+                   "hot_columns": info["hot_columns"],
+                   "hot_coverage": round(info["hot_coverage"], 4), "grid": info["grid"],
+                   "alpha": args.alpha,
                    "seed": w["meta"].get("seed"), "x0": "1/n"},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),

@@ -44,6 +44,43 @@ typedef enum {
 
 typedef enum { MERBIT_F32 = 0, MERBIT_F64 = 1 } merbit_dtype;
 
+/* Granularity of the output commit (the paper's block size b, Sec. 4.2/4.3). */
+typedef enum {
+    MERBIT_COMMIT_AUTO = 0,  /* = MERBIT_COMMIT_WAVE                                      */
+    MERBIT_COMMIT_BLOCK = 1, /* b = block_lanes: rows are buffered for a block of b/64
+                                tiles and committed after one block barrier; only the
+                                block's first and last rows are added atomically         */
+    MERBIT_COMMIT_WAVE = 2   /* b = 64: every wavefront commits its own tile with no
+                                barrier; each tile's first and last rows are added
+                                atomically; blocks stay resident and stride over tiles  */
+} merbit_commit;
+
+/* Plan options; merbit_opts_init fills the defaults (every field 0 except
+ * hot_columns = -1 and validate = 1). */
+typedef struct {
+    int32_t sigma;         /* steps per lane; 0 = 12 (F32) / 7 (F64).  Must satisfy
+                              2 ceil(log2(64 sigma)) + sigma <= 32: 1..12 are built     */
+    int32_t block_lanes;   /* threads per block; 0 = 1024 (WAVE) / 256 (BLOCK).  Built:
+                              BLOCK 128, 256, 512, 1024; WAVE 256, 512, 1024           */
+    int32_t commit;        /* merbit_commit                                            */
+    int32_t hot_columns;   /* LDS x cache for the most frequent columns -- an addition
+                              to the paper's method: on gfx950 scattered x gathers are
+                              bounded by the L2 request rate and power-law matrices
+                              concentrate their nonzeros on few columns.  -1 = automatic
+                              (largest cache that fits one block per CU, kept only when
+                              the hot columns hold >= 20 % of the nonzeros), 0 = off,
+                              k > 0 = at most k columns (MERBIT_EUNSUPPORTED if k values
+                              do not fit in LDS).  With the cache the plan owns a
+                              recoded copy of col_ind (int32[nnz]) and each SpMV first
+                              gathers the hot x values (one small launch); the sums and
+                              their order are unchanged.                                */
+    int32_t validate;      /* nonzero: check the CSR on the device first (one host
+                              synchronisation); MERBIT_EINVAL if it is malformed        */
+    int32_t blocks_per_cu; /* resident blocks per CU for the persistent launches;
+                              0 = as many as LDS and wavefront slots allow              */
+    int32_t reserved[2];
+} merbit_opts_t;
+
 typedef struct merbit_plan merbit_plan;
 
 /* Read-only description of a plan (merbit_plan_info). */
@@ -52,14 +89,23 @@ typedef struct {
     int64_t tile_num;      /* ceil((nnz + n_rows) / (omega sigma))          Sec. 4.1.1 */
     int64_t lane_num;      /* ceil((nnz + n_rows) / sigma)                  Sec. 4.1.1 */
     int64_t fast_tiles;    /* tiles with the long-row mark (MSB of tile_y)  Sec. 4.2 (1) */
-    int64_t block_num;     /* thread blocks of one SpMV launch                          */
+    int64_t chunk_num;     /* commit units (tiles for WAVE, b / 64 tiles for BLOCK)     */
+    int32_t grid;          /* thread blocks of one fused launch                         */
+    int32_t chunks_per_block; /* chunks each block works through (1 without hot cache) */
+    int32_t hot_columns;   /* columns whose x values are served from LDS (0 = none)     */
     int32_t omega;         /* lanes per tile = wavefront size = 64                      */
     int32_t sigma;         /* merge-path steps per lane                     Sec. 4.3    */
     int32_t block_lanes;   /* lanes (threads) per block, b of Sec. 4.3                  */
     int32_t offset_bits;   /* ceil(log2(omega sigma)), width of x_offset / y_offset     */
     int32_t dtype;         /* merbit_dtype                                              */
-    int32_t lds_bytes;     /* (b sigma + 1) sizeof(value): products + partial sums      */
+    int32_t lds_bytes;     /* LDS per block: (b sigma + 1) values for products and row
+                              partial sums (Sec. 4.3) + the hot x values               */
+    int32_t commit;        /* merbit_commit of the plan                                 */
+    double hot_coverage;   /* fraction of nonzeros whose column is hot                  */
 } merbit_plan_info_t;
+
+/* Fill *opts (host pointer) with the defaults. */
+void merbit_opts_init(merbit_opts_t* opts);
 
 /* Build a reusable plan (Sec. 4.1.2, Algorithm generate_tile: merge search
  * per lane, sigma-step walk, descriptor packing, long-row tile mark).
@@ -70,21 +116,15 @@ typedef struct {
  *   values               device float[nnz] or double[nnz] per dtype (may be
  *                        replaced later with merbit_plan_set_values)
  *   dtype                MERBIT_F32 or MERBIT_F64
- *   sigma                steps per lane; 0 = default (12 for F32, 7 for F64).
- *                        Must satisfy 2 ceil(log2(64 sigma)) + sigma <= 32 and be
- *                        one of the built values 1..12.
- *   block_lanes          lanes per thread block; 0 = default 256.  Built: 128,
- *                        256, 512.
- *   validate             nonzero: check the CSR on the device first (one host
- *                        synchronisation); MERBIT_EINVAL if it is malformed.
+ *   opts                 host pointer to options, or NULL for the defaults
  *   out                  host pointer; receives the plan.  Free with
  *                        merbit_plan_destroy.
  * The plan owns TILE = {tile_x int32[T+1], tile_y uint32[T+1],
- * lane_desc uint32[lane_num]} and its work buffers. */
+ * lane_desc uint32[lane_num]} and its work buffers.  Building the hot cache
+ * synchronises `stream` (a column-count histogram is read back). */
 int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz,
                        const int32_t* row_ptr, const int32_t* col_ind, const void* values,
-                       int dtype, int sigma, int block_lanes, int validate,
-                       void* stream, merbit_plan** out);
+                       int dtype, const merbit_opts_t* opts, void* stream, merbit_plan** out);
 
 /* Replace the borrowed values pointer (same sparsity pattern, same dtype).
  * The TILE arrays depend only on row_ptr, so nothing is rebuilt. */
@@ -102,18 +142,19 @@ int merbit_plan_export(merbit_plan* plan, int32_t* tile_x, uint32_t* tile_y,
 
 /* y <- A x (Sec. 4.2, Algorithm "MERBIT SpMV"), overwriting y whatever it
  * held.  x: device [n_cols], y: device [n_rows], both of the plan's dtype, not
- * aliased.  Two launches: a scatter that zeroes y at the block-boundary rows,
- * then the fused kernel. */
+ * aliased.  Launches: a scatter that zeroes y at the first row of every commit
+ * unit, the hot-value gather (partial hot cache only), then the fused kernel. */
 int merbit_spmv(merbit_plan* plan, const void* x, void* y, void* stream);
 
-/* Dual-buffer form (Sec. 4.2, optimisation (3)): one launch.
- * Requires y to be zero at the plan's block-boundary rows on entry (true for a
- * buffer last used as `z` here, or after merbit_zero_boundary); computes
- * y <- A x and zeroes z at the same rows, so z can be the next call's y.
- * y and z: device [n_rows], distinct, not aliased with x. */
+/* Dual-buffer form (Sec. 4.2, optimisation (3)): the fused launch only (plus
+ * the hot-value gather).  Requires y to be zero at the first row of every
+ * commit unit (every tile for WAVE, every b/64 tiles for BLOCK) on entry: true
+ * for a buffer last used as `z` here, or after merbit_zero_boundary; computes
+ * y <- A x and zeroes z at the same rows, so z can be the next call's y.  y and
+ * z: device [n_rows], distinct, not aliased with x. */
 int merbit_spmv_dual(merbit_plan* plan, const void* x, void* y, void* z, void* stream);
 
-/* Zero v (device [n_rows]) at the plan's block-boundary rows. */
+/* Zero v (device [n_rows]) at the first row of every commit unit. */
 int merbit_zero_boundary(merbit_plan* plan, void* v, void* stream);
 
 /* PageRank by the power method (Sec. 5.5.1) on the plan's matrix, which must

@@ -19,7 +19,12 @@ struct merbit_plan {
   int64_t n_rows = 0, n_cols = 0, nnz = 0;
   int dtype = 0, sigma = 0, block_lanes = 0, waves = 0, bits = 0;
   int device = 0;
-  int64_t tile_num = 0, lane_num = 0, block_num = 0;
+  int commit = MERBIT_COMMIT_WAVE;  // kernel family
+  int blocks_per_cu_req = 0;
+  int64_t tile_num = 0, lane_num = 0;
+  int64_t chunk_num = 0;  // commit units
+  int unit_tiles = 1;     // tiles per commit unit: 1 (wave) or waves (block)
+  int grid = 0, chunks_per_block = 1;
   int32_t* tile_x = nullptr;
   uint32_t* tile_y = nullptr;
   uint32_t* lane_desc = nullptr;
@@ -28,6 +33,14 @@ struct merbit_plan {
   hipStream_t last_stream = nullptr;
   // small device scratch: [0] validation flags / fast-tile count
   unsigned long long* scratch = nullptr;
+  // hot-column x cache (hot_n > 0: the fused kernel reads col from colx)
+  int32_t hot_n = 0;
+  bool hot_all = false;        // every column is hot: slot = column, x itself is copied
+  int32_t* hot_cols = nullptr; // [hot_n] column of each slot (partial mode)
+  int32_t* colx = nullptr;     // [nnz] recoded column stream
+  void* x_hot = nullptr;       // [hot_n] gathered hot x values (partial mode)
+  size_t hot_lds_bytes = 0;
+  double hot_coverage = 0.0;   // fraction of nonzeros whose column is hot
   // PageRank state
   uint32_t* dmask = nullptr;
   void* ybuf[2] = {nullptr, nullptr};
@@ -66,7 +79,8 @@ static void plan_free_all(merbit_plan* p) {
   if (!p) return;
   (void)hipDeviceSynchronize();
   void* bufs[] = {p->tile_x, p->tile_y, p->lane_desc, p->scratch, p->dmask, p->ybuf[0],
-                  p->ybuf[1], p->xwork, p->partials[0], p->partials[1]};
+                  p->ybuf[1], p->xwork, p->partials[0], p->partials[1], p->hot_cols,
+                  p->colx, p->x_hot};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& ev : p->events) {
@@ -81,22 +95,29 @@ static SpmvArgs spmv_args(const merbit_plan* p, const void* x, void* y, void* z)
   a.tile_x = p->tile_x;
   a.tile_y = p->tile_y;
   a.lane_desc = p->lane_desc;
-  a.col = p->col;
+  a.col = p->hot_n > 0 ? p->colx : p->col;
   a.val = p->values;
   a.x = x;
+  a.x_hot = p->hot_n > 0 ? (p->hot_all ? x : p->x_hot) : nullptr;
   a.y = y;
   a.z = z;
   a.tile_num = (int32_t)p->tile_num;
   a.lane_num = (int32_t)p->lane_num;
   a.path_len = (int32_t)(p->nnz + p->n_rows);
   a.n_rows = (int32_t)p->n_rows;
-  a.block_num = (int32_t)p->block_num;
+  a.chunk_num = (int32_t)p->chunk_num;  // commit units of the block kernel
+  a.chunks_per_block = p->chunks_per_block;
+  a.grid = p->grid;
+  a.hot_n = p->hot_n;
   return a;
 }
 
-// Launch the fused kernel, bracketed by events when profiling is on.
+// Launch the fused kernel (after the hot gather), bracketed by events when
+// profiling is on.
 static int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st) {
-  if (p->block_num == 0) return MERBIT_OK;
+  if (p->chunk_num == 0) return MERBIT_OK;
+  if (p->hot_n > 0 && !p->hot_all)
+    HIP_TRY(launch_hot_gather(p->dtype, x, p->hot_cols, p->hot_n, p->x_hot, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (p->profiling) {
     if (p->events_used == p->events.size()) {
@@ -110,7 +131,12 @@ static int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_
     ++p->events_used;
     HIP_TRY(hipEventRecord(e0, st));
   }
-  HIP_TRY(launch_spmv(p->dtype, p->sigma, p->waves, spmv_args(p, x, y, z), st));
+  if (p->commit == MERBIT_COMMIT_WAVE)
+    HIP_TRY(launch_spmv_wave(p->dtype, p->sigma, p->waves, p->hot_n > 0, p->hot_lds_bytes,
+                             spmv_args(p, x, y, z), st));
+  else
+    HIP_TRY(launch_spmv(p->dtype, p->sigma, p->waves, p->hot_n > 0, p->hot_lds_bytes,
+                        spmv_args(p, x, y, z), st));
   if (p->profiling) HIP_TRY(hipEventRecord(e1, st));
   p->last_stream = st;
   return MERBIT_OK;
@@ -122,10 +148,181 @@ const char* merbit_last_error(void) { return g_last_error.c_str(); }
 
 const char* merbit_version(void) { return "merbit-mi355x 0.1 (gfx950, wave64)"; }
 
+// Static LDS of the fused kernel: block kernel = products + row slots of b
+// lanes plus head/tail partials; wave kernel = 64 sigma values per wavefront.
+static size_t static_lds_bytes(const merbit_plan* p) {
+  const size_t vs = vsize(p->dtype);
+  if (p->commit == MERBIT_COMMIT_WAVE) return (size_t)p->waves * kOmega * p->sigma * vs + 64;
+  return ((size_t)p->waves * kOmega * p->sigma + 1 + 2 * (size_t)p->waves) * vs + 64;
+}
+
+static bool kernel_supported(const merbit_plan* p, bool hot) {
+  return p->commit == MERBIT_COMMIT_WAVE ? spmv_wave_supported(p->dtype, p->sigma, p->waves, hot)
+                                         : spmv_supported(p->dtype, p->sigma, p->waves, hot);
+}
+
+// Choose the grid.  Block kernel: one commit unit (b lanes) per block, or with
+// the hot cache as many blocks as fit at once, each taking a run of units.
+// Wave kernel: as many resident blocks as LDS and wavefront slots allow (or
+// blocks_per_cu), every wavefront striding over the tiles.
+static int size_grid(merbit_plan* p) {
+  p->unit_tiles = p->commit == MERBIT_COMMIT_WAVE ? 1 : p->waves;
+  p->chunk_num = (p->tile_num + p->unit_tiles - 1) / p->unit_tiles;
+  p->chunks_per_block = 1;
+  p->grid = (int)((p->tile_num + p->waves - 1) / p->waves);
+  if (p->tile_num == 0) return MERBIT_OK;
+  if (p->commit != MERBIT_COMMIT_WAVE && p->hot_n == 0) return MERBIT_OK;
+  int cus = 0, lds_cu = 0;
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device));
+  HIP_TRY(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor,
+                                p->device));
+  const size_t per_block = static_lds_bytes(p) + p->hot_lds_bytes;
+  int64_t blocks_per_cu = (int64_t)lds_cu / (int64_t)per_block;
+  const int64_t wave_cap = 32 / p->waves;  // 8 wavefronts per SIMD, 4 SIMDs per CU
+  if (blocks_per_cu > wave_cap) blocks_per_cu = wave_cap;
+  if (p->blocks_per_cu_req > 0 && p->blocks_per_cu_req < blocks_per_cu)
+    blocks_per_cu = p->blocks_per_cu_req;
+  if (blocks_per_cu < 1) blocks_per_cu = 1;
+  int64_t grid = (int64_t)cus * blocks_per_cu;
+  if (p->commit == MERBIT_COMMIT_WAVE) {
+    const int64_t need = (p->tile_num + p->waves - 1) / p->waves;  // one tile per wavefront
+    p->grid = (int)(grid < need ? grid : need);
+    return MERBIT_OK;
+  }
+  if (grid > p->chunk_num) grid = p->chunk_num;
+  p->chunks_per_block = (int)((p->chunk_num + grid - 1) / grid);
+  p->grid = (int)((p->chunk_num + p->chunks_per_block - 1) / p->chunks_per_block);
+  return MERBIT_OK;
+}
+
+// Hot-column cache: pick at most `cap` most frequent columns (or every column
+// when they all fit) and recode the column stream.  `cap` < 0 picks the
+// largest cap that leaves one block per CU room for its LDS, and keeps the
+// cache only if the hot columns hold at least 20 % of the nonzeros.
+static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
+  p->hot_n = 0;
+  if (cap_req == 0 || p->nnz == 0 || p->n_cols == 0) return MERBIT_OK;
+  if (!kernel_supported(p, true))
+    return cap_req > 0 ? fail(MERBIT_EUNSUPPORTED, "hot cache not built for this block size")
+                       : MERBIT_OK;
+  int lds_block = 0;
+  HIP_TRY(hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock,
+                                p->device));
+  const size_t vs = vsize(p->dtype);
+  int64_t cap_lds = ((int64_t)lds_block - (int64_t)static_lds_bytes(p)) / (int64_t)vs;
+  cap_lds = (cap_lds / 256) * 256;
+  int64_t cap = cap_req > 0 ? cap_req : cap_lds;
+  if (cap > cap_lds) return fail(MERBIT_EUNSUPPORTED, "hot_columns exceeds the LDS budget");
+  if (cap <= 0) return MERBIT_OK;
+
+  const int64_t nc = p->n_cols;
+  if (nc <= cap) {
+    // every column fits: the slot of column c is c and x is copied as is
+    p->hot_all = true;
+    p->hot_n = (int32_t)nc;
+    p->hot_coverage = 1.0;
+  } else {
+    int32_t* counts = nullptr;
+    int32_t* hist = nullptr;
+    HIP_TRY(hipMalloc(&counts, sizeof(int32_t) * (size_t)nc));
+    HIP_TRY(hipMalloc(&hist, sizeof(int32_t) * kHotHistBins));
+    std::vector<int32_t> h(kHotHistBins);
+    hipError_t e = hot_count_columns(p->col, p->nnz, nc, counts, hist, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h.data(), hist, sizeof(int32_t) * kHotHistBins, hipMemcpyDeviceToHost,
+                         st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+      (void)hipFree(counts);
+      (void)hipFree(hist);
+      return fail_hip("hot column counts", e);
+    }
+    // smallest threshold t >= 1 with at most cap columns of count >= t
+    int64_t taken = 0;
+    double covered = 0.0;
+    int32_t t = kHotHistBins;
+    for (int b = kHotHistBins - 1; b >= 1; --b) {
+      if (taken + h[b] > cap) break;
+      taken += h[b];
+      covered += (double)b * h[b];
+      t = b;
+    }
+    p->hot_coverage = covered / (double)p->nnz;
+    const bool keep = taken > 0 && (cap_req > 0 || p->hot_coverage >= 0.2);
+    if (keep) {
+      const int nb = hot_select_blocks(nc);
+      int32_t* blk = nullptr;
+      int32_t* slot_of = nullptr;
+      std::vector<int32_t> hb(nb);
+      e = hipMalloc(&blk, sizeof(int32_t) * (size_t)nb);
+      if (e == hipSuccess) e = hipMalloc(&slot_of, sizeof(int32_t) * (size_t)nc);
+      if (e == hipSuccess) e = hipMalloc(&p->hot_cols, sizeof(int32_t) * (size_t)taken);
+      if (e == hipSuccess) e = hot_select_count(counts, nc, t, blk, st);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(hb.data(), blk, sizeof(int32_t) * (size_t)nb, hipMemcpyDeviceToHost,
+                           st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e == hipSuccess) {
+        int32_t acc = 0;
+        for (int b = 0; b < nb; ++b) {
+          const int32_t c = hb[b];
+          hb[b] = acc;
+          acc += c;
+        }
+        e = hipMemcpyAsync(blk, hb.data(), sizeof(int32_t) * (size_t)nb, hipMemcpyHostToDevice,
+                           st);
+      }
+      if (e == hipSuccess) e = hot_select_assign(counts, nc, t, blk, slot_of, p->hot_cols, st);
+      if (e == hipSuccess) e = hipMalloc(&p->colx, sizeof(int32_t) * (size_t)p->nnz);
+      if (e == hipSuccess) e = hot_recode(p->col, p->nnz, slot_of, p->colx, st);
+      if (e == hipSuccess) e = hipMalloc(&p->x_hot, vs * (size_t)taken);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      (void)hipFree(blk);
+      (void)hipFree(slot_of);
+      if (e != hipSuccess) {
+        (void)hipFree(counts);
+        (void)hipFree(hist);
+        return fail_hip("hot column selection", e);
+      }
+      p->hot_n = (int32_t)taken;
+    }
+    (void)hipFree(counts);
+    (void)hipFree(hist);
+  }
+  if (p->hot_n > 0) {
+    if (p->hot_all) {
+      // slot = column: the recoded stream is -1 - col
+      HIP_TRY(hipMalloc(&p->colx, sizeof(int32_t) * (size_t)p->nnz));
+      HIP_TRY(hot_recode(p->col, p->nnz, nullptr, p->colx, st));
+    }
+    p->hot_lds_bytes = vs * (size_t)p->hot_n;
+    if (p->commit == MERBIT_COMMIT_WAVE)
+      HIP_TRY(spmv_wave_set_hot_lds(p->dtype, p->sigma, p->waves, p->hot_lds_bytes));
+    else
+      HIP_TRY(spmv_set_hot_lds(p->dtype, p->sigma, p->waves, p->hot_lds_bytes));
+  }
+  return MERBIT_OK;
+}
+
+void merbit_opts_init(merbit_opts_t* o) {
+  if (!o) return;
+  memset(o, 0, sizeof *o);
+  o->hot_columns = -1;
+  o->validate = 1;
+}
+
 int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* row_ptr,
-                       const int32_t* col_ind, const void* values, int dtype, int sigma,
-                       int block_lanes, int validate, void* stream, merbit_plan** out) {
+                       const int32_t* col_ind, const void* values, int dtype,
+                       const merbit_opts_t* opts_in, void* stream, merbit_plan** out) {
   g_last_error.clear();
+  merbit_opts_t opts;
+  if (opts_in) opts = *opts_in;
+  else merbit_opts_init(&opts);
+  int sigma = opts.sigma, block_lanes = opts.block_lanes;
+  const int hot_columns = opts.hot_columns, validate = opts.validate;
+  int commit = opts.commit == MERBIT_COMMIT_AUTO ? MERBIT_COMMIT_WAVE : opts.commit;
+  if (commit != MERBIT_COMMIT_WAVE && commit != MERBIT_COMMIT_BLOCK)
+    return fail(MERBIT_EINVAL, "commit must be MERBIT_COMMIT_AUTO, _BLOCK or _WAVE");
   if (!out) return fail(MERBIT_EINVAL, "out is NULL");
   *out = nullptr;
   if (dtype != MERBIT_F32 && dtype != MERBIT_F64) return fail(MERBIT_EUNSUPPORTED, "dtype");
@@ -137,15 +334,19 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   if (nnz > 0 && (!col_ind || !values)) return fail(MERBIT_EINVAL, "col_ind/values NULL");
   if (nnz > 0 && n_rows == 0) return fail(MERBIT_EINVAL, "nonzeros without rows");
   if (sigma == 0) sigma = dtype == MERBIT_F32 ? 12 : 7;
-  if (block_lanes == 0) block_lanes = 256;
+  if (block_lanes == 0) block_lanes = commit == MERBIT_COMMIT_WAVE ? 1024 : 256;
   if (sigma < 1 || sigma > kMaxSigma)
     return fail(MERBIT_EUNSUPPORTED, "sigma must be in 1..12");
   const int bits = ceil_log2(kOmega * sigma);
   if (2 * bits + sigma > 32) return fail(MERBIT_EUNSUPPORTED, "descriptor exceeds 32 bits");
   if (block_lanes % kOmega != 0) return fail(MERBIT_EINVAL, "block_lanes % 64 != 0");
   const int waves = block_lanes / kOmega;
-  if (!spmv_supported(dtype, sigma, waves))
-    return fail(MERBIT_EUNSUPPORTED, "block_lanes must be 128, 256 or 512");
+  if (commit == MERBIT_COMMIT_WAVE ? !spmv_wave_supported(dtype, sigma, waves, false)
+                                   : !spmv_supported(dtype, sigma, waves, false))
+    return fail(MERBIT_EUNSUPPORTED, commit == MERBIT_COMMIT_WAVE
+                                         ? "block_lanes must be 256, 512 or 1024"
+                                         : "block_lanes must be 128, 256, 512 or 1024");
+  if (opts.blocks_per_cu < 0) return fail(MERBIT_EINVAL, "blocks_per_cu < 0");
 
   hipStream_t st = static_cast<hipStream_t>(stream);
   merbit_plan* p = new merbit_plan();
@@ -157,6 +358,8 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   p->block_lanes = block_lanes;
   p->waves = waves;
   p->bits = bits;
+  p->commit = commit;
+  p->blocks_per_cu_req = opts.blocks_per_cu;
   p->col = col_ind;
   p->values = values;
   p->last_stream = st;
@@ -164,7 +367,6 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   const int64_t L = nnz + n_rows;
   p->tile_num = (L + (int64_t)kOmega * sigma - 1) / ((int64_t)kOmega * sigma);
   p->lane_num = (L + sigma - 1) / sigma;
-  p->block_num = (p->tile_num + waves - 1) / waves;
 
   hipError_t e;
 #define CREATE_TRY(expr)                       \
@@ -217,6 +419,13 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
     CREATE_TRY(launch_plan(pa, st));
   }
 #undef CREATE_TRY
+  int rc = build_hot_cache(p, hot_columns, st);
+  if (rc == MERBIT_OK) rc = size_grid(p);
+  if (rc != MERBIT_OK) {
+    std::string msg = g_last_error;
+    plan_free_all(p);
+    return fail(rc, msg);
+  }
   *out = p;
   return MERBIT_OK;
 }
@@ -236,13 +445,18 @@ int merbit_plan_info(merbit_plan* p, merbit_plan_info_t* info) {
   info->nnz = p->nnz;
   info->tile_num = p->tile_num;
   info->lane_num = p->lane_num;
-  info->block_num = p->block_num;
+  info->chunk_num = p->chunk_num;
+  info->commit = p->commit;
+  info->grid = p->grid;
+  info->chunks_per_block = p->chunks_per_block;
+  info->hot_columns = p->hot_n;
+  info->hot_coverage = p->hot_coverage;
   info->omega = kOmega;
   info->sigma = p->sigma;
   info->block_lanes = p->block_lanes;
   info->offset_bits = p->bits;
   info->dtype = p->dtype;
-  info->lds_bytes = (int32_t)(((int64_t)p->block_lanes * p->sigma + 1) * (int64_t)vsize(p->dtype));
+  info->lds_bytes = (int32_t)(static_lds_bytes(p) + p->hot_lds_bytes);
   if (p->tile_num > 0) {
     hipStream_t st = p->last_stream;
     unsigned long long cnt = 0;
@@ -276,10 +490,10 @@ int merbit_plan_export(merbit_plan* p, int32_t* tile_x, uint32_t* tile_y, uint32
 
 int merbit_zero_boundary(merbit_plan* p, void* v, void* stream) {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
-  if (p->block_num == 0) return MERBIT_OK;
+  if (p->chunk_num == 0) return MERBIT_OK;
   if (!v) return fail(MERBIT_EINVAL, "vector is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->block_num, p->waves, v, st));
+  HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->chunk_num, p->unit_tiles, v, st));
   p->last_stream = st;
   return MERBIT_OK;
 }
@@ -290,7 +504,7 @@ int merbit_spmv(merbit_plan* p, const void* x, void* y, void* stream) {
   if (!y || (p->nnz > 0 && !x)) return fail(MERBIT_EINVAL, "x or y is NULL");
   if (x == y) return fail(MERBIT_EINVAL, "x and y alias");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->block_num, p->waves, y, st));
+  HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->chunk_num, p->unit_tiles, y, st));
   return run_fused(p, x, y, nullptr, st);
 }
 
@@ -351,7 +565,7 @@ int merbit_pagerank(merbit_plan* p, double alpha, double tol, int max_iter, int 
   int yb = p->zeroed_buf;
   if (yb < 0) {
     yb = 0;
-    HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->block_num, p->waves,
+    HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->chunk_num, p->unit_tiles,
                                  p->ybuf[0], st));
   }
   void* xs[2] = {x_inout, p->xwork};

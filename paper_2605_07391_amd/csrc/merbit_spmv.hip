@@ -26,78 +26,28 @@
 // (Sec. 4.2, opt. (3)).
 // LDS: m_b products followed by the block's row slots, at most
 // WAVES * 64 * sigma + 1 values (Sec. 4.2: a block segment has b sigma steps).
+//
+// Hot variant (HOT = true): the column stream is the plan's recoded copy in
+// which the most frequent columns are negative LDS slot numbers.  Each block
+// first copies the hot x values into LDS and then works through
+// chunks_per_block consecutive chunks of WAVES tiles (one commit unit each),
+// so the LDS copy is paid once per block; a hot nonzero reads x from LDS.
 #include "merbit_internal.hpp"
 
 namespace merbit {
 
-template <typename V>
-__device__ __forceinline__ void global_add(V* p, V v) {
-  unsafeAtomicAdd(p, v);
-}
-
-// DPP move of a 32-bit value (lanes without a source lane receive 0).
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ int dpp_i(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROW_MASK, 0xF, false);
-}
-
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_move(float v) {
-  return __builtin_bit_cast(float, dpp_i<CTRL, ROW_MASK>(__builtin_bit_cast(int, v)));
-}
-
-template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_move(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = dpp_i<CTRL, ROW_MASK>((int)(b & 0xFFFFFFFFll));
-  const int hi = dpp_i<CTRL, ROW_MASK>((int)(b >> 32));
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
-}
-
-// DPP controls (GFX9): row shift right by n within rows of 16 lanes,
-// broadcast of lane 15 / 31 of a row into the next row(s), whole-wave shift.
-constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
-constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShr1 = 0x138;
-
-// Inclusive segmented scan across the wavefront.  seg = index of the last
-// segment head at or before this lane (lane 0 is always a head).  Each step
-// adds the value from `dist` lanes below only if no head lies in between.
-template <typename V>
-__device__ __forceinline__ V wave_segmented_scan(V v, int lid, int seg) {
-  V t;
-  t = dpp_move<kRowShr1, 0xF>(v);
-  if (seg <= lid - 1) v += t;
-  t = dpp_move<kRowShr2, 0xF>(v);
-  if (seg <= lid - 2) v += t;
-  t = dpp_move<kRowShr4, 0xF>(v);
-  if (seg <= lid - 4) v += t;
-  t = dpp_move<kRowShr8, 0xF>(v);
-  if (seg <= lid - 8) v += t;
-  // rows 1 and 3 take the end of rows 0 and 2
-  t = dpp_move<kRowBcast15, 0xA>(v);
-  if ((lid & 16) && seg < (lid & ~15)) v += t;
-  // rows 2 and 3 take lane 31
-  t = dpp_move<kRowBcast31, 0xC>(v);
-  if (lid >= 32 && seg < 32) v += t;
-  return v;
-}
-
-template <typename V>
-__device__ __forceinline__ V wave_total(V v) {
-  // the segmented scan with a single head at lane 0 is a plain inclusive scan
-  v = wave_segmented_scan(v, (int)__lane_id(), 0);
-  return __shfl(v, kOmega - 1, kOmega);
-}
-
 template <typename V, int SIGMA, int WAVES>
-__global__ __launch_bounds__(WAVES * 64) void spmv_kernel(SpmvArgs a) {
+constexpr int lds_values() {
+  return WAVES * kOmega * SIGMA + 1;
+}
+
+// One commit unit: WAVES consecutive tiles starting at tile `chunk * WAVES`.
+template <typename V, int SIGMA, int WAVES, bool HOT>
+__device__ __forceinline__ void spmv_chunk(const SpmvArgs& a, int chunk, V* s_data, V* s_head,
+                                           V* s_tail, const V* s_hot) {
   constexpr int BITS = ceil_log2(kOmega * SIGMA);
   constexpr uint32_t FMASK = (1u << BITS) - 1u;
   constexpr int NT = WAVES * kOmega;
-  constexpr int LDS_N = NT * SIGMA + 1;
-  __shared__ V s_data[LDS_N];
-  __shared__ V s_head[WAVES];
-  __shared__ V s_tail[WAVES];
 
   const int32_t* __restrict__ tile_x = a.tile_x;
   const uint32_t* __restrict__ tile_y = a.tile_y;
@@ -109,7 +59,7 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_kernel(SpmvArgs a) {
   const int tid = threadIdx.x;
   const int lid = tid & (kOmega - 1);
   const int wid = __builtin_amdgcn_readfirstlane(tid / kOmega);
-  const int bs = blockIdx.x * WAVES;
+  const int bs = chunk * WAVES;
   const int be = min(bs + WAVES, a.tile_num);
 
   // block and tile bounds (prologue of Algorithm "MERBIT SpMV"); a wavefront
@@ -153,7 +103,17 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_kernel(SpmvArgs a) {
       vv[it] = __builtin_nontemporal_load(tv + k);
     }
 #pragma unroll
-    for (int it = 0; it < SIGMA; ++it) prod[it] = vv[it] * x[cc[it]];
+    for (int it = 0; it < SIGMA; ++it) {
+      const int c = cc[it];
+      if (HOT) {
+        V xv;
+        if (c >= 0) xv = x[c];
+        else xv = s_hot[-1 - c];
+        prod[it] = vv[it] * xv;
+      } else {
+        prod[it] = vv[it] * x[c];
+      }
+    }
   }
 
   V head_part = V(0), tail_part = V(0);
@@ -255,77 +215,112 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_kernel(SpmvArgs a) {
   }
 }
 
-template <typename V, int S, int W>
-static hipError_t launch_t(const SpmvArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL((spmv_kernel<V, S, W>), dim3((unsigned)a.block_num), dim3(W * kOmega), 0,
-                     st, a);
+template <typename V, int SIGMA, int WAVES, bool HOT>
+__global__ __launch_bounds__(WAVES * 64) void spmv_kernel(SpmvArgs a) {
+  __shared__ V s_data[lds_values<V, SIGMA, WAVES>()];
+  __shared__ V s_head[WAVES];
+  __shared__ V s_tail[WAVES];
+  if (!HOT) {
+    spmv_chunk<V, SIGMA, WAVES, false>(a, blockIdx.x, s_data, s_head, s_tail, nullptr);
+    return;
+  }
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  V* s_hot = reinterpret_cast<V*>(s_dyn);
+  const V* __restrict__ xh = static_cast<const V*>(a.x_hot);
+  for (int s = threadIdx.x; s < a.hot_n; s += WAVES * kOmega) s_hot[s] = xh[s];
+  const int c0 = blockIdx.x * a.chunks_per_block;
+  const int c1 = min(c0 + a.chunks_per_block, a.chunk_num);
+  for (int chunk = c0; chunk < c1; ++chunk) {
+    __syncthreads();  // hot values loaded / the previous chunk is done with LDS
+    spmv_chunk<V, SIGMA, WAVES, true>(a, chunk, s_data, s_head, s_tail, s_hot);
+  }
+}
+
+template <typename V, int S, int W, bool H>
+static hipError_t launch_t(const SpmvArgs& a, size_t dyn, hipStream_t st) {
+  hipLaunchKernelGGL((spmv_kernel<V, S, W, H>), dim3((unsigned)a.grid), dim3(W * kOmega), dyn, st,
+                     a);
   return hipGetLastError();
 }
 
-typedef hipError_t (*launch_fn)(const SpmvArgs&, hipStream_t);
+template <typename V, int S, int W, bool H>
+static hipError_t set_lds_t(size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&spmv_kernel<V, S, W, H>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
 
-template <typename V, int W>
-static launch_fn pick_sigma(int sigma) {
+struct KernelEntry {
+  hipError_t (*launch)(const SpmvArgs&, size_t, hipStream_t);
+  hipError_t (*set_lds)(size_t);
+};
+
+template <typename V, int W, bool H>
+static KernelEntry pick_sigma(int sigma) {
   switch (sigma) {
-    case 1: return launch_t<V, 1, W>;
-    case 2: return launch_t<V, 2, W>;
-    case 3: return launch_t<V, 3, W>;
-    case 4: return launch_t<V, 4, W>;
-    case 5: return launch_t<V, 5, W>;
-    case 6: return launch_t<V, 6, W>;
-    case 7: return launch_t<V, 7, W>;
-    case 8: return launch_t<V, 8, W>;
-    case 9: return launch_t<V, 9, W>;
-    case 10: return launch_t<V, 10, W>;
-    case 11: return launch_t<V, 11, W>;
-    case 12: return launch_t<V, 12, W>;
-    default: return nullptr;
+#define MERBIT_CASE(S) \
+  case S: return KernelEntry{launch_t<V, S, W, H>, set_lds_t<V, S, W, H>};
+    MERBIT_CASE(1) MERBIT_CASE(2) MERBIT_CASE(3) MERBIT_CASE(4) MERBIT_CASE(5) MERBIT_CASE(6)
+    MERBIT_CASE(7) MERBIT_CASE(8) MERBIT_CASE(9) MERBIT_CASE(10) MERBIT_CASE(11) MERBIT_CASE(12)
+#undef MERBIT_CASE
+    default: return KernelEntry{nullptr, nullptr};
   }
 }
 
-template <typename V>
-static launch_fn pick(int sigma, int waves) {
+template <typename V, bool H>
+static KernelEntry pick_waves(int sigma, int waves) {
   switch (waves) {
-    case 2: return pick_sigma<V, 2>(sigma);
-    case 4: return pick_sigma<V, 4>(sigma);
-    case 8: return pick_sigma<V, 8>(sigma);
-    default: return nullptr;
+    case 2: return H ? KernelEntry{nullptr, nullptr} : pick_sigma<V, 2, H>(sigma);
+    case 4: return pick_sigma<V, 4, H>(sigma);
+    case 8: return pick_sigma<V, 8, H>(sigma);
+    case 16: return pick_sigma<V, 16, H>(sigma);
+    default: return KernelEntry{nullptr, nullptr};
   }
 }
 
-static launch_fn pick_any(int dtype, int sigma, int waves) {
-  return dtype == 0 ? pick<float>(sigma, waves) : dtype == 1 ? pick<double>(sigma, waves)
-                                                             : nullptr;
+static KernelEntry pick_any(int dtype, int sigma, int waves, bool hot) {
+  if (dtype == 0) return hot ? pick_waves<float, true>(sigma, waves)
+                             : pick_waves<float, false>(sigma, waves);
+  if (dtype == 1) return hot ? pick_waves<double, true>(sigma, waves)
+                             : pick_waves<double, false>(sigma, waves);
+  return KernelEntry{nullptr, nullptr};
 }
 
-bool spmv_supported(int dtype, int sigma, int waves) {
-  return pick_any(dtype, sigma, waves) != nullptr;
+bool spmv_supported(int dtype, int sigma, int waves, bool hot) {
+  return pick_any(dtype, sigma, waves, hot).launch != nullptr;
 }
 
-hipError_t launch_spmv(int dtype, int sigma, int waves, const SpmvArgs& a, hipStream_t st) {
-  launch_fn f = pick_any(dtype, sigma, waves);
-  if (!f) return hipErrorInvalidValue;
-  return f(a, st);
+hipError_t launch_spmv(int dtype, int sigma, int waves, bool hot, size_t hot_lds_bytes,
+                       const SpmvArgs& a, hipStream_t st) {
+  KernelEntry k = pick_any(dtype, sigma, waves, hot);
+  if (!k.launch) return hipErrorInvalidValue;
+  return k.launch(a, hot ? hot_lds_bytes : 0, st);
 }
 
-// Zero v at every block's first row (the rows the fused kernel adds onto).
+hipError_t spmv_set_hot_lds(int dtype, int sigma, int waves, size_t bytes) {
+  KernelEntry k = pick_any(dtype, sigma, waves, true);
+  if (!k.set_lds) return hipErrorInvalidValue;
+  return k.set_lds(bytes);
+}
+
+// Zero v at the first row of every commit unit (the rows the fused kernels
+// add onto).
 template <typename V>
-__global__ void zero_boundary_kernel(const uint32_t* __restrict__ tile_y, int32_t block_num,
-                                     int32_t waves, V* __restrict__ v) {
+__global__ void zero_boundary_kernel(const uint32_t* __restrict__ tile_y, int32_t units,
+                                     int32_t unit, V* __restrict__ v) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < block_num) v[tile_y[(int64_t)k * waves] & kRowMask] = V(0);
+  if (k < units) v[tile_y[(int64_t)k * unit] & kRowMask] = V(0);
 }
 
-hipError_t launch_zero_boundary(int dtype, const uint32_t* tile_y, int32_t block_num,
-                                int32_t waves, void* v, hipStream_t st) {
-  const unsigned grid = (unsigned)((block_num + 255) / 256);
+hipError_t launch_zero_boundary(int dtype, const uint32_t* tile_y, int32_t units, int32_t unit,
+                                void* v, hipStream_t st) {
+  const unsigned grid = (unsigned)((units + 255) / 256);
   if (grid == 0) return hipSuccess;
   if (dtype == 0)
-    hipLaunchKernelGGL(zero_boundary_kernel<float>, dim3(grid), dim3(256), 0, st, tile_y,
-                       block_num, waves, static_cast<float*>(v));
+    hipLaunchKernelGGL(zero_boundary_kernel<float>, dim3(grid), dim3(256), 0, st, tile_y, units,
+                       unit, static_cast<float*>(v));
   else
-    hipLaunchKernelGGL(zero_boundary_kernel<double>, dim3(grid), dim3(256), 0, st, tile_y,
-                       block_num, waves, static_cast<double*>(v));
+    hipLaunchKernelGGL(zero_boundary_kernel<double>, dim3(grid), dim3(256), 0, st, tile_y, units,
+                       unit, static_cast<double*>(v));
   return hipGetLastError();
 }
 

@@ -1,0 +1,259 @@
+// MERBIT SpMV with one commit unit per tile (b = 64 lanes = one wavefront),
+// persistent and software pipelined, for gfx950.
+//
+// Same method as the block kernel (Sec. 4.2 of the MERBIT paper): tiles of 64
+// lanes x sigma merge-path steps, coalesced loads of values / col_ind, products
+// staged in LDS, each lane walking its descriptor, a head-flagged segmented
+// scan across the wavefront, long-row fast tiles and empty-tile skips.  The
+// paper's block size b is set to one wavefront, so wavefronts never wait for
+// each other:
+//   - rows that start and end inside a tile are complete after the tile's own
+//     scan and are stored with coalesced writes from the wavefront's LDS slots;
+//   - the tile's first row and last row may continue in neighbouring tiles and
+//     are added atomically to y, which is zero at every tile's first row before
+//     the launch (dual buffer: each tile zeroes z at its first row, Sec. 4.2
+//     opt. (3)).
+// A block of WAVES wavefronts is resident for the whole launch; wavefront g
+// of the grid takes tiles g, g + W_total, g + 2 W_total, ...  The loads of the
+// next tile (bounds, descriptor, col_ind, values) are issued before the
+// current tile's gathers are consumed, so memory stays busy while a tile is
+// walked and committed.
+//
+// HOT: the block first copies the hot x values into LDS (the plan's recoded
+// column stream marks hot columns as -1 - slot) and serves those gathers from
+// LDS.
+#include "merbit_internal.hpp"
+
+namespace merbit {
+
+template <typename V, int SIGMA>
+struct WaveTile {
+  int x_ws;
+  int x_se;
+  uint32_t tyw;
+  int y_we;
+  uint32_t desc;
+  int cc[SIGMA];
+  V vv[SIGMA];
+};
+
+template <typename V, int SIGMA>
+__device__ __forceinline__ void wave_load_tile(const SpmvArgs& a, const int32_t* __restrict__ col,
+                                               const V* __restrict__ val, int t, int lid,
+                                               WaveTile<V, SIGMA>& s) {
+  s.x_ws = a.tile_x[t];
+  s.x_se = a.tile_x[t + 1] - s.x_ws;
+  s.tyw = a.tile_y[t];
+  s.y_we = (int)(a.tile_y[t + 1] & kRowMask);
+  const bool normal = s.x_se > 0 && !(s.tyw & kFastBit);
+  s.desc = 0;
+  if (normal) s.desc = a.lane_desc[min(t * kOmega + lid, a.lane_num - 1)];
+  // A tile without nonzeros reads nothing: col / val may be empty (nnz = 0).
+  // The branch is uniform across the wavefront.
+  if (s.x_se > 0) {
+#pragma unroll
+    for (int it = 0; it < SIGMA; ++it) {
+      const int k = min(lid + it * kOmega, s.x_se - 1);
+      s.cc[it] = __builtin_nontemporal_load(col + s.x_ws + k);
+      s.vv[it] = __builtin_nontemporal_load(val + s.x_ws + k);
+    }
+  } else {
+#pragma unroll
+    for (int it = 0; it < SIGMA; ++it) {
+      s.cc[it] = 0;
+      s.vv[it] = V(0);
+    }
+  }
+}
+
+template <typename V, int SIGMA, int WAVES, bool HOT>
+__global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
+  constexpr int BITS = ceil_log2(kOmega * SIGMA);
+  constexpr uint32_t FMASK = (1u << BITS) - 1u;
+  constexpr int WLDS = kOmega * SIGMA;  // per wavefront: products, then inner-row slots
+  __shared__ V s_stage[WAVES * WLDS];
+
+  const int32_t* __restrict__ col = a.col;
+  const V* __restrict__ val = static_cast<const V*>(a.val);
+  const V* __restrict__ x = static_cast<const V*>(a.x);
+  V* __restrict__ y = static_cast<V*>(a.y);
+  V* __restrict__ z = static_cast<V*>(a.z);
+
+  const int tid = threadIdx.x;
+  const int lid = tid & (kOmega - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(tid / kOmega);
+  V* s_w = s_stage + wid * WLDS;
+
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  const V* s_hot = reinterpret_cast<const V*>(s_dyn);
+  if (HOT) {
+    V* dst = reinterpret_cast<V*>(s_dyn);
+    const V* __restrict__ xh = static_cast<const V*>(a.x_hot);
+    for (int s = tid; s < a.hot_n; s += WAVES * kOmega) dst[s] = xh[s];
+    __syncthreads();
+  }
+
+  const int stride = a.grid * WAVES;
+  int t = blockIdx.x * WAVES + wid;
+  WaveTile<V, SIGMA> cur;
+  if (t < a.tile_num) wave_load_tile<V, SIGMA>(a, col, val, t, lid, cur);
+  while (t < a.tile_num) {
+    // gathers of the current tile (none for a tile without nonzeros: x may be
+    // empty then)
+    V g[SIGMA];
+    if (cur.x_se > 0) {
+#pragma unroll
+      for (int it = 0; it < SIGMA; ++it) {
+        const int c = cur.cc[it];
+        if (HOT) {
+          if (c >= 0) g[it] = x[c];
+          else g[it] = s_hot[-1 - c];
+        } else {
+          g[it] = x[c];
+        }
+      }
+    }
+    // loads of the next tile go out before the gathers are consumed
+    const int tn = t + stride;
+    WaveTile<V, SIGMA> nxt;
+    if (tn < a.tile_num) wave_load_tile<V, SIGMA>(a, col, val, tn, lid, nxt);
+
+    const int x_se = cur.x_se;
+    const int y_ws = (int)(cur.tyw & kRowMask);
+    const int y_we = cur.y_we;
+    if (x_se == 0) {
+      // down steps only: the rows strictly inside the tile are empty
+      for (int r = y_ws + 1 + lid; r < y_we; r += kOmega) y[r] = V(0);
+    } else if (cur.tyw & kFastBit) {
+      // single-row tile (Sec. 4.2 opt. (1))
+      V acc = V(0);
+#pragma unroll
+      for (int it = 0; it < SIGMA; ++it)
+        if (lid + it * kOmega < x_se) acc += cur.vv[it] * g[it];
+      acc = wave_total(acc);
+      if (lid == 0) global_add(&y[y_ws], acc);
+    } else {
+      wave_lds_sync();  // the previous tile's commit has read its slots
+#pragma unroll
+      for (int it = 0; it < SIGMA; ++it) {
+        const int k = lid + it * kOmega;
+        if (k < x_se) s_w[k] = cur.vv[it] * g[it];
+      }
+      wave_lds_sync();
+      // walk (Algorithm tile_normal_tackle); inner row r (y_ws < r < y_we)
+      // goes to slot x_se + (r - y_ws - 1)
+      const int j = t * kOmega + lid;
+      V sum = V(0), first_sum = V(0);
+      bool has_down = false;
+      int start_off = 0;
+      if (j < a.lane_num) {
+        int xo = (int)(cur.desc & FMASK);
+        int yo = (int)((cur.desc >> BITS) & FMASK);
+        start_off = yo;
+        const uint32_t flags = cur.desc >> (2 * BITS);
+        const int steps = min(SIGMA, a.path_len - j * SIGMA);
+#pragma unroll
+        for (int k = 0; k < SIGMA; ++k) {
+          if (k < steps) {
+            if ((flags >> k) & 1u) {
+              if (has_down) s_w[x_se + yo - 1] = sum;
+              else first_sum = sum;
+              has_down = true;
+              sum = V(0);
+              ++yo;
+            } else {
+              sum += s_w[xo];
+              ++xo;
+            }
+          }
+        }
+      }
+      const unsigned long long heads = __ballot(has_down) | 1ull;
+      const unsigned long long upto = lid == kOmega - 1 ? ~0ull : ((2ull << lid) - 1ull);
+      const int seg = 63 - __builtin_clzll(heads & upto);
+      const V scan = wave_segmented_scan(sum, lid, seg);
+      const V carry = dpp_move<kWaveShr1, 0xF>(scan);
+      if (has_down) {
+        const V row_val = first_sum + (lid > 0 ? carry : V(0));
+        if (start_off == 0) global_add(&y[y_ws], row_val);  // the tile's first row
+        else s_w[x_se + start_off - 1] = row_val;           // begun inside the tile
+      }
+      // the last segment belongs to the row the tile ends in
+      if (lid == kOmega - 1 && y_we < a.n_rows && scan != V(0)) global_add(&y[y_we], scan);
+      wave_lds_sync();
+      for (int r = lid; r < y_we - y_ws - 1; r += kOmega) y[y_ws + 1 + r] = s_w[x_se + r];
+    }
+    if (z != nullptr && lid == 0) z[y_ws] = V(0);
+    if (tn >= a.tile_num) break;
+    cur = nxt;
+    t = tn;
+  }
+}
+
+template <typename V, int S, int W, bool H>
+static hipError_t launch_wave_t(const SpmvArgs& a, size_t dyn, hipStream_t st) {
+  hipLaunchKernelGGL((spmv_wave_kernel<V, S, W, H>), dim3((unsigned)a.grid), dim3(W * kOmega), dyn,
+                     st, a);
+  return hipGetLastError();
+}
+
+template <typename V, int S, int W, bool H>
+static hipError_t set_wave_lds_t(size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&spmv_wave_kernel<V, S, W, H>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+struct WaveEntry {
+  hipError_t (*launch)(const SpmvArgs&, size_t, hipStream_t);
+  hipError_t (*set_lds)(size_t);
+};
+
+template <typename V, int W, bool H>
+static WaveEntry wave_pick_sigma(int sigma) {
+  switch (sigma) {
+#define MERBIT_WCASE(S) \
+  case S: return WaveEntry{launch_wave_t<V, S, W, H>, set_wave_lds_t<V, S, W, H>};
+    MERBIT_WCASE(1) MERBIT_WCASE(2) MERBIT_WCASE(3) MERBIT_WCASE(4) MERBIT_WCASE(5)
+    MERBIT_WCASE(6) MERBIT_WCASE(7) MERBIT_WCASE(8) MERBIT_WCASE(9) MERBIT_WCASE(10)
+    MERBIT_WCASE(11) MERBIT_WCASE(12)
+#undef MERBIT_WCASE
+    default: return WaveEntry{nullptr, nullptr};
+  }
+}
+
+template <typename V, bool H>
+static WaveEntry wave_pick_waves(int sigma, int waves) {
+  switch (waves) {
+    case 4: return wave_pick_sigma<V, 4, H>(sigma);
+    case 8: return wave_pick_sigma<V, 8, H>(sigma);
+    case 16: return wave_pick_sigma<V, 16, H>(sigma);
+    default: return WaveEntry{nullptr, nullptr};
+  }
+}
+
+static WaveEntry wave_pick(int dtype, int sigma, int waves, bool hot) {
+  if (dtype == 0) return hot ? wave_pick_waves<float, true>(sigma, waves)
+                             : wave_pick_waves<float, false>(sigma, waves);
+  if (dtype == 1) return hot ? wave_pick_waves<double, true>(sigma, waves)
+                             : wave_pick_waves<double, false>(sigma, waves);
+  return WaveEntry{nullptr, nullptr};
+}
+
+bool spmv_wave_supported(int dtype, int sigma, int waves, bool hot) {
+  return wave_pick(dtype, sigma, waves, hot).launch != nullptr;
+}
+
+hipError_t launch_spmv_wave(int dtype, int sigma, int waves, bool hot, size_t hot_lds_bytes,
+                            const SpmvArgs& a, hipStream_t st) {
+  WaveEntry k = wave_pick(dtype, sigma, waves, hot);
+  if (!k.launch) return hipErrorInvalidValue;
+  return k.launch(a, hot ? hot_lds_bytes : 0, st);
+}
+
+hipError_t spmv_wave_set_hot_lds(int dtype, int sigma, int waves, size_t bytes) {
+  WaveEntry k = wave_pick(dtype, sigma, waves, true);
+  if (!k.set_lds) return hipErrorInvalidValue;
+  return k.set_lds(bytes);
+}
+
+}  // namespace merbit

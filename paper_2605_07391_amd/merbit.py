@@ -17,7 +17,7 @@ _lib = None
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, NOT_CONVERGED = 0, -1, -2, -3, -4, 1
 F32, F64 = 0, 1
-EXPORTED = ("merbit_plan_create", "merbit_plan_set_values", "merbit_plan_info",
+EXPORTED = ("merbit_opts_init", "merbit_plan_create", "merbit_plan_set_values", "merbit_plan_info",
             "merbit_plan_export", "merbit_spmv", "merbit_spmv_dual", "merbit_zero_boundary",
             "merbit_pagerank", "merbit_profile_enable", "merbit_profile_read",
             "merbit_plan_destroy", "merbit_last_error", "merbit_version")
@@ -32,10 +32,24 @@ class MerbitError(RuntimeError):
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n_rows", ctypes.c_int64), ("n_cols", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("tile_num", ctypes.c_int64), ("lane_num", ctypes.c_int64),
-                ("fast_tiles", ctypes.c_int64), ("block_num", ctypes.c_int64),
-                ("omega", ctypes.c_int32), ("sigma", ctypes.c_int32),
-                ("block_lanes", ctypes.c_int32), ("offset_bits", ctypes.c_int32),
-                ("dtype", ctypes.c_int32), ("lds_bytes", ctypes.c_int32)]
+                ("fast_tiles", ctypes.c_int64), ("chunk_num", ctypes.c_int64),
+                ("grid", ctypes.c_int32), ("chunks_per_block", ctypes.c_int32),
+                ("hot_columns", ctypes.c_int32), ("omega", ctypes.c_int32),
+                ("sigma", ctypes.c_int32), ("block_lanes", ctypes.c_int32),
+                ("offset_bits", ctypes.c_int32), ("dtype", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("commit", ctypes.c_int32),
+                ("hot_coverage", ctypes.c_double)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_int32), ("block_lanes", ctypes.c_int32),
+                ("commit", ctypes.c_int32), ("hot_columns", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
+
+
+COMMIT_AUTO, COMMIT_BLOCK, COMMIT_WAVE = 0, 1, 2
+_COMMIT = {"auto": COMMIT_AUTO, "block": COMMIT_BLOCK, "wave": COMMIT_WAVE}
 
 
 def library_path() -> str:
@@ -51,8 +65,10 @@ def load():
         raise RuntimeError(f"{_LIB_PATH} is not built (python -m paper_2605_07391_amd.build)")
     lib = ctypes.CDLL(_LIB_PATH)
     vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
-    lib.merbit_plan_create.argtypes = [i64, i64, i64, vp, vp, vp, i32, i32, i32, i32, vp,
+    lib.merbit_plan_create.argtypes = [i64, i64, i64, vp, vp, vp, i32, ctypes.POINTER(Opts), vp,
                                        ctypes.POINTER(vp)]
+    lib.merbit_opts_init.argtypes = [ctypes.POINTER(Opts)]
+    lib.merbit_opts_init.restype = None
     lib.merbit_plan_set_values.argtypes = [vp, vp]
     lib.merbit_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
     lib.merbit_plan_export.argtypes = [vp, vp, vp, vp, ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -109,7 +125,8 @@ class Plan:
     repeated y = A x.  col_ind and values are borrowed (kept referenced)."""
 
     def __init__(self, row_ptr: torch.Tensor, col_ind: torch.Tensor, values: torch.Tensor,
-                 n_cols: int, *, sigma: int = 0, block_lanes: int = 0, validate: bool = True,
+                 n_cols: int, *, sigma: int = 0, block_lanes: int = 0, hot_columns: int = -1,
+                 commit: str = "auto", blocks_per_cu: int = 0, validate: bool = True,
                  stream=None):
         lib = load()
         self.dtype = values.dtype
@@ -123,10 +140,17 @@ class Plan:
         if values.numel() != self.nnz:
             raise ValueError("values and col_ind differ in length")
         self._keep = [row_ptr, col_ind, values]
+        opts = Opts()
+        lib.merbit_opts_init(ctypes.byref(opts))
+        opts.sigma = sigma
+        opts.block_lanes = block_lanes
+        opts.commit = _COMMIT[commit]
+        opts.hot_columns = hot_columns
+        opts.validate = 1 if validate else 0
+        opts.blocks_per_cu = blocks_per_cu
         h = ctypes.c_void_p()
         _check(lib.merbit_plan_create(self.n_rows, self.n_cols, self.nnz, rp, ci, va, self._code,
-                                      sigma, block_lanes, 1 if validate else 0, _stream(stream),
-                                      ctypes.byref(h)))
+                                      ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
         self._h = h
 
     # -- lifecycle ----------------------------------------------------------

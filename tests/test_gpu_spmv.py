@@ -80,18 +80,41 @@ def test_plan_bit_exact(name, sigma):
     plan.close()
 
 
+# hot: 0 = no LDS x cache, -1 = automatic (every column fits here), 37 = a
+# partial cache of the 37 most frequent columns
+# commit: "block" = b lanes buffered per block (the paper's layout), "wave" =
+# one commit unit per tile (b = 64), persistent blocks
+CONFIGS = [(1, 256, 0, "block"), (4, 128, -1, "block"), (7, 256, 37, "block"),
+           (12, 256, -1, "block"), (12, 512, 0, "block"), (12, 1024, 37, "block"),
+           (3, 128, 0, "block"), (2, 512, 37, "block"),
+           (1, 256, 0, "wave"), (4, 256, -1, "wave"), (7, 1024, 37, "wave"),
+           (12, 1024, -1, "wave"), (12, 512, 0, "wave"), (5, 1024, -1, "wave"),
+           (12, 256, 37, "wave"), (7, 512, 0, "wave")]
+
+
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
-@pytest.mark.parametrize("sigma,block_lanes", [(1, 256), (4, 128), (7, 256), (12, 256),
-                                                 (12, 512), (7, 512), (3, 128)])
+@pytest.mark.parametrize("sigma,block_lanes,hot,commit", CONFIGS,
+                         ids=[f"s{a}b{b}h{c}{d}" for a, b, c, d in CONFIGS])
 @pytest.mark.parametrize("name", list(CASES))
-def test_spmv_parity(name, sigma, block_lanes, dtype):
+def test_spmv_parity(name, sigma, block_lanes, hot, commit, dtype):
     import paper_2605_07391_amd as pkg
     dev = require_gpu()
     rp, col, vals, nc = _matrix(name, seed=sigma)
     r, c, v = to_device(rp, col, vals, dtype, dev)
     x64 = seeded_x(nc, sigma, dtype)
     x = torch.from_numpy(x64).to(dtype).to(dev)
-    plan = pkg.Plan(r, c, v, nc, sigma=sigma, block_lanes=block_lanes)
+    plan = pkg.Plan(r, c, v, nc, sigma=sigma, block_lanes=block_lanes, hot_columns=hot,
+                    commit=commit)
+    info = plan.info()
+    assert info["commit"] == {"block": 1, "wave": 2}[commit]
+    if hot == 0 or block_lanes == 128 or len(col) == 0:
+        assert info["hot_columns"] == 0
+    elif hot == 37:
+        assert 0 < info["hot_columns"] <= 37 or nc <= 37
+    elif nc <= 4096:
+        assert info["hot_columns"] == nc  # every column fits in LDS
+    else:
+        assert 0 <= info["hot_columns"] <= nc  # partial cache within the LDS budget
     y = torch.full((len(rp) - 1,), float("nan"), dtype=dtype, device=dev)
     plan.spmv(x, out=y)
     torch.cuda.synchronize()
@@ -101,18 +124,22 @@ def test_spmv_parity(name, sigma, block_lanes, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+@pytest.mark.parametrize("commit", ["block", "wave"])
+@pytest.mark.parametrize("hot", [0, -1, 5])
 @pytest.mark.parametrize("sigma", [4, 7, 12])
-def test_rows_ending_on_lane_tile_block_boundaries(sigma, dtype):
+def test_rows_ending_on_lane_tile_block_boundaries(sigma, hot, commit, dtype):
     import paper_2605_07391_amd as pkg
     dev = require_gpu()
-    for block_lanes in (128, 256, 512):
+    sizes = (256, 512, 1024) if (hot or commit == "wave") else (128, 256, 512, 1024)
+    for block_lanes in sizes:
         lens = _boundary_rows(sigma, block_lanes)
         nc = max(lens) + 1
         rp, col, vals = graphgen.csr_from_lengths(lens, nc, seed=sigma + block_lanes)
         r, c, v = to_device(rp, col, vals, dtype, dev)
         x64 = seeded_x(nc, 3, dtype)
         x = torch.from_numpy(x64).to(dtype).to(dev)
-        plan = pkg.Plan(r, c, v, nc, sigma=sigma, block_lanes=block_lanes)
+        plan = pkg.Plan(r, c, v, nc, sigma=sigma, block_lanes=block_lanes, hot_columns=hot,
+                        commit=commit)
         tx, ty, ld = plan.export()
         ox, oy, od = oracle.plan(rp, OMEGA, sigma)
         assert np.array_equal(ty, oy) and np.array_equal(ld, od) and np.array_equal(tx, ox)
@@ -123,14 +150,16 @@ def test_rows_ending_on_lane_tile_block_boundaries(sigma, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
-def test_dual_buffer_chain(dtype):
+@pytest.mark.parametrize("commit", ["block", "wave"])
+@pytest.mark.parametrize("hot", [0, -1, 300])
+def test_dual_buffer_chain(dtype, hot, commit):
     """Alternating outputs: each call needs y zero at the boundary rows and
     leaves z zero there (Sec. 4.2, optimisation (3))."""
     import paper_2605_07391_amd as pkg
     dev = require_gpu()
     rp, col, vals, nc = _matrix("chung_lu_10k", seed=5)
     r, c, v = to_device(rp, col, vals, dtype, dev)
-    plan = pkg.Plan(r, c, v, nc)
+    plan = pkg.Plan(r, c, v, nc, hot_columns=hot, commit=commit)
     n = len(rp) - 1
     bufs = [torch.full((n,), float("nan"), dtype=dtype, device=dev) for _ in range(2)]
     plan.zero_boundary(bufs[0])
@@ -223,7 +252,10 @@ def test_profile_counts_launches():
 
 @pytest.mark.parametrize("dtype,sigma", [(torch.float32, 12), (torch.float64, 7)],
                          ids=["f32s12", "f64s7"])
-def test_rmat22_full_size(dtype, sigma):
+@pytest.mark.parametrize("hot,block_lanes,commit",
+                         [(-1, 0, "auto"), (0, 0, "wave"), (0, 0, "block"), (-1, 1024, "block")],
+                         ids=["auto", "wave_nohot", "block_nohot", "block_hot_b1024"])
+def test_rmat22_full_size(dtype, sigma, hot, block_lanes, commit):
     """R-MAT scale 22 (the benchmark matrix) at full size: plan bit exact and
     every row of y within tolerance, in the benchmark's launch configuration."""
     import paper_2605_07391_amd as pkg
@@ -231,7 +263,14 @@ def test_rmat22_full_size(dtype, sigma):
     w = workload("rmat22")
     rp, col, vals, n = w["row_ptr"], w["col"], w["values"], w["n_rows"]
     r, c, v = to_device(rp, col, vals, dtype, dev)
-    plan = pkg.Plan(r, c, v, n, sigma=sigma)
+    plan = pkg.Plan(r, c, v, n, sigma=sigma, hot_columns=hot, block_lanes=block_lanes,
+                    commit=commit)
+    info = plan.info()
+    if hot == 0:
+        assert info["hot_columns"] == 0
+    else:
+        # the most frequent columns hold well over the automatic threshold
+        assert info["hot_columns"] > 1000 and info["hot_coverage"] > 0.3
     tx, ty, ld = plan.export()
     ox, oy, od = oracle.plan(rp, OMEGA, sigma)
     assert np.array_equal(tx, ox) and np.array_equal(ty, oy) and np.array_equal(ld, od)

@@ -36,20 +36,37 @@ def test_argument_errors_without_gpu():
     lib = mb.load()
     out = ctypes.c_void_p()
     vp = ctypes.c_void_p
+
+    def opts(**kw):
+        o = mb.Opts()
+        lib.merbit_opts_init(ctypes.byref(o))
+        for k, v in kw.items():
+            setattr(o, k, v)
+        return ctypes.byref(o)
+
+    d = mb.Opts()
+    lib.merbit_opts_init(ctypes.byref(d))
+    assert (d.sigma, d.block_lanes, d.commit, d.hot_columns, d.validate) == (0, 0, 0, -1, 1)
     # NULL out pointer
-    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, 0, 0, 0, None, None) == mb.EINVAL
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, None, None, None) == mb.EINVAL
     # unsupported dtype
-    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 7, 0, 0, 0, None,
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 7, None, None,
                                   ctypes.byref(out)) == mb.EUNSUPPORTED
     # sigma 13 does not fit a 32-bit descriptor at omega = 64
-    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, 13, 0, 0, None,
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, opts(sigma=13), None,
                                   ctypes.byref(out)) == mb.EUNSUPPORTED
     assert b"sigma" in lib.merbit_last_error()
     # size limit n_rows + nnz < 2^31
-    assert lib.merbit_plan_create(1 << 30, 1, 1 << 30, vp(8), vp(8), vp(8), 0, 0, 0, 0, None,
+    assert lib.merbit_plan_create(1 << 30, 1, 1 << 30, vp(8), vp(8), vp(8), 0, None, None,
                                   ctypes.byref(out)) == mb.EINVAL
     # block size not built
-    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, 0, 192, 0, None,
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, opts(block_lanes=192), None,
+                                  ctypes.byref(out)) == mb.EUNSUPPORTED
+    # commit mode out of range; the wave kernel has no 128-lane build
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, opts(commit=7), None,
+                                  ctypes.byref(out)) == mb.EINVAL
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0,
+                                  opts(commit=2, block_lanes=128), None,
                                   ctypes.byref(out)) == mb.EUNSUPPORTED
     assert not out.value
     # calls on a NULL plan
