@@ -334,7 +334,7 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   if (nnz > 0 && (!col_ind || !values)) return fail(MERBIT_EINVAL, "col_ind/values NULL");
   if (nnz > 0 && n_rows == 0) return fail(MERBIT_EINVAL, "nonzeros without rows");
   if (sigma == 0) sigma = dtype == MERBIT_F32 ? 12 : 7;
-  if (block_lanes == 0) block_lanes = commit == MERBIT_COMMIT_WAVE ? 1024 : 256;
+  if (block_lanes == 0) block_lanes = commit == MERBIT_COMMIT_WAVE ? 512 : 256;
   if (sigma < 1 || sigma > kMaxSigma)
     return fail(MERBIT_EUNSUPPORTED, "sigma must be in 1..12");
   const int bits = ceil_log2(kOmega * sigma);
