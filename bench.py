@@ -81,25 +81,49 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
     torch.cuda.synchronize()
     plan_ms = e0.elapsed_time(e1)
     info = plan.info()
-    x = torch.full((n,), 1.0 / n, dtype=dtype, device=dev)
-    if warmup > 0:
-        plan.pagerank(x, alpha, tol=0.0, max_iter=warmup)
-    x.fill_(1.0 / n)
-    torch.cuda.synchronize()
+    pagerank = w["meta"]["generator"] != "stress"
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
-    wall0 = time.perf_counter()
-    t0.record()
-    iters, resid, _ = plan.pagerank(x, alpha, tol=0.0, max_iter=steps)
-    t1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
+    if pagerank:
+        # a step is one PageRank iteration: fused SpMV + update kernel
+        x = torch.full((n,), 1.0 / n, dtype=dtype, device=dev)
+        if warmup > 0:
+            plan.pagerank(x, alpha, tol=0.0, max_iter=warmup)
+        x.fill_(1.0 / n)
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        t0.record()
+        iters, resid, _ = plan.pagerank(x, alpha, tol=0.0, max_iter=steps)
+        t1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        mass = float(x.double().sum().item())
+        # roofline pass: same steps, fused SpMV launches bracketed by HIP events
+        x.fill_(1.0 / n)
+        plan.profile_enable(True)
+        plan.pagerank(x, alpha, tol=0.0, max_iter=steps)
+    else:
+        # a step is one y = A x with the workload's x (dual output buffers)
+        x = torch.from_numpy(w["x"]).to(dtype).to(dev)
+        ys = [torch.empty(n, dtype=dtype, device=dev) for _ in range(2)]
+        plan.zero_boundary(ys[0])
+        for k in range(warmup):
+            plan.spmv_dual(x, ys[k % 2], ys[(k + 1) % 2])
+        base = warmup
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        t0.record()
+        for k in range(steps):
+            plan.spmv_dual(x, ys[(base + k) % 2], ys[(base + k + 1) % 2])
+        t1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        iters, resid, mass = steps, None, None
+        plan.profile_enable(True)
+        base += steps
+        for k in range(steps):
+            plan.spmv_dual(x, ys[(base + k) % 2], ys[(base + k + 1) % 2])
     step_ms = t0.elapsed_time(t1) / steps
-    mass = float(x.double().sum().item())
-    # roofline pass: same steps, fused SpMV launches bracketed by HIP events
-    x.fill_(1.0 / n)
-    plan.profile_enable(True)
-    plan.pagerank(x, alpha, tol=0.0, max_iter=steps)
     launches, kernel_ms = plan.profile_read()
     plan.profile_enable(False)
     spmv_ms = kernel_ms / max(launches, 1)
@@ -116,11 +140,20 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
     }
 
 
-def cpu_baseline(w, iters: int, alpha: float):
+def cpu_baseline(w, iters: int, alpha: float, dtype_name: str = "f32"):
     import numpy as np
 
     import oracle
     n = w["n_rows"]
+    if w["meta"]["generator"] == "stress":
+        t = time.perf_counter()
+        for _ in range(iters):
+            oracle.spmv(w["row_ptr"], w["col"], w["values"], w["x"])
+        dt = time.perf_counter() - t
+        return {"value": round(w["nnz"] * iters / dt / 1e9, 5), "unit": "GNZ/s", "cores": 1,
+                "kind": "oracle",
+                "sample": f"{iters} SpMVs of the full workload matrix "
+                          f"(single-threaded C, long-double sums), {dt:.1f} s"}
     vals = w["values"].astype(np.float32).astype(np.float64)
     x0 = np.full(n, np.float32(1.0 / n), np.float64)
     t = time.perf_counter()
@@ -181,7 +214,7 @@ def main():
     print(f"[bench] {args.dtype}: step {main_run['step_ms'] * 1e3:.1f} us, spmv "
           f"{main_run['spmv_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
     extra = None
-    if not args.no_f64 and args.dtype == "f32":
+    if not args.no_f64 and args.dtype == "f32" and w["meta"]["generator"] != "stress":
         r64 = run_gpu(w, "f64", args.steps, args.warmup, 0, args.block_lanes, args.alpha,
                       args.hot_columns, args.commit, args.blocks_per_cu)
         extra = {
@@ -198,7 +231,7 @@ def main():
               f"{r64['spmv_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, args.cpu_iters, args.alpha)
+        cpu = cpu_baseline(w, args.cpu_iters, args.alpha, args.dtype)
     ach = main_run["achieved_gbs"]
     out = {
         "metric": METRIC,
@@ -212,8 +245,12 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.dtype,
-        "data": "synthetic (seeded R-MAT, values 1/outdeg)",
-        "config": {"workload": f"{args.workload}_pagerank", "n": info["n_rows"],
+        "data": ("synthetic (seeded R-MAT, values 1/outdeg)"
+                 if w["meta"]["generator"] != "stress" else
+                 "synthetic (seeded R-MAT scale 24, 30% rows cleared, 8 hub rows of 2M nnz, "
+                 "values in (0,1], x in [-1,1))"),
+        "config": {"workload": (f"{args.workload}_pagerank" if w["meta"]["generator"] != "stress"
+                                else f"{args.workload}_spmv"), "n": info["n_rows"],
                    "nnz": info["nnz"], "sigma": info["sigma"],
                    "block_lanes": info["block_lanes"],
                    "commit": {1: "block", 2: "wave"}[info["commit"]],
@@ -232,7 +269,7 @@ def main():
         "spmv_gnzs": round(main_run["spmv_gnzs"], 3),
         "plan_ms": round(main_run["plan_ms"], 3),
         "fast_tile_fraction": round(info["fast_tiles"] / max(info["tile_num"], 1), 4),
-        "rank_mass": round(main_run["mass"], 7),
+        "rank_mass": None if main_run["mass"] is None else round(main_run["mass"], 7),
         "f64": extra,
     }
     print(json.dumps(out), flush=True)

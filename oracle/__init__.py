@@ -17,6 +17,13 @@ for Iterative Workloads") it follows.  Functions and their pins:
   ``plan_replay`` reproducing ``spmv`` bit for bit.
 * ``pagerank`` (Sec. 5.5.1) -- pinned by closed-form cases, by a dense direct
   solve of the stationary equation and by the mass / contraction invariants.
+* ``spmm`` (Sec. 3.1 per column) -- pinned by dense brute force.
+* ``pagerank_teleport`` / ``personalized_pagerank`` (the power method of
+  Sec. 5.5.1 with a general teleport vector) -- pinned by a dense direct
+  solve, by closed forms and by reducing to ``pagerank`` for a uniform vector.
+* ``pagerank_multi`` (independent graphs on the diagonal of one matrix) --
+  each graph's PageRank computed on its own slice; pinned by the block
+  structure (a graph's ranks do not depend on the other graphs).
 """
 from __future__ import annotations
 
@@ -70,6 +77,11 @@ def _load():
     lib.or_plan_replay.restype = c_int
     lib.or_plan_replay.argtypes = [c_i64, c_i64, c_int, c_int, _i32, _u32, _u32, _i32, _f64,
                                    _f64, _f64, ctypes.c_void_p]
+    lib.or_spmm.restype = None
+    lib.or_spmm.argtypes = [c_i64, _i32, _i32, _f64, c_int, _f64, _f64]
+    lib.or_pagerank_teleport.restype = c_int
+    lib.or_pagerank_teleport.argtypes = [c_i64, _i32, _i32, _f64, c_dbl, c_int, _f64, _f64, _f64,
+                                         ctypes.c_void_p]
     lib.or_pagerank.restype = c_int
     lib.or_pagerank.argtypes = [c_i64, _i32, _i32, _f64, c_dbl, c_int, _f64, _f64,
                                 ctypes.c_void_p, ctypes.c_void_p]
@@ -213,3 +225,65 @@ def pagerank(row_ptr, col, values, alpha: float, iters: int, x0, *, history: boo
     if rc != 0:
         raise MemoryError("or_pagerank failed")
     return x_out[:n], resid[:iters], (hist[:iters, :n] if history else None)
+
+
+# -------------------------------------------------------------- batched --
+
+def spmm(row_ptr, col, values, X) -> np.ndarray:
+    """Y = A X for X of shape (n_cols, k) (Sec. 3.1 per column), long-double sums."""
+    row_ptr = _i32a(row_ptr)
+    X = np.ascontiguousarray(X, np.float64)
+    n = len(row_ptr) - 1
+    k = X.shape[1]
+    Y = np.empty((max(n, 1), max(k, 1)), np.float64)
+    _load().or_spmm(n, row_ptr, _i32a(col) if len(col) else np.zeros(1, np.int32),
+                    _f64a(values) if len(values) else np.zeros(1), k,
+                    X.ravel() if X.size else np.zeros(1), Y.ravel())
+    return Y[:n, :k]
+
+
+def pagerank_teleport(row_ptr, col, values, alpha: float, iters: int, v, x0):
+    """Power method x' = alpha P x + (alpha * dangling mass + 1 - alpha) v.
+    Returns (x_iters, resid[iters])."""
+    row_ptr = _i32a(row_ptr)
+    n = len(row_ptr) - 1
+    x_out = np.empty(max(n, 1), np.float64)
+    resid = np.empty(max(iters, 1), np.float64)
+    rc = _load().or_pagerank_teleport(n, row_ptr, _i32a(col) if len(col) else np.zeros(1, np.int32),
+                                      _f64a(values) if len(values) else np.zeros(1), float(alpha),
+                                      int(iters), _f64a(v), _f64a(x0), x_out,
+                                      resid.ctypes.data_as(ctypes.c_void_p))
+    if rc != 0:
+        raise MemoryError("or_pagerank_teleport failed")
+    return x_out[:n], resid[:iters]
+
+
+def personalized_pagerank(row_ptr, col, values, alpha: float, iters: int, sources):
+    """Personalised PageRank for each source s (teleport and x_0 = e_s).
+    Returns X of shape (n, len(sources))."""
+    n = len(row_ptr) - 1
+    out = np.empty((n, len(sources)), np.float64)
+    for j, s in enumerate(sources):
+        e = np.zeros(n)
+        e[s] = 1.0
+        out[:, j], _ = pagerank_teleport(row_ptr, col, values, alpha, iters, e, e)
+    return out
+
+
+def pagerank_multi(row_ptr, col, values, graph_ptr, alpha: float, iters: int, x0):
+    """PageRank (Sec. 5.5.1) of every graph on the diagonal of a block-diagonal
+    matrix: graph g owns rows and columns [graph_ptr[g], graph_ptr[g+1]).
+    Each graph is solved on its own slice with its own n, dangling set and
+    teleport."""
+    row_ptr = np.asarray(row_ptr, np.int64)
+    x = np.empty(len(row_ptr) - 1, np.float64)
+    for g in range(len(graph_ptr) - 1):
+        a, b = int(graph_ptr[g]), int(graph_ptr[g + 1])
+        lo, hi = int(row_ptr[a]), int(row_ptr[b])
+        sub_ptr = (row_ptr[a:b + 1] - lo).astype(np.int32)
+        sub_col = np.asarray(col[lo:hi], np.int64) - a
+        if len(sub_col) and (sub_col.min() < 0 or sub_col.max() >= b - a):
+            raise ValueError(f"graph {g} has a column outside its block")
+        x[a:b], _, _ = pagerank(sub_ptr, sub_col.astype(np.int32), values[lo:hi], alpha, iters,
+                                x0[a:b])
+    return x

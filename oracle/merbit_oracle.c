@@ -247,3 +247,58 @@ int or_pagerank(int64_t n, const int32_t* row_ptr, const int32_t* col, const dou
     free(xn);
     return 0;
 }
+
+/* -------------------------------------------------------- batched forms -- */
+
+/* Y = A X for k right-hand sides (Sec. 3.1 applied to every column of X):
+ * X is n_cols x k and Y is n_rows x k, both row-major.  Long-double sums. */
+void or_spmm(int64_t n_rows, const int32_t* row_ptr, const int32_t* col, const double* values,
+             int k, const double* X, double* Y) {
+    for (int64_t r = 0; r < n_rows; ++r) {
+        for (int j = 0; j < k; ++j) {
+            long double s = 0.0L;
+            for (int64_t p = row_ptr[r]; p < row_ptr[r + 1]; ++p)
+                s += (long double)values[p] * (long double)X[(int64_t)col[p] * k + j];
+            Y[r * k + j] = (double)s;
+        }
+    }
+}
+
+/* Power method with a general teleport (personalisation) vector v, sum v = 1:
+ *     x_{t+1} = alpha P x_t + (alpha sum_{u dangling} x_t[u] + 1 - alpha) v.
+ * The dangling mass follows the teleport vector.  v = 1/n gives the PageRank
+ * of Sec. 5.5.1 (or_pagerank); v = e_s gives personalised PageRank for source s.
+ * resid (optional, iters): ||x_{t+1} - x_t||_1 per step. */
+int or_pagerank_teleport(int64_t n, const int32_t* row_ptr, const int32_t* col,
+                         const double* values, double alpha, int iters, const double* v,
+                         const double* x0, double* x_out, double* resid) {
+    const int64_t m = row_ptr[n];
+    unsigned char* has_out = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    long double* x = (long double*)malloc(sizeof(long double) * (size_t)(n > 0 ? n : 1));
+    long double* xn = (long double*)malloc(sizeof(long double) * (size_t)(n > 0 ? n : 1));
+    if (!has_out || !x || !xn) { free(has_out); free(x); free(xn); return -2; }
+    for (int64_t k = 0; k < m; ++k) has_out[col[k]] = 1;
+    for (int64_t i = 0; i < n; ++i) x[i] = x0[i];
+    const long double a = alpha;
+    for (int t = 0; t < iters; ++t) {
+        long double dangling = 0.0L;
+        for (int64_t u = 0; u < n; ++u)
+            if (!has_out[u]) dangling += x[u];
+        const long double scale = a * dangling + 1.0L - a;
+        long double change = 0.0L;
+        for (int64_t r = 0; r < n; ++r) {
+            long double s = 0.0L;
+            for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k)
+                s += (long double)values[k] * x[col[k]];
+            xn[r] = a * s + scale * (long double)v[r];
+            change += fabsl(xn[r] - x[r]);
+        }
+        long double* tmp = x; x = xn; xn = tmp;
+        if (resid) resid[t] = (double)change;
+    }
+    for (int64_t r = 0; r < n; ++r) x_out[r] = (double)x[r];
+    free(has_out);
+    free(x);
+    free(xn);
+    return 0;
+}

@@ -283,3 +283,32 @@ def test_rmat22_full_size(dtype, sigma, hot, block_lanes, commit):
         torch.cuda.synchronize()
         check_spmv(y, rp, col, host_values(vals, dtype), x64, dtype, f"rmat22 x{k}")
     plan.close()
+
+
+@pytest.mark.parametrize("commit,hot", [("wave", -1), ("block", 0)], ids=["wave_hot", "block"])
+def test_stress24_fp64_full_size(commit, hot):
+    """The irregular stress matrix at full size (R-MAT scale 24, 30 % of rows
+    cleared, 8 rows of 2,000,000 nonzeros, values in (0, 1], x in [-1, 1)),
+    FP64, sigma 7: plan bit exact, every row of y within 1e-12 |A||x|.  Hub
+    rows span thousands of tiles, so their partial sums cross thousands of
+    commit units."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    w = workload("stress24")
+    rp, col, vals, n, x64 = w["row_ptr"], w["col"], w["values"], w["n_rows"], w["x"]
+    r, c, v = to_device(rp, col, vals, torch.float64, dev)
+    plan = pkg.Plan(r, c, v, n, sigma=7, commit=commit, hot_columns=hot)
+    if commit == "wave":
+        tx, ty, ld = plan.export()
+        ox, oy, od = oracle.plan(rp, OMEGA, 7)
+        assert np.array_equal(tx, ox) and np.array_equal(ty, oy) and np.array_equal(ld, od)
+        del tx, ty, ld, ox, oy, od
+    x = torch.from_numpy(x64).to(dev)
+    y = torch.full((n,), float("nan"), dtype=torch.float64, device=dev)
+    plan.spmv(x, out=y)
+    torch.cuda.synchronize()
+    check_spmv(y, rp, col, vals, x64, torch.float64, f"stress24 {commit}")
+    # a hub row is a sum of 2,000,000 products
+    hub = w["meta"]["hub_rows"][0]
+    assert rp[hub + 1] - rp[hub] == 2_000_000
+    plan.close()
