@@ -24,6 +24,13 @@ for Iterative Workloads") it follows.  Functions and their pins:
 * ``pagerank_multi`` (independent graphs on the diagonal of one matrix) --
   each graph's PageRank computed on its own slice; pinned by the block
   structure (a graph's ranks do not depend on the other graphs).
+* ``transpose`` (CSR of A^T, stable) -- pinned by dense transposes, the
+  double-transpose identity and the adjoint identity <A x, g> = <x, A^T g>.
+* ``pagerank_adjoint``, ``pagerank_value_grad``, ``colnorm`` /
+  ``colnorm_backward``, ``pagerank_loss_grad`` (the derivative of the
+  PageRank fixed point of Sec. 5.5.1 with respect to the matrix values) --
+  pinned by a dense solve of the adjoint equation and by central finite
+  differences of the oracle's own converged PageRank.
 """
 from __future__ import annotations
 
@@ -82,6 +89,10 @@ def _load():
     lib.or_pagerank_teleport.restype = c_int
     lib.or_pagerank_teleport.argtypes = [c_i64, _i32, _i32, _f64, c_dbl, c_int, _f64, _f64, _f64,
                                          ctypes.c_void_p]
+    lib.or_transpose.restype = c_int
+    lib.or_transpose.argtypes = [c_i64, c_i64, _i32, _i32, _i32, _i32, _i32]
+    lib.or_pagerank_adjoint.restype = c_int
+    lib.or_pagerank_adjoint.argtypes = [c_i64, _i32, _i32, _f64, c_dbl, c_int, _f64, _f64]
     lib.or_pagerank.restype = c_int
     lib.or_pagerank.argtypes = [c_i64, _i32, _i32, _f64, c_dbl, c_int, _f64, _f64,
                                 ctypes.c_void_p, ctypes.c_void_p]
@@ -287,3 +298,82 @@ def pagerank_multi(row_ptr, col, values, graph_ptr, alpha: float, iters: int, x0
         x[a:b], _, _ = pagerank(sub_ptr, sub_col.astype(np.int32), values[lo:hi], alpha, iters,
                                 x0[a:b])
     return x
+
+
+# ------------------------------------------------- adjoint of PageRank --
+
+def transpose(n_cols: int, row_ptr, col):
+    """CSR of A^T: (rowT_ptr, colT, perm); row c of A^T lists the nonzeros of
+    column c of A in increasing row order, perm[i] = their index in A."""
+    row_ptr = _i32a(row_ptr)
+    n = len(row_ptr) - 1
+    m = int(row_ptr[-1])
+    rowT = np.empty(n_cols + 1, np.int32)
+    colT = np.empty(max(m, 1), np.int32)
+    perm = np.empty(max(m, 1), np.int32)
+    rc = _load().or_transpose(n, int(n_cols), row_ptr, _i32a(col) if m else np.zeros(1, np.int32),
+                              rowT, colT, perm)
+    if rc != 0:
+        raise MemoryError("or_transpose failed")
+    return rowT, colT[:m], perm[:m]
+
+
+def pagerank_adjoint(row_ptr, col, values, alpha: float, iters: int, g):
+    """lambda = g + M^T lambda for the Jacobian M = alpha P + (alpha/n) 1 d^T
+    of the PageRank step (Sec. 5.5.1), by `iters` fixed-point steps from g."""
+    row_ptr = _i32a(row_ptr)
+    n = len(row_ptr) - 1
+    lam = np.empty(max(n, 1), np.float64)
+    rc = _load().or_pagerank_adjoint(n, row_ptr, _i32a(col) if len(col) else np.zeros(1, np.int32),
+                                     _f64a(values) if len(values) else np.zeros(1), float(alpha),
+                                     int(iters), _f64a(g), lam)
+    if rc != 0:
+        raise MemoryError("or_pagerank_adjoint failed")
+    return lam[:n]
+
+
+def row_index(row_ptr) -> np.ndarray:
+    """Row of every nonzero."""
+    row_ptr = np.asarray(row_ptr, np.int64)
+    return np.repeat(np.arange(len(row_ptr) - 1), np.diff(row_ptr))
+
+
+def pagerank_value_grad(row_ptr, col, lam, x, alpha: float) -> np.ndarray:
+    """dL/dP[e] = alpha lambda[row(e)] x*[col(e)] for every nonzero e = (v, u):
+    the derivative of the fixed point through the term alpha P x."""
+    return alpha * np.asarray(lam)[row_index(row_ptr)] * np.asarray(x)[np.asarray(col)]
+
+
+def colnorm(col, w, n_cols: int):
+    """P[e] = w[e] / s[col(e)], s[c] = sum of w over column c (column
+    normalisation of positive edge weights).  Returns (P, s)."""
+    col = np.asarray(col, np.int64)
+    s = np.zeros(n_cols)
+    for k in range(len(col)):
+        s[col[k]] += w[k]
+    return np.asarray(w) / s[col], s
+
+
+def colnorm_backward(col, w, G, n_cols: int) -> np.ndarray:
+    """dL/dw[e] = (G[e] - sum_{e' in col(e)} G[e'] P[e']) / s[col(e)] for
+    G = dL/dP, from differentiating P[e'] = w[e'] / s[col(e')]."""
+    col = np.asarray(col, np.int64)
+    P, s = colnorm(col, w, n_cols)
+    t = np.zeros(n_cols)
+    for k in range(len(col)):
+        t[col[k]] += G[k] * P[k]
+    return (np.asarray(G) - t[col]) / s[col]
+
+
+def pagerank_loss_grad(row_ptr, col, w, target, alpha: float, iters: int):
+    """Loss ||x*(P(w)) - target||^2 of the PageRank of the column-normalised
+    weights and its gradient with respect to w (adjoint method).  x_0 = 1/n;
+    `iters` steps for both the forward and the adjoint fixed point.
+    Returns (loss, dL/dw, x*, lambda)."""
+    n = len(row_ptr) - 1
+    P, _ = colnorm(col, w, n)
+    x, _, _ = pagerank(row_ptr, col, P, alpha, iters, np.full(n, 1.0 / n))
+    r = x - np.asarray(target)
+    lam = pagerank_adjoint(row_ptr, col, P, alpha, iters, 2.0 * r)
+    G = pagerank_value_grad(row_ptr, col, lam, x, alpha)
+    return float(r @ r), colnorm_backward(col, w, G, n), x, lam

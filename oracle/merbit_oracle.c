@@ -15,6 +15,11 @@
  *   or_plan_replay   decode TILE (Sec. 4.1.1 coordinate formula) and redo y = A x
  *   or_pagerank      power method of Sec. 5.5.1, damping alpha, dangling mass
  *                    spread uniformly
+ *   or_spmm          Sec. 3.1 applied to every column of a multi-vector
+ *   or_pagerank_teleport  the power method with a general teleport vector
+ *   or_transpose     CSR of A^T with the permutation of the nonzeros
+ *   or_pagerank_adjoint   the adjoint fixed point of the PageRank step
+ *                    (derivative of Sec. 5.5.1's iteration map)
  *
  * Conventions.  CSR: row_ptr has n_rows + 1 entries (Sec. 3.1 says "length n";
  * the algorithms read offset[y + 1], so the array has n + 1 entries), col and
@@ -300,5 +305,70 @@ int or_pagerank_teleport(int64_t n, const int32_t* row_ptr, const int32_t* col,
     free(has_out);
     free(x);
     free(xn);
+    return 0;
+}
+
+/* ---------------------------------------------- adjoint of PageRank ---- */
+
+/* CSR of the transpose A^T (n_cols rows): the nonzeros of column c of A, in
+ * increasing row order, become row c of A^T.  perm[i] is the index in A of
+ * the i-th nonzero of A^T.  One counting pass, then one placement pass in
+ * A's storage order (so the order within each row of A^T is stable). */
+int or_transpose(int64_t n_rows, int64_t n_cols, const int32_t* row_ptr, const int32_t* col,
+                 int32_t* rowT_ptr, int32_t* colT, int32_t* perm) {
+    const int64_t m = row_ptr[n_rows];
+    int64_t* next = (int64_t*)calloc((size_t)(n_cols + 1), sizeof(int64_t));
+    if (!next) return -2;
+    for (int64_t c = 0; c <= n_cols; ++c) rowT_ptr[c] = 0;
+    for (int64_t k = 0; k < m; ++k) rowT_ptr[col[k] + 1] += 1;
+    for (int64_t c = 0; c < n_cols; ++c) rowT_ptr[c + 1] += rowT_ptr[c];
+    for (int64_t c = 0; c < n_cols; ++c) next[c] = rowT_ptr[c];
+    for (int64_t r = 0; r < n_rows; ++r)
+        for (int64_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+            const int64_t pos = next[col[k]]++;
+            colT[pos] = (int32_t)r;
+            perm[pos] = (int32_t)k;
+        }
+    free(next);
+    return 0;
+}
+
+/* Adjoint of the PageRank fixed point of Sec. 5.5.1.  The step is
+ *     G(x) = alpha P x + (alpha d^T x + 1 - alpha) / n * 1,
+ * d = indicator of the dangling vertices (columns of P without nonzeros), so
+ * its Jacobian is M = alpha P + (alpha / n) 1 d^T and the adjoint vector of a
+ * loss gradient g solves lambda = g + M^T lambda, i.e.
+ *     lambda_{t+1} = g + alpha P^T lambda_t + (alpha / n) (1^T lambda_t) d.
+ * P^T lambda is formed straight from P's CSR ((P^T l)[u] = sum over the
+ * nonzeros (v, u) of P[v][u] l[v]).  Starts from lambda_0 = g; runs `iters`
+ * steps (a contraction with factor alpha in the 1-norm).  Long double. */
+int or_pagerank_adjoint(int64_t n, const int32_t* row_ptr, const int32_t* col,
+                        const double* values, double alpha, int iters, const double* g,
+                        double* lam_out) {
+    const int64_t m = row_ptr[n];
+    unsigned char* has_out = (unsigned char*)calloc((size_t)(n > 0 ? n : 1), 1);
+    long double* l = (long double*)malloc(sizeof(long double) * (size_t)(n > 0 ? n : 1));
+    long double* pt = (long double*)malloc(sizeof(long double) * (size_t)(n > 0 ? n : 1));
+    if (!has_out || !l || !pt) { free(has_out); free(l); free(pt); return -2; }
+    for (int64_t k = 0; k < m; ++k) has_out[col[k]] = 1;
+    for (int64_t i = 0; i < n; ++i) l[i] = g[i];
+    const long double a = alpha;
+    for (int t = 0; t < iters; ++t) {
+        long double total = 0.0L;
+        for (int64_t i = 0; i < n; ++i) {
+            total += l[i];
+            pt[i] = 0.0L;
+        }
+        for (int64_t v = 0; v < n; ++v)
+            for (int64_t k = row_ptr[v]; k < row_ptr[v + 1]; ++k)
+                pt[col[k]] += (long double)values[k] * l[v];
+        const long double dang = a * total / (long double)n;
+        for (int64_t u = 0; u < n; ++u)
+            l[u] = (long double)g[u] + a * pt[u] + (has_out[u] ? 0.0L : dang);
+    }
+    for (int64_t i = 0; i < n; ++i) lam_out[i] = (double)l[i];
+    free(has_out);
+    free(l);
+    free(pt);
     return 0;
 }
