@@ -25,11 +25,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "SpMV GNZ/s and % of HBM peak (FP32/FP64); batched + adjoint vs plain"
-SPMV_SRC = os.path.join(ROOT, "paper_2605_07391_amd", "csrc", "merbit_spmv.hip")
+CSRC = os.path.join(ROOT, "paper_2605_07391_amd", "csrc")
+# fused SpMV kernel of each commit family: (kernel name, source file)
+KERNELS = {1: ("merbit::spmv_kernel", "merbit_spmv.hip"),
+           2: ("merbit::spmv_wave_kernel", "merbit_spmv_wave.hip")}
 
 
-def spmv_source_hash() -> str:
-    with open(SPMV_SRC, "rb") as f:
+def spmv_source_hash(commit: int) -> str:
+    with open(os.path.join(CSRC, KERNELS[commit][1]), "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
@@ -44,21 +47,23 @@ def algorithmic_bytes(info: dict, value_size: int) -> float:
             + 4 * lanes * (1.0 - r_f))
 
 
-def load_traffic(workload: str, dtype: str):
+def load_traffic(workload: str, dtype: str, commit: int):
     """Measured HBM bytes per launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    summary, if it was taken on the current source of the same kernel."""
     path = os.path.join(ROOT, "profiles", f"spmv_traffic_{workload}_{dtype}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if rec.get("spmv_source_sha256_16") != spmv_source_hash():
+    if (not rec.get("kernel", "").startswith(KERNELS[commit][0] + "<")
+            or rec.get("spmv_source_sha256_16") != spmv_source_hash(commit)):
         return None
     return rec.get("hbm_bytes_per_launch")
 
 
 def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes: int,
-            alpha: float, hot_columns: int = -1, commit: str = "auto", blocks_per_cu: int = 0):
+            alpha: float, hot_columns: int = -1, commit: str = "auto", blocks_per_cu: int = 0,
+            tune: bool = False):
     import numpy as np
     import torch
 
@@ -72,6 +77,13 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
     c = torch.from_numpy(w["col"]).to(dev)
     v = torch.from_numpy(w["values"]).to(dtype).to(dev)
     torch.cuda.synchronize()
+    tuning = None
+    if tune:
+        # sigma and block size by measurement on this matrix (untimed)
+        best, table = pkg.tune(r, c, v, n, reps=10, commit=commit, hot_columns=hot_columns)
+        sigma, block_lanes = best["sigma"], best["block_lanes"]
+        tuning = {"best": best, "us_per_spmv": {f"s{a}_b{b}": round(t, 1)
+                                                for (a, b), t in table.items()}}
     # plan build, timed on its own (kernel + allocation of TILE)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
@@ -134,10 +146,93 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
     return {
         "iters": iters, "resid": resid, "mass": mass, "step_ms": step_ms, "wall_s": wall,
         "plan_ms": plan_ms, "spmv_ms": spmv_ms, "launches": launches, "info": info,
+        "tuning": tuning,
         "alg_bytes": abytes, "achieved_gbs": achieved,
         "value_gnzs": nnz * steps / (step_ms * steps * 1e-3) / 1e9,
         "spmv_gnzs": nnz / (spmv_ms * 1e-3) / 1e9,
     }
+
+
+def run_ppr(w, k: int, steps: int, warmup: int, alpha: float):
+    """Personalised PageRank for k sources at once on the workload graph
+    (FP32): a step is one SpMM over k right-hand sides plus the per-column
+    update.  Returns step and SpMM-kernel times."""
+    import torch
+
+    import graphgen
+    import paper_2605_07391_amd as pkg
+    dev = torch.device("cuda:0")
+    n = w["n_rows"]
+    r = torch.from_numpy(w["row_ptr"]).to(dev)
+    c = torch.from_numpy(w["col"]).to(dev)
+    v = torch.from_numpy(w["values"]).float().to(dev)
+    plan = pkg.Plan(r, c, v, n, validate=False)
+    src = graphgen.ppr_sources(n, k, seed=4)
+    X, _, _, _ = plan.pagerank_personalized(src, alpha=alpha, max_iter=max(warmup, 1))
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    X0 = torch.zeros_like(X)
+    X0[torch.as_tensor(src, dtype=torch.int64, device=dev), torch.arange(k, device=dev)] = 1.0
+    X.copy_(X0)
+    t0.record()
+    plan.pagerank_personalized(src, X=X, alpha=alpha, max_iter=steps)
+    t1.record()
+    torch.cuda.synchronize()
+    step_ms = t0.elapsed_time(t1) / steps
+    mass_err = float((X.double().sum(0) - 1.0).abs().max().item())
+    X.copy_(X0)
+    plan.profile_enable(True)
+    plan.pagerank_personalized(src, X=X, alpha=alpha, max_iter=steps)
+    launches, kernel_ms = plan.profile_read()
+    plan.close()
+    spmm_ms = kernel_ms / max(launches, 1)
+    nnz = w["nnz"]
+    return {"k": k, "steps": steps, "ms_per_step": round(step_ms, 4),
+            "spmm_us": round(spmm_ms * 1e3, 1),
+            "gnz_rhs_per_s": round(nnz * k / (spmm_ms * 1e-3) / 1e9, 2),
+            "step_gnz_rhs_per_s": round(nnz * k / (step_ms * 1e-3) / 1e9, 2),
+            "max_mass_error": mass_err, "sources_seed": 4}
+
+
+def run_multi(steps: int, warmup: int, alpha: float):
+    """PageRank of the 256 Chung-Lu graphs stored on one diagonal, FP32, one
+    plan: a step is one fused SpMV over all graphs plus the per-graph update."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2605_07391_amd as pkg
+    dev = torch.device("cuda:0")
+    w = graphgen.workload("chung_lu_multi256")
+    n, gp = w["n_rows"], w["graph_ptr"]
+    r = torch.from_numpy(w["row_ptr"]).to(dev)
+    c = torch.from_numpy(w["col"]).to(dev)
+    v = torch.from_numpy(w["values"]).float().to(dev)
+    plan = pkg.Plan(r, c, v, n, validate=False)
+    sizes = np.diff(gp)
+    x0 = torch.from_numpy(np.repeat(1.0 / sizes, sizes)).float().to(dev)
+    x = x0.clone()
+    plan.pagerank_multi(gp, x, alpha=alpha, max_iter=max(warmup, 1))
+    x.copy_(x0)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    plan.pagerank_multi(gp, x, alpha=alpha, max_iter=steps)
+    t1.record()
+    torch.cuda.synchronize()
+    step_ms = t0.elapsed_time(t1) / steps
+    x.copy_(x0)
+    plan.profile_enable(True)
+    plan.pagerank_multi(gp, x, alpha=alpha, max_iter=steps)
+    launches, kernel_ms = plan.profile_read()
+    plan.close()
+    spmv_ms = kernel_ms / max(launches, 1)
+    nnz = w["nnz"]
+    return {"graphs": len(sizes), "n": int(n), "nnz": int(nnz), "steps": steps,
+            "ms_per_step": round(step_ms, 4), "spmv_us": round(spmv_ms * 1e3, 1),
+            "gnzs": round(nnz / (step_ms * 1e-3) / 1e9, 3),
+            "spmv_gnzs": round(nnz / (spmv_ms * 1e-3) / 1e9, 3),
+            "seed": w["meta"]["seed"]}
 
 
 def cpu_baseline(w, iters: int, alpha: float, dtype_name: str = "f32"):
@@ -172,7 +267,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--sigma", type=int, default=0)
+    ap.add_argument("--sigma", type=int, default=0,
+                    help="steps per lane; 0 = chosen by the autotuner (with --block-lanes 0)")
     ap.add_argument("--block-lanes", type=int, default=0)
     ap.add_argument("--hot-columns", type=int, default=-1,
                     help="LDS x cache size in columns: -1 automatic, 0 off")
@@ -182,6 +278,11 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 companion run")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched runs (64-source PPR, 256 graphs)")
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the default sigma / block size instead of the autotuner")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times), used to "
                          "scale rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -208,15 +309,16 @@ def main():
     print(f"[bench] workload {args.workload}: n={w['n_rows']} nnz={w['nnz']} "
           f"generated in {gen_s:.1f}s", file=sys.stderr, flush=True)
 
+    tune = not args.no_tune and args.sigma == 0 and args.block_lanes == 0
     main_run = run_gpu(w, args.dtype, args.steps, args.warmup, args.sigma, args.block_lanes,
-                       args.alpha, args.hot_columns, args.commit, args.blocks_per_cu)
+                       args.alpha, args.hot_columns, args.commit, args.blocks_per_cu, tune)
     info = main_run["info"]
     print(f"[bench] {args.dtype}: step {main_run['step_ms'] * 1e3:.1f} us, spmv "
           f"{main_run['spmv_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
     extra = None
     if not args.no_f64 and args.dtype == "f32" and w["meta"]["generator"] != "stress":
         r64 = run_gpu(w, "f64", args.steps, args.warmup, 0, args.block_lanes, args.alpha,
-                      args.hot_columns, args.commit, args.blocks_per_cu)
+                      args.hot_columns, args.commit, args.blocks_per_cu, tune)
         extra = {
             "value": round(r64["value_gnzs"], 3), "ms_per_step": round(r64["step_ms"], 5),
             "spmv_us": round(r64["spmv_ms"] * 1e3, 2), "spmv_gnzs": round(r64["spmv_gnzs"], 3),
@@ -225,10 +327,22 @@ def main():
             "plan_ms": round(r64["plan_ms"], 3), "sigma": r64["info"]["sigma"],
             "hot_columns": r64["info"]["hot_columns"],
             "hot_coverage": round(r64["info"]["hot_coverage"], 4),
-            "traffic": load_traffic(args.workload, "f64"),
+            "traffic": load_traffic(args.workload, "f64", r64["info"]["commit"]),
+            "block_lanes": r64["info"]["block_lanes"], "tuning": r64["tuning"],
         }
         print(f"[bench] f64: step {r64['step_ms'] * 1e3:.1f} us, spmv "
               f"{r64['spmv_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
+    batched = None
+    if not args.no_batched and w["meta"]["generator"] == "rmat":
+        ppr = run_ppr(w, 64, args.batched_steps, 2, args.alpha)
+        ppr["vs_plain_spmv"] = round(ppr["gnz_rhs_per_s"] / main_run["spmv_gnzs"], 3)
+        print(f"[bench] ppr64: step {ppr['ms_per_step']:.3f} ms, spmm {ppr['spmm_us']:.1f} us",
+              file=sys.stderr, flush=True)
+        multi = run_multi(args.batched_steps, 2, args.alpha)
+        multi["vs_plain"] = round(multi["gnzs"] / main_run["value_gnzs"], 3)
+        print(f"[bench] multi256: step {multi['ms_per_step']:.3f} ms", file=sys.stderr,
+              flush=True)
+        batched = {"ppr64_" + args.workload + "_f32": ppr, "chung_lu_multi256_f32": multi}
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_iters, args.alpha, args.dtype)
@@ -260,8 +374,8 @@ def main():
                    "seed": w["meta"].get("seed"), "x0": "1/n"},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": load_traffic(args.workload, args.dtype),
-                     "kernel": "merbit::spmv_kernel",
+                     "traffic": load_traffic(args.workload, args.dtype, info["commit"]),
+                     "kernel": KERNELS[info["commit"]][0],
                      "alg_bytes_per_launch": int(main_run["alg_bytes"]),
                      "mean_launch_us": round(main_run["spmv_ms"] * 1e3, 2),
                      "launches_timed": main_run["launches"]},
@@ -270,7 +384,9 @@ def main():
         "plan_ms": round(main_run["plan_ms"], 3),
         "fast_tile_fraction": round(info["fast_tiles"] / max(info["tile_num"], 1), 4),
         "rank_mass": None if main_run["mass"] is None else round(main_run["mass"], 7),
+        "tuning": main_run["tuning"],
         "f64": extra,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

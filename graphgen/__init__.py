@@ -13,6 +13,11 @@ Workloads (all int32 CSR, rows = destinations, duplicates merged):
 * ``rmat<s>`` -- R-MAT with 2^s vertices, 16 * 2^s edge draws,
   (a, b, c) = (0.57, 0.19, 0.19), no noise, no relabelling.  PageRank matrix,
   values 1/outdeg.  Scale 22 uses graph seed 22.
+* ``chung_lu_multi256`` -- 256 independent Chung-Lu graphs on the diagonal of
+  one matrix (rows and columns of graph g are [graph_ptr[g], graph_ptr[g+1])).
+  Vertex counts log-uniform in [1,000, 200,000] (seed 40, stream 22), 8 edge
+  draws per vertex, exponent 2.1, 10 % empty rows; graph g uses seed 1000 + g.
+  Values 1/outdeg.  The key ``graph_ptr`` holds the offsets.
 * ``stress24`` -- R-MAT scale 24 as above (seed 24), 30 % of rows cleared,
   8 rows replaced by 2,000,000 uniformly chosen distinct columns.  Values
   uniform in (0, 1] (seed 24, stream 20), x uniform in [-1, 1) (seed 25,
@@ -138,8 +143,54 @@ class Workload(dict):
     nnz, x (float64 or None) and meta (seeds and recipe)."""
 
 
+def ppr_sources(n: int, k: int = 64, seed: int = 4) -> np.ndarray:
+    """k distinct personalised-PageRank source vertices, uniform in [0, n), sorted."""
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(n, size=k, replace=False)).astype(np.int32)
+
+
+STREAM_SIZES = 22
+
+
+def multi_graph_sizes(n_graphs: int, lo: int, hi: int, seed: int) -> np.ndarray:
+    """Vertex counts log-uniform in [lo, hi]."""
+    u = uniform(seed, STREAM_SIZES, n_graphs, np.log(lo), np.log(hi + 1.0))
+    return np.clip(np.floor(np.exp(u)), lo, hi).astype(np.int64)
+
+
+def chung_lu_multi(n_graphs: int = 256, lo: int = 1000, hi: int = 200_000, degree: int = 8,
+                   seed: int = 40, graph_seed0: int = 1000):
+    """Block-diagonal CSR of independent Chung-Lu graphs.  Returns
+    (row_ptr, col, graph_ptr); graph g's rows and columns are
+    [graph_ptr[g], graph_ptr[g+1])."""
+    sizes = multi_graph_sizes(n_graphs, lo, hi, seed)
+    graph_ptr = np.zeros(n_graphs + 1, np.int64)
+    np.cumsum(sizes, out=graph_ptr[1:])
+    parts_ptr, parts_col = [np.zeros(1, np.int64)], []
+    nnz = 0
+    for g, n in enumerate(sizes):
+        rp, cl = chung_lu_pattern(int(n), degree * int(n), 2.1, 0.1, seed=graph_seed0 + g)
+        parts_ptr.append(rp[1:].astype(np.int64) + nnz)
+        parts_col.append(cl.astype(np.int32) + np.int32(graph_ptr[g]))
+        nnz += int(rp[-1])
+    row_ptr = np.concatenate(parts_ptr)
+    if row_ptr[-1] >= 2**31:
+        raise ValueError("too many nonzeros for int32 row_ptr")
+    return row_ptr.astype(np.int32), np.concatenate(parts_col), graph_ptr
+
+
 def workload(name: str) -> Workload:
     """Build one of the named synthetic workloads (see module docstring)."""
+    if name.startswith("chung_lu_multi"):
+        count = int(name[len("chung_lu_multi"):] or 256)
+        row_ptr, col, graph_ptr = chung_lu_multi(count)
+        n = int(graph_ptr[-1])
+        vals = column_stochastic_values(col, n)
+        meta = {"generator": "chung_lu_multi", "graphs": count, "size_range": [1000, 200_000],
+                "degree": 8, "gamma_out": 2.1, "empty_frac": 0.1, "seed": 40,
+                "graph_seed0": 1000}
+        return Workload(row_ptr=row_ptr, col=col, values=vals, n_rows=n, n_cols=n,
+                        nnz=len(col), x=None, meta=meta, graph_ptr=graph_ptr)
     if name == "chung_lu_10k":
         row_ptr, col = chung_lu_pattern(10_000, 100_000, 2.1, 0.1, seed=1)
         n = 10_000

@@ -78,7 +78,10 @@ typedef struct {
                               synchronisation); MERBIT_EINVAL if it is malformed        */
     int32_t blocks_per_cu; /* resident blocks per CU for the persistent launches;
                               0 = as many as LDS and wavefront slots allow              */
-    int32_t reserved[2];
+    int32_t eager_loops;   /* 0: the PageRank drivers record each chunk of iterations
+                              between two convergence checks into a HIP graph on first
+                              use and replay it; nonzero: launch every kernel directly  */
+    int32_t reserved;
 } merbit_opts_t;
 
 typedef struct merbit_plan merbit_plan;
@@ -176,9 +179,142 @@ int merbit_pagerank(merbit_plan* plan, double alpha, double tol, int max_iter,
                     int check_every, void* x_inout, int* iters_out, double* resid_out,
                     void* stream);
 
+/* ------------------------------------------------------ batched forms -- */
+
+/* Y <- A X for k right-hand sides on the same plan (each column is the SpMV
+ * of Sec. 4.2).  X: device [n_cols][ldx] row-major (first k columns used),
+ * Y: device [n_rows][ldy] row-major, overwritten whatever it held; plan dtype;
+ * k >= 1, ldx >= k, ldy >= k; X and Y not aliased.  One wavefront walks one
+ * tile of the merge path and its 64 lanes carry 64 columns, so every X access
+ * is one coalesced row read; k > 64 runs in slabs of 64 columns.  Launches: a
+ * scatter that zeroes Y at every tile's first row, then the SpMM kernel. */
+int merbit_spmm(merbit_plan* plan, const void* X, int64_t ldx, void* Y, int64_t ldy, int k,
+                void* stream);
+
+/* Dual-buffer SpMM: Y must be zero at every tile's first row (columns 0..k-1)
+ * on entry; Z (same shape rules) is zeroed at those rows for the next call. */
+int merbit_spmm_dual(merbit_plan* plan, const void* X, int64_t ldx, void* Y, int64_t ldy,
+                     void* Z, int64_t ldz, int k, void* stream);
+
+/* Zero columns 0..k-1 of Y at every tile's first row. */
+int merbit_spmm_zero_boundary(merbit_plan* plan, void* Y, int64_t ldy, int k, void* stream);
+
+/* Personalised PageRank for k sources at once (1 <= k <= 64), on the plan's
+ * column-stochastic matrix (rows = destinations).  Column j is the power
+ * method of Sec. 5.5.1 with teleport vector e_{sources[j]}; the dangling mass
+ * follows the teleport vector:
+ *     X'[:, j] = alpha P X[:, j] + (alpha sum_{u dangling} X[u, j] + 1 - alpha) e_{s_j}.
+ *   sources    host int32[k], each in [0, n)
+ *   X_inout    device [n][k] row-major, plan dtype: initial vectors in (for
+ *              example e_{s_j}), ranks out
+ *   tol        stop when every column's ||X' - X||_1 < tol, tested every
+ *              check_every iterations; tol <= 0 runs exactly max_iter
+ *   iters_out  host, optional; resid_out host double[k], optional: last l1
+ *              change per column
+ * Returns MERBIT_OK or MERBIT_NOT_CONVERGED; synchronises `stream`. */
+int merbit_pagerank_personalized(merbit_plan* plan, double alpha, double tol, int max_iter,
+                                 int check_every, const int32_t* sources, int k, void* X_inout,
+                                 int* iters_out, double* resid_out, void* stream);
+
+/* PageRank of many graphs stored on the diagonal of one matrix, all solved by
+ * one plan: graph g owns rows and columns [graph_ptr[g], graph_ptr[g+1]) of
+ * the plan's column-stochastic matrix (rows = destinations), and each step is
+ * the power method of Sec. 5.5.1 on every graph at once, with the graph's own
+ * size n_g, dangling mass and uniform teleport:
+ *     x'[r] = alpha (P x)[r] + (alpha sum_{u in g dangling} x[u] + 1 - alpha) / n_g.
+ * One fused SpMV covers all graphs (the merge path balances work across them);
+ * the per-graph sums are deterministic segment reductions.
+ *   graph_ptr  host int64[n_graphs + 1]: 0 = graph_ptr[0] < ... <
+ *              graph_ptr[n_graphs] = n (no empty graph).  Nonzeros outside
+ *              their row's graph are not checked for; they couple graphs.
+ *   x_inout    device [n], plan dtype: x_0 in (e.g. 1/n_g on graph g), ranks out
+ *   tol        stop when every graph's ||x' - x||_1 (over its rows) < tol,
+ *              tested every check_every iterations; tol <= 0 runs max_iter
+ *   resid_out  host double[n_graphs], optional: last l1 change per graph
+ * Returns MERBIT_OK or MERBIT_NOT_CONVERGED; synchronises `stream`. */
+int merbit_pagerank_multi(merbit_plan* plan, const int64_t* graph_ptr, int n_graphs,
+                          double alpha, double tol, int max_iter, int check_every, void* x_inout,
+                          int* iters_out, double* resid_out, void* stream);
+
+/* ------------------------------------------- adjoint (differentiation) -- */
+/* Pieces for differentiating PageRank (Sec. 5.5.1) with respect to the
+ * matrix values.  With x* the fixed point of G(x) = alpha P x +
+ * (alpha d^T x + 1 - alpha)/n 1 (d = dangling indicator) and a loss L(x*)
+ * with gradient g = dL/dx*, the adjoint vector solves
+ *     lambda = g + alpha P^T lambda + (alpha / n) (1^T lambda) d
+ * and dL/dP[e] = alpha lambda[row(e)] x*[col(e)] for every nonzero e. */
+
+/* CSR of the transpose of the plan's matrix, for a second plan that runs
+ * P^T lambda with the same merge-path kernels.  Outputs (device, caller
+ * owned): rowT_ptr int32[n_cols + 1], colT int32[nnz], perm int32[nnz], where
+ * row c of A^T lists the nonzeros of column c of A in increasing row order
+ * and perm[i] is the index in A of the i-th nonzero of A^T (so A^T's values
+ * are values[perm[i]], see merbit_gather_values).  Rows of the nonzeros come
+ * from the plan's descriptors; the order is a stable radix sort by column,
+ * so the result is deterministic.  Allocates and frees temporary device
+ * memory (about 12 bytes per nonzero plus the sort's workspace); synchronises
+ * `stream`. */
+int merbit_transpose(merbit_plan* plan, int32_t* rowT_ptr, int32_t* colT, int32_t* perm,
+                     void* stream);
+
+/* Per-nonzero product on the plan's pattern: out[e] = scale g[row(e)]
+ * x[col(e)] (device, plan dtype: g[n_rows], x[n_cols], out[nnz], in the plan's
+ * nonzero order).  With g = lambda, x = x*, scale = alpha this is dL/dP. */
+int merbit_sddmm(merbit_plan* plan, const void* g, const void* x, double scale, void* out,
+                 void* stream);
+
+/* dst[i] = src[perm[i]] (times src2[perm[i]] when src2 is not NULL); device
+ * arrays of nnz values of `dtype` (merbit_dtype).  dst must not alias src or
+ * src2. */
+int merbit_gather_values(int dtype, int64_t nnz, const int32_t* perm, const void* src,
+                         const void* src2, void* dst, void* stream);
+
+/* out[e] = (a[e] - t[col[e]]) / s[col[e]] (t may be NULL: out = a / s[col]);
+ * device arrays, `dtype` values.  With a = w and s = column sums of w this is
+ * the column normalisation P = w / colsum(w); with a = dL/dP and t[c] = sum
+ * over column c of dL/dP[e] P[e] it is the derivative dL/dw. */
+int merbit_column_scale(int dtype, int64_t nnz, const int32_t* col, const void* a, const void* t,
+                        const void* s, void* out, void* stream);
+
+/* Adjoint fixed point: lambda <- g + alpha P^T lambda + (alpha/n) (1^T lambda) d,
+ * iterated from lambda_in (e.g. a copy of g).  `plan` is P's plan (square;
+ * its dangling mask gives d), `plan_t` the plan of P^T built from
+ * merbit_transpose's output with values[perm] (same dtype; its SpMV does
+ * P^T lambda).  g, lambda_inout: device [n], plan dtype, not aliased.
+ * Stops when ||lambda' - lambda||_1 < tol (tested every check_every
+ * iterations) or after max_iter; tol <= 0 runs exactly max_iter.  Uses
+ * plan_t's iteration buffers (not concurrently with PageRank on plan_t).
+ * Returns MERBIT_OK or MERBIT_NOT_CONVERGED; synchronises `stream`. */
+int merbit_pagerank_adjoint(merbit_plan* plan, merbit_plan* plan_t, double alpha, double tol,
+                            int max_iter, int check_every, const void* g, void* lambda_inout,
+                            int* iters_out, double* resid_out, void* stream);
+
+/* ------------------------------------------------------------ autotuner -- */
+
+/* Choose sigma (steps per lane) and block_lanes for one matrix by measurement,
+ * the sweep of Sec. 4.3 / Sec. 5.3 (the paper tunes sigma per precision).  For
+ * every candidate pair a plan is built from the given CSR (device pointers as
+ * in merbit_plan_create; validation off), the dual-buffer SpMV is launched
+ * 2 + reps times on `stream` with a constant nonzero x, and the mean time of
+ * the last reps launches is taken.
+ *   sigmas, n_sigmas      host int32 candidates; NULL or n <= 0 = 7..12 (F32),
+ *                         4..10 (F64)
+ *   block_lanes, n_blocks host int32 candidates; NULL or n <= 0 = 256, 512, 1024
+ *   opts_inout            host: base options in (commit, hot_columns, ...);
+ *                         the best sigma and block_lanes out
+ *   us_out                host float[n_sigmas * n_blocks], optional: mean
+ *                         microseconds per launch, row-major by sigma; -1 for a
+ *                         candidate the kernels do not build
+ * Allocates and frees its own buffers; synchronises `stream`.  Returns
+ * MERBIT_EUNSUPPORTED if no candidate is built. */
+int merbit_tune(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* row_ptr,
+                const int32_t* col_ind, const void* values, int dtype, const int32_t* sigmas,
+                int n_sigmas, const int32_t* block_lanes, int n_blocks, int reps,
+                merbit_opts_t* opts_inout, float* us_out, void* stream);
+
 /* Kernel timing for the SpMV launches of this plan.  While enabled, every
  * fused SpMV launch (from merbit_spmv, merbit_spmv_dual and merbit_pagerank)
- * is bracketed by HIP events on its stream.  merbit_profile_read (synchronous)
+ * and every SpMM slab launch is bracketed by HIP events on its stream.  merbit_profile_read (synchronous)
  * returns the number of timed launches and their summed duration in ms, then
  * clears the record.  Host pointers. */
 int merbit_profile_enable(merbit_plan* plan, int enable);

@@ -1,0 +1,122 @@
+"""Differentiable PageRank on a fixed sparsity pattern (torch.autograd).
+
+The forward pass is the power method of Sec. 5.5.1 (``Plan.pagerank``) on the
+column-normalised edge weights P = w / colsum(w).  The backward pass never
+stores iterates: it solves the adjoint fixed point
+
+    lambda = dL/dx* + alpha P^T lambda + (alpha / n) (1^T lambda) d
+
+with the merge-path SpMV of a second plan built on the transpose of the
+pattern (``Plan.transpose``), forms dL/dP[e] = alpha lambda[row] x*[col] with
+a per-nonzero kernel, and differentiates the column normalisation with a
+gather through the transpose's permutation, a transposed SpMV (column sums)
+and a column scaling.  Every step is a kernel of libmerbit.so; torch provides
+the tensors and the autograd graph only.
+"""
+from __future__ import annotations
+
+import torch
+
+from .merbit import Plan, column_scale, gather_values
+
+
+class DiffPageRank:
+    """Plans and buffers for PageRank of column-normalised weights on one
+    pattern (CSR rows = destinations, columns = sources).
+
+    alpha, tol, max_iter, check_every apply to the forward power method;
+    adj_tol / adj_max_iter to the adjoint fixed point (defaults: the same).
+    """
+
+    def __init__(self, row_ptr: torch.Tensor, col_ind: torch.Tensor, n: int, *,
+                 dtype=torch.float32, alpha: float = 0.85, tol: float = 0.0,
+                 max_iter: int = 100, check_every: int = 10, adj_tol: float | None = None,
+                 adj_max_iter: int | None = None, sigma: int = 0, stream=None):
+        dev = col_ind.device
+        self.n = int(n)
+        self.nnz = col_ind.numel()
+        self.dtype = dtype
+        self.alpha, self.tol, self.max_iter, self.check_every = alpha, tol, max_iter, check_every
+        self.adj_tol = tol if adj_tol is None else adj_tol
+        self.adj_max_iter = max_iter if adj_max_iter is None else adj_max_iter
+        self.stream = stream
+        self.col = col_ind
+        self.values = torch.zeros(self.nnz, dtype=dtype, device=dev)  # P, persistent
+        self.plan = Plan(row_ptr, col_ind, self.values, n, sigma=sigma, stream=stream)
+        self.row_t, self.col_t, self.perm = self.plan.transpose(stream=stream)
+        self.values_t = torch.zeros(self.nnz, dtype=dtype, device=dev)  # P^T, persistent
+        self.plan_t = Plan(self.row_t, self.col_t, self.values_t, n, sigma=sigma, stream=stream)
+        self.ones = torch.ones(n, dtype=dtype, device=dev)
+        self.x0 = torch.full((n,), 1.0 / n, dtype=dtype, device=dev)
+        self.last_forward = None   # (iterations, l1 change) of the last forward solve
+        self.last_adjoint = None
+
+    # column sums over the pattern's columns of per-nonzero values a[e] (times
+    # b[e]): the transpose's SpMV with a vector of ones
+    def _column_sums(self, a: torch.Tensor, b: torch.Tensor | None = None) -> torch.Tensor:
+        gather_values(self.perm, a, b, out=self.values_t, stream=self.stream)
+        return self.plan_t.spmv(self.ones, stream=self.stream)
+
+    def colnorm(self, w: torch.Tensor) -> torch.Tensor:
+        return _ColumnNormalize.apply(w, self)
+
+    def pagerank(self, P: torch.Tensor) -> torch.Tensor:
+        return _PageRank.apply(P, self)
+
+    def __call__(self, w: torch.Tensor) -> torch.Tensor:
+        """x*(colnorm(w))."""
+        return self.pagerank(self.colnorm(w))
+
+    def close(self):
+        self.plan.close()
+        self.plan_t.close()
+
+
+class _ColumnNormalize(torch.autograd.Function):
+    """P[e] = w[e] / s[col(e)], s = column sums of w."""
+
+    @staticmethod
+    def forward(ctx, w, op: DiffPageRank):
+        w = w.detach().contiguous()
+        s = op._column_sums(w)
+        P = column_scale(op.col, w, s, stream=op.stream)
+        ctx.op = op
+        ctx.save_for_backward(P, s)
+        return P
+
+    @staticmethod
+    def backward(ctx, G):
+        op = ctx.op
+        P, s = ctx.saved_tensors
+        G = G.contiguous().to(op.dtype)
+        t = op._column_sums(G, P)            # t[c] = sum over column c of G[e] P[e]
+        return column_scale(op.col, G, s, t, stream=op.stream), None
+
+
+class _PageRank(torch.autograd.Function):
+    """x* = fixed point of x -> alpha P x + (alpha d^T x + 1 - alpha) / n."""
+
+    @staticmethod
+    def forward(ctx, P, op: DiffPageRank):
+        P = P.detach().contiguous()
+        op.values.copy_(P)
+        x = op.x0.clone()
+        it, res, _ = op.plan.pagerank(x, op.alpha, op.tol, op.max_iter, op.check_every,
+                                      stream=op.stream)
+        op.last_forward = (it, res)
+        ctx.op = op
+        ctx.save_for_backward(P, x)
+        return x
+
+    @staticmethod
+    def backward(ctx, gx):
+        op = ctx.op
+        P, x = ctx.saved_tensors
+        gx = gx.contiguous().to(op.dtype)
+        gather_values(op.perm, P, out=op.values_t, stream=op.stream)   # P^T's values
+        lam = gx.clone()
+        it, res, _ = op.plan.pagerank_adjoint(op.plan_t, gx, lam, op.alpha, op.adj_tol,
+                                              op.adj_max_iter, op.check_every,
+                                              stream=op.stream)
+        op.last_adjoint = (it, res)
+        return op.plan.sddmm(lam, x, op.alpha, stream=op.stream), None

@@ -1,0 +1,409 @@
+// Batched forms on the same plan: Y = A X for up to 64 right-hand sides at
+// once, the per-column PageRank update for personalised PageRank, and the
+// per-graph PageRank update for many graphs stored on the diagonal of one
+// matrix.
+//
+// SpMM (one wavefront per tile, lanes = right-hand-side columns).  The
+// tile's merge-path segment (Sec. 4.1) fixes its nonzeros [x_ws, x_we) and
+// rows [y_ws, y_we]; every nonzero is a 64-wide row operation
+// Y[row, :] += v * X[col, :], so each X access is one coalesced row load.
+//   1. col_ind / values of the tile are staged in LDS with coalesced loads;
+//   2. each lane decodes its 32-bit descriptor (Sec. 4.1.1) and writes, for
+//      each of its right steps, the row (relative to the tile) of that
+//      nonzero: nonzero x_off + r of lane j lies in row y_off + (downs before
+//      it) -- no scan is needed;
+//   3. the wavefront walks the tile's nonzeros in order, with the X rows of
+//      the next kChunk nonzeros in flight while the current ones are summed;
+//      a change of row finishes the previous one.
+// Rows strictly inside the tile are stored; the tile's first and last rows
+// (shared with neighbouring tiles) are added atomically to Y, which is zero
+// there before the launch.  Empty rows inside the tile are written as 0.
+#include "merbit_internal.hpp"
+
+namespace merbit {
+
+constexpr int kSpmmWaves = 4;
+constexpr int kChunk = 16;
+
+template <typename V>
+__device__ __forceinline__ void spmm_commit(V* Y, int64_t ld, int row_abs, int rel, int last_rel,
+                                            int n_rows, V acc, bool lane_on, int lid) {
+  if (!lane_on) return;
+  V* p = Y + (int64_t)row_abs * ld + lid;
+  if (rel == 0 || rel == last_rel) {
+    if (row_abs < n_rows) global_add(p, acc);  // shared with a neighbouring tile
+  } else {
+    *p = acc;
+  }
+}
+
+template <typename V, int SIGMA>
+__global__ __launch_bounds__(kSpmmWaves * 64) void spmm_kernel(SpmmArgs a) {
+  constexpr int WLDS = kOmega * SIGMA;
+  __shared__ int32_t s_col[kSpmmWaves * WLDS];
+  __shared__ V s_val[kSpmmWaves * WLDS];
+  __shared__ int32_t s_row[kSpmmWaves * WLDS];
+
+  const int lid = threadIdx.x & (kOmega - 1);
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kOmega);
+  const int t = blockIdx.x * kSpmmWaves + wid;
+  if (t >= a.tile_num) return;  // no block-wide synchronisation in this kernel
+  int32_t* wcol = s_col + wid * WLDS;
+  V* wval = s_val + wid * WLDS;
+  int32_t* wrow = s_row + wid * WLDS;
+
+  const V* __restrict__ X = static_cast<const V*>(a.X);
+  V* __restrict__ Y = static_cast<V*>(a.Y);
+  const bool lane_on = lid < a.k;
+  const int x_ws = a.tile_x[t];
+  const int x_se = a.tile_x[t + 1] - x_ws;
+  const uint32_t tyw = a.tile_y[t];
+  const int y_ws = (int)(tyw & kRowMask);
+  const int y_we = (int)(a.tile_y[t + 1] & kRowMask);
+  const int last_rel = y_we - y_ws;
+
+  if (x_se > 0) {
+    const int32_t* __restrict__ tc = a.col + x_ws;
+    const V* __restrict__ tv = static_cast<const V*>(a.val) + x_ws;
+    for (int q = lid; q < x_se; q += kOmega) {
+      wcol[q] = __builtin_nontemporal_load(tc + q);
+      wval[q] = __builtin_nontemporal_load(tv + q);
+    }
+  }
+  tile_nz_rows<SIGMA>(a.lane_desc, a.lane_num, a.path_len, t, tyw, x_se, lid, wrow);
+  wave_lds_sync();
+
+  // walk the nonzeros in order; X rows of a chunk are loaded before use
+  V acc = V(0);
+  int cur = 0;  // current row, relative to y_ws
+  const int64_t ldx = a.ldx, ldy = a.ldy;
+  for (int q0 = 0; q0 < x_se; q0 += kChunk) {
+    V xr[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int q = min(q0 + u, x_se - 1);
+      xr[u] = lane_on ? X[(int64_t)wcol[q] * ldx + lid] : V(0);
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int q = q0 + u;
+      if (q < x_se) {
+        const int r = wrow[q];
+        if (r != cur) {
+          spmm_commit(Y, ldy, y_ws + cur, cur, last_rel, a.n_rows, acc, lane_on, lid);
+          for (int e = cur + 1; e < r; ++e)  // empty rows strictly inside the tile
+            if (lane_on) Y[(int64_t)(y_ws + e) * ldy + lid] = V(0);
+          cur = r;
+          acc = V(0);
+        }
+        acc += wval[q] * xr[u];
+      }
+    }
+  }
+  if (x_se > 0) spmm_commit(Y, ldy, y_ws + cur, cur, last_rel, a.n_rows, acc, lane_on, lid);
+  // rows after the last nonzero and strictly inside the tile are empty
+  for (int e = (x_se > 0 ? cur + 1 : 1); e < last_rel; ++e)
+    if (lane_on) Y[(int64_t)(y_ws + e) * ldy + lid] = V(0);
+  if (a.Z != nullptr && lane_on)
+    static_cast<V*>(a.Z)[(int64_t)y_ws * a.ldz + lid] = V(0);
+}
+
+template <typename V, int S>
+static hipError_t spmm_launch_t(const SpmmArgs& a, hipStream_t st) {
+  const unsigned grid = (unsigned)((a.tile_num + kSpmmWaves - 1) / kSpmmWaves);
+  hipLaunchKernelGGL((spmm_kernel<V, S>), dim3(grid), dim3(kSpmmWaves * 64), 0, st, a);
+  return hipGetLastError();
+}
+
+typedef hipError_t (*spmm_fn)(const SpmmArgs&, hipStream_t);
+
+template <typename V>
+static spmm_fn spmm_pick(int sigma) {
+  switch (sigma) {
+#define MERBIT_MCASE(S) \
+  case S: return spmm_launch_t<V, S>;
+    MERBIT_MCASE(1) MERBIT_MCASE(2) MERBIT_MCASE(3) MERBIT_MCASE(4) MERBIT_MCASE(5)
+    MERBIT_MCASE(6) MERBIT_MCASE(7) MERBIT_MCASE(8) MERBIT_MCASE(9) MERBIT_MCASE(10)
+    MERBIT_MCASE(11) MERBIT_MCASE(12)
+#undef MERBIT_MCASE
+    default: return nullptr;
+  }
+}
+
+hipError_t launch_spmm(int dtype, int sigma, const SpmmArgs& a, hipStream_t st) {
+  if (a.tile_num == 0) return hipSuccess;
+  spmm_fn f = dtype == 0 ? spmm_pick<float>(sigma) : spmm_pick<double>(sigma);
+  if (!f) return hipErrorInvalidValue;
+  return f(a, st);
+}
+
+// Zero Y[tile_y[t], col0 .. col0 + k) for every tile t (the rows the SpMM adds onto).
+template <typename V>
+__global__ void spmm_zero_kernel(const uint32_t* __restrict__ tile_y, int32_t tile_num, V* Y,
+                                 int64_t ld, int k) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = e / 64, j = e % 64;
+  if (t < tile_num && j < k) Y[(int64_t)(tile_y[t] & kRowMask) * ld + j] = V(0);
+}
+
+hipError_t launch_spmm_zero(int dtype, const uint32_t* tile_y, int32_t tile_num, void* Y,
+                            int64_t ld, int k, hipStream_t st) {
+  if (tile_num == 0) return hipSuccess;
+  const unsigned grid = (unsigned)(((int64_t)tile_num * 64 + 255) / 256);
+  if (dtype == 0)
+    hipLaunchKernelGGL(spmm_zero_kernel<float>, dim3(grid), dim3(256), 0, st, tile_y, tile_num,
+                       static_cast<float*>(Y), ld, k);
+  else
+    hipLaunchKernelGGL(spmm_zero_kernel<double>, dim3(grid), dim3(256), 0, st, tile_y, tile_num,
+                       static_cast<double*>(Y), ld, k);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------- personalised PageRank step --
+//
+// Column j of X is the rank vector of source src[j]:
+//   X'[r, j] = alpha Y[r, j] + (r == src[j]) (alpha delta_j + 1 - alpha),
+// with delta_j the dangling mass of column j.  Every block writes, per column,
+// its part of the next dangling mass and of the l1 change; a small kernel
+// sums those parts in block order (deterministic) for the next step and the
+// host.  Threads are laid out so that thread t always handles column t % 64.
+
+constexpr int kPprThreads = 256;
+
+template <typename V>
+__global__ __launch_bounds__(kPprThreads) void ppr_update_kernel(
+    const V* __restrict__ Y, const V* __restrict__ X_old, V* __restrict__ X_new,
+    const uint32_t* __restrict__ dmask, int64_t n, int k, double alpha,
+    const int32_t* __restrict__ src, const double* __restrict__ delta_in,
+    double* __restrict__ part_out) {
+  __shared__ double s_d[kPprThreads], s_r[kPprThreads];
+  const int j = threadIdx.x & 63;
+  const int rsub = threadIdx.x >> 6;  // 4 rows per block iteration
+  const bool on = j < k;
+  const V a = (V)alpha;
+  double dsum = 0.0, rsum = 0.0;
+  const int sj = on ? src[j] : -1;
+  const V tele = on ? (V)(alpha * delta_in[2 * j] + 1.0 - alpha) : V(0);
+  for (int64_t r = (int64_t)blockIdx.x * 4 + rsub; r < n; r += (int64_t)gridDim.x * 4) {
+    if (!on) continue;
+    const int64_t e = r * k + j;
+    V xn = a * Y[e];
+    if (r == sj) xn += tele;
+    X_new[e] = xn;
+    rsum += fabs((double)xn - (double)X_old[e]);
+    if ((dmask[r >> 5] >> (r & 31)) & 1u) dsum += (double)xn;
+  }
+  s_d[threadIdx.x] = dsum;
+  s_r[threadIdx.x] = rsum;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double d = 0.0, rr = 0.0;
+    for (int w = 0; w < kPprThreads / 64; ++w) {
+      d += s_d[w * 64 + threadIdx.x];
+      rr += s_r[w * 64 + threadIdx.x];
+    }
+    part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2] = d;
+    part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2 + 1] = rr;
+  }
+}
+
+// dangling mass of X (per column) -> the same per-block part layout
+template <typename V>
+__global__ __launch_bounds__(kPprThreads) void ppr_dangling_kernel(
+    const V* __restrict__ X, const uint32_t* __restrict__ dmask, int64_t n, int k,
+    double* __restrict__ part_out) {
+  __shared__ double s_d[kPprThreads];
+  const int j = threadIdx.x & 63;
+  const int rsub = threadIdx.x >> 6;
+  double dsum = 0.0;
+  if (j < k)
+    for (int64_t r = (int64_t)blockIdx.x * 4 + rsub; r < n; r += (int64_t)gridDim.x * 4)
+      if ((dmask[r >> 5] >> (r & 31)) & 1u) dsum += (double)X[r * k + j];
+  s_d[threadIdx.x] = dsum;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double d = 0.0;
+    for (int w = 0; w < kPprThreads / 64; ++w) d += s_d[w * 64 + threadIdx.x];
+    part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2] = d;
+    part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2 + 1] = 0.0;
+  }
+}
+
+// sums[j] = (sum over blocks of part[b][j][0], ... [1]), block order
+__global__ void ppr_sum_parts_kernel(const double* __restrict__ part, int nblocks,
+                                     double* __restrict__ sums) {
+  const int j = threadIdx.x;  // 64 threads
+  double d = 0.0, r = 0.0;
+  for (int b = 0; b < nblocks; ++b) {
+    d += part[((int64_t)b * 64 + j) * 2];
+    r += part[((int64_t)b * 64 + j) * 2 + 1];
+  }
+  sums[2 * j] = d;
+  sums[2 * j + 1] = r;
+}
+
+int ppr_grid(int64_t n) {
+  int64_t g = (n + 4 * 16 - 1) / (4 * 16);
+  if (g > 512) g = 512;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_ppr_dangling(int dtype, const void* X, const uint32_t* dmask, int64_t n, int k,
+                               double* part, double* sums, int grid, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(ppr_dangling_kernel<float>, dim3(grid), dim3(kPprThreads), 0, st,
+                       static_cast<const float*>(X), dmask, n, k, part);
+  else
+    hipLaunchKernelGGL(ppr_dangling_kernel<double>, dim3(grid), dim3(kPprThreads), 0, st,
+                       static_cast<const double*>(X), dmask, n, k, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(ppr_sum_parts_kernel, dim3(1), dim3(64), 0, st, part, grid, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_ppr_update(int dtype, const void* Y, const void* X_old, void* X_new,
+                             const uint32_t* dmask, int64_t n, int k, double alpha,
+                             const int32_t* src, const double* sums_in, double* part,
+                             double* sums_out, int grid, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(ppr_update_kernel<float>, dim3(grid), dim3(kPprThreads), 0, st,
+                       static_cast<const float*>(Y), static_cast<const float*>(X_old),
+                       static_cast<float*>(X_new), dmask, n, k, alpha, src, sums_in, part);
+  else
+    hipLaunchKernelGGL(ppr_update_kernel<double>, dim3(grid), dim3(kPprThreads), 0, st,
+                       static_cast<const double*>(Y), static_cast<const double*>(X_old),
+                       static_cast<double*>(X_new), dmask, n, k, alpha, src, sums_in, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(ppr_sum_parts_kernel, dim3(1), dim3(64), 0, st, part, grid, sums_out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ PageRank of many graphs --
+//
+// The graphs lie on the diagonal of one matrix: graph g owns rows and columns
+// [gp[g], gp[g+1]), and its step is the PageRank step of Sec. 5.5.1 with its
+// own size, dangling mass and teleport:
+//   x'[r] = alpha y[r] + (alpha delta_g + 1 - alpha) / n_g   for r in graph g.
+// Rows are cut into chunks of at most kMultiRows rows that never cross a
+// graph; chunk c is rows [chunk_row[c], chunk_row[c+1]) of graph
+// chunk_graph[c], and graph g's chunks are chunk_ptr[g] .. chunk_ptr[g+1]-1.
+// One block per chunk writes the chunk's (dangling mass, l1 change) pair; a
+// second kernel adds each graph's pairs in chunk order (deterministic).
+
+constexpr int kMultiILP = 4;
+constexpr int kMultiRows = kReduceThreads * kMultiILP;
+
+int multi_chunk_rows() { return kMultiRows; }
+
+template <typename V>
+__global__ __launch_bounds__(kReduceThreads) void multi_update_kernel(
+    const V* __restrict__ y, const V* __restrict__ x_old, V* __restrict__ x_new,
+    const uint32_t* __restrict__ dmask, const int32_t* __restrict__ chunk_row,
+    const int32_t* __restrict__ chunk_graph, const double* __restrict__ gsum_in,
+    const double* __restrict__ gsize, double alpha, double* __restrict__ part_out) {
+  const int c = blockIdx.x;
+  const int64_t r0 = chunk_row[c], r1 = chunk_row[c + 1];
+  const int g = chunk_graph[c];
+  const V tele = (V)((alpha * gsum_in[2 * g] + 1.0 - alpha) / gsize[g]);
+  const V a = (V)alpha;
+  V yv[kMultiILP], xo[kMultiILP];
+  uint32_t mw[kMultiILP];
+#pragma unroll
+  for (int u = 0; u < kMultiILP; ++u) {
+    const int64_t i = min(r0 + threadIdx.x + (int64_t)u * kReduceThreads, r1 - 1);
+    yv[u] = y[i];
+    xo[u] = x_old[i];
+    mw[u] = dmask[i >> 5];
+  }
+  double dsum = 0.0, rsum = 0.0;
+#pragma unroll
+  for (int u = 0; u < kMultiILP; ++u) {
+    const int64_t i = r0 + threadIdx.x + (int64_t)u * kReduceThreads;
+    if (i < r1) {
+      const V xn = a * yv[u] + tele;
+      x_new[i] = xn;
+      rsum += fabs((double)xn - (double)xo[u]);
+      if ((mw[u] >> (i & 31)) & 1u) dsum += (double)xn;
+    }
+  }
+  block_sum2(dsum, rsum);
+  if (threadIdx.x == 0) {
+    part_out[2 * c] = dsum;
+    part_out[2 * c + 1] = rsum;
+  }
+}
+
+template <typename V>
+__global__ __launch_bounds__(kReduceThreads) void multi_dangling_kernel(
+    const V* __restrict__ x, const uint32_t* __restrict__ dmask,
+    const int32_t* __restrict__ chunk_row, double* __restrict__ part_out) {
+  const int c = blockIdx.x;
+  const int64_t r0 = chunk_row[c], r1 = chunk_row[c + 1];
+  double dsum = 0.0, zero = 0.0;
+  for (int64_t i = r0 + threadIdx.x; i < r1; i += kReduceThreads)
+    if ((dmask[i >> 5] >> (i & 31)) & 1u) dsum += (double)x[i];
+  block_sum2(dsum, zero);
+  if (threadIdx.x == 0) {
+    part_out[2 * c] = dsum;
+    part_out[2 * c + 1] = 0.0;
+  }
+}
+
+__global__ void multi_sum_kernel(const double* __restrict__ part,
+                                 const int32_t* __restrict__ chunk_ptr, int n_graphs,
+                                 double* __restrict__ gsum_out) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n_graphs) return;
+  double d = 0.0, r = 0.0;
+  for (int c = chunk_ptr[g]; c < chunk_ptr[g + 1]; ++c) {
+    d += part[2 * c];
+    r += part[2 * c + 1];
+  }
+  gsum_out[2 * g] = d;
+  gsum_out[2 * g + 1] = r;
+}
+
+static hipError_t launch_multi_sum(const double* part, const int32_t* chunk_ptr, int n_graphs,
+                                   double* gsum_out, hipStream_t st) {
+  hipLaunchKernelGGL(multi_sum_kernel, dim3((unsigned)((n_graphs + 255) / 256)), dim3(256), 0,
+                     st, part, chunk_ptr, n_graphs, gsum_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_multi_dangling(int dtype, const void* x, const uint32_t* dmask,
+                                 const MultiTables& mt, double* gsum_out, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(multi_dangling_kernel<float>, dim3((unsigned)mt.n_chunks),
+                       dim3(kReduceThreads), 0, st, static_cast<const float*>(x), dmask,
+                       mt.chunk_row, mt.part);
+  else
+    hipLaunchKernelGGL(multi_dangling_kernel<double>, dim3((unsigned)mt.n_chunks),
+                       dim3(kReduceThreads), 0, st, static_cast<const double*>(x), dmask,
+                       mt.chunk_row, mt.part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_multi_sum(mt.part, mt.chunk_ptr, mt.n_graphs, gsum_out, st);
+}
+
+hipError_t launch_multi_update(int dtype, const void* y, const void* x_old, void* x_new,
+                               const uint32_t* dmask, const MultiTables& mt, double alpha,
+                               const double* gsum_in, double* gsum_out, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(multi_update_kernel<float>, dim3((unsigned)mt.n_chunks),
+                       dim3(kReduceThreads), 0, st, static_cast<const float*>(y),
+                       static_cast<const float*>(x_old), static_cast<float*>(x_new), dmask,
+                       mt.chunk_row, mt.chunk_graph, gsum_in, mt.gsize, alpha, mt.part);
+  else
+    hipLaunchKernelGGL(multi_update_kernel<double>, dim3((unsigned)mt.n_chunks),
+                       dim3(kReduceThreads), 0, st, static_cast<const double*>(y),
+                       static_cast<const double*>(x_old), static_cast<double*>(x_new), dmask,
+                       mt.chunk_row, mt.chunk_graph, gsum_in, mt.gsize, alpha, mt.part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_multi_sum(mt.part, mt.chunk_ptr, mt.n_graphs, gsum_out, st);
+}
+
+}  // namespace merbit

@@ -100,6 +100,65 @@ __device__ __forceinline__ V wave_total(V v) {
 #endif
 
 // -------------------------------------------------------------- launchers --
+// Row of each nonzero of tile t, relative to the tile's first row, into
+// wrow[0 .. x_se) (LDS of one wavefront).  Lane j replays its descriptor
+// (Sec. 4.1.1): its k-th right step is nonzero x_off + (right steps before it)
+// of the tile and lies in row y_off + (down steps before it).  A long-row tile
+// has one row.  The caller synchronises the wavefront before reading wrow.
+template <int SIGMA>
+__device__ __forceinline__ void tile_nz_rows(const uint32_t* __restrict__ lane_desc,
+                                             int lane_num, int path_len, int t, uint32_t tyw,
+                                             int x_se, int lid, int32_t* wrow) {
+  constexpr int BITS = ceil_log2(kOmega * SIGMA);
+  constexpr uint32_t FMASK = (1u << BITS) - 1u;
+  if (x_se <= 0) return;
+  if (tyw & kFastBit) {
+    for (int q = lid; q < x_se; q += kOmega) wrow[q] = 0;
+    return;
+  }
+  const int j = t * kOmega + lid;
+  if (j >= lane_num) return;
+  const uint32_t d = lane_desc[j];
+  int xo = (int)(d & FMASK);
+  int yo = (int)((d >> BITS) & FMASK);
+  const uint32_t flags = d >> (2 * BITS);
+  const int steps = min(SIGMA, path_len - j * SIGMA);
+  for (int k = 0; k < steps; ++k) {
+    if ((flags >> k) & 1u) {
+      ++yo;
+    } else {
+      wrow[xo] = yo;
+      ++xo;
+    }
+  }
+}
+
+// Threads per block of the reduction kernels.
+constexpr int kReduceThreads = 256;
+
+// Sum (a, b) over the block in a fixed order; thread 0 gets the totals.
+__device__ __forceinline__ void block_sum2(double& a, double& b) {
+  __shared__ double sa[kReduceThreads / kOmega], sb[kReduceThreads / kOmega];
+  const int tid = threadIdx.x, lid = tid & (kOmega - 1), wid = tid / kOmega;
+  a = wave_sum(a);
+  b = wave_sum(b);
+  __syncthreads();  // sa/sb may still be read from a previous call
+  if (lid == 0) {
+    sa[wid] = a;
+    sb[wid] = b;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double ta = 0.0, tb = 0.0;
+    for (int w = 0; w < kReduceThreads / kOmega; ++w) {
+      ta += sa[w];
+      tb += sb[w];
+    }
+    a = ta;
+    b = tb;
+  }
+}
+
 struct PlanArgs {
   const int32_t* row_ptr;
   int32_t n_rows;
@@ -131,6 +190,23 @@ struct SpmvArgs {
   int32_t chunks_per_block;
   int32_t grid;
   int32_t hot_n;
+};
+
+struct SpmmArgs {
+  const int32_t* tile_x;
+  const uint32_t* tile_y;
+  const uint32_t* lane_desc;
+  const int32_t* col;
+  const void* val;
+  const void* X;   // first column of the slab; row stride ldx
+  void* Y;         // row stride ldy
+  void* Z;         // dual buffer (row stride ldz) cleared at tile starts, or nullptr
+  int64_t ldx, ldy, ldz;
+  int32_t k;       // columns in this slab, 1..64
+  int32_t tile_num;
+  int32_t lane_num;
+  int32_t path_len;
+  int32_t n_rows;
 };
 
 // CSR checks; *flags gets bit 0: row_ptr[0] != 0, bit 1: row_ptr[n] != nnz,
@@ -180,5 +256,63 @@ hipError_t launch_pr_update(int dtype, const void* y, const void* x_old, void* x
                             const double* partials_in, int n_in, double* partials_out, int grid,
                             hipStream_t st);
 int pr_reduce_grid(int64_t n);
+
+// Adjoint pieces.
+struct TileRowsArgs {
+  const int32_t* tile_x;
+  const uint32_t* tile_y;
+  const uint32_t* lane_desc;
+  int32_t tile_num, lane_num, path_len;
+  const int32_t* col;
+  const void* g;    // SDDMM: per-row factor
+  const void* x;    // SDDMM: per-column factor
+  double scale;
+  void* out;        // SDDMM: per-nonzero output
+  int32_t* rows;    // row of every nonzero (row decode)
+};
+hipError_t launch_tile_rows(int dtype, int sigma, bool sddmm, const TileRowsArgs& a,
+                            hipStream_t st);
+hipError_t transpose_sort_bytes(int64_t m, int end_bit, size_t* bytes);
+hipError_t launch_transpose(const int32_t* col, const int32_t* rows, int64_t m, int64_t n_cols,
+                            int end_bit, void* sort_tmp, size_t sort_bytes, uint32_t* keys_out,
+                            int32_t* iota, int32_t* rowT, int32_t* colT, int32_t* perm,
+                            hipStream_t st);
+hipError_t launch_gather_values(int dtype, const int32_t* perm, const void* src, const void* src2,
+                                void* dst, int64_t m, hipStream_t st);
+hipError_t launch_column_scale(int dtype, const int32_t* col, const void* a, const void* t,
+                               const void* s, void* out, int64_t m, hipStream_t st);
+hipError_t launch_adj_sum(int dtype, const void* v, int64_t n, double* part_out, int grid,
+                          hipStream_t st);
+hipError_t launch_adj_update(int dtype, const void* y, const void* lam_old, void* lam_new,
+                             const void* g, const uint32_t* dmask, int64_t n, double alpha,
+                             const double* part_in, int n_in, double* part_out, int grid,
+                             hipStream_t st);
+
+// Batched forms.
+struct MultiTables {  // device row-chunk tables of a block-diagonal matrix
+  const int32_t* chunk_row;    // [n_chunks + 1]
+  const int32_t* chunk_graph;  // [n_chunks]
+  const int32_t* chunk_ptr;    // [n_graphs + 1]
+  const double* gsize;         // [n_graphs] vertex count of each graph
+  double* part;                // [2 n_chunks] per-chunk pairs
+  int32_t n_chunks;
+  int32_t n_graphs;
+};
+int multi_chunk_rows();
+hipError_t launch_multi_dangling(int dtype, const void* x, const uint32_t* dmask,
+                                 const MultiTables& mt, double* gsum_out, hipStream_t st);
+hipError_t launch_multi_update(int dtype, const void* y, const void* x_old, void* x_new,
+                               const uint32_t* dmask, const MultiTables& mt, double alpha,
+                               const double* gsum_in, double* gsum_out, hipStream_t st);
+hipError_t launch_spmm(int dtype, int sigma, const SpmmArgs& a, hipStream_t st);
+hipError_t launch_spmm_zero(int dtype, const uint32_t* tile_y, int32_t tile_num, void* Y,
+                            int64_t ld, int k, hipStream_t st);
+int ppr_grid(int64_t n);
+hipError_t launch_ppr_dangling(int dtype, const void* X, const uint32_t* dmask, int64_t n, int k,
+                               double* part, double* sums, int grid, hipStream_t st);
+hipError_t launch_ppr_update(int dtype, const void* Y, const void* X_old, void* X_new,
+                             const uint32_t* dmask, int64_t n, int k, double alpha,
+                             const int32_t* src, const double* sums_in, double* part,
+                             double* sums_out, int grid, hipStream_t st);
 
 }  // namespace merbit

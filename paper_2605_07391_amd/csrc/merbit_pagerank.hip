@@ -13,8 +13,6 @@
 
 namespace merbit {
 
-constexpr int kReduceThreads = 256;
-
 // ------------------------------------------------------- dangling mask ----
 
 __global__ void mark_out_kernel(const int32_t* __restrict__ col, int64_t nnz,
@@ -66,29 +64,6 @@ hipError_t launch_dangling_mask(const int32_t* col, int64_t nnz, int64_t n,
 // next update, or the host) sums the pairs in block order.  Kernel boundaries
 // order the writes before the reads, so no device-scope fence is needed, and
 // every consumer block computes the same bits.
-
-// Sum (a, b) over the block in a fixed order; thread 0 gets the totals.
-__device__ __forceinline__ void block_sum2(double& a, double& b) {
-  __shared__ double sa[kReduceThreads / kOmega], sb[kReduceThreads / kOmega];
-  const int tid = threadIdx.x, lid = tid & (kOmega - 1), wid = tid / kOmega;
-  a = wave_sum(a);
-  b = wave_sum(b);
-  __syncthreads();  // sa/sb may still be read from a previous call
-  if (lid == 0) {
-    sa[wid] = a;
-    sb[wid] = b;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double ta = 0.0, tb = 0.0;
-    for (int w = 0; w < kReduceThreads / kOmega; ++w) {
-      ta += sa[w];
-      tb += sb[w];
-    }
-    a = ta;
-    b = tb;
-  }
-}
 
 // Total of the first components of n_in pairs, identical in every block.
 __device__ __forceinline__ double sum_partials_first(const double* __restrict__ p, int n_in) {

@@ -19,7 +19,11 @@ OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, NOT_CONVERGED = 0, -1, -2, -3, -4, 1
 F32, F64 = 0, 1
 EXPORTED = ("merbit_opts_init", "merbit_plan_create", "merbit_plan_set_values", "merbit_plan_info",
             "merbit_plan_export", "merbit_spmv", "merbit_spmv_dual", "merbit_zero_boundary",
-            "merbit_pagerank", "merbit_profile_enable", "merbit_profile_read",
+            "merbit_pagerank", "merbit_spmm", "merbit_spmm_dual", "merbit_spmm_zero_boundary",
+            "merbit_pagerank_personalized", "merbit_pagerank_multi", "merbit_transpose",
+            "merbit_sddmm", "merbit_gather_values", "merbit_column_scale",
+            "merbit_pagerank_adjoint", "merbit_tune",
+            "merbit_profile_enable", "merbit_profile_read",
             "merbit_plan_destroy", "merbit_last_error", "merbit_version")
 
 
@@ -45,7 +49,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_int32), ("block_lanes", ctypes.c_int32),
                 ("commit", ctypes.c_int32), ("hot_columns", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("eager_loops", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 COMMIT_AUTO, COMMIT_BLOCK, COMMIT_WAVE = 0, 1, 2
@@ -77,6 +81,21 @@ def load():
     lib.merbit_zero_boundary.argtypes = [vp, vp, vp]
     lib.merbit_pagerank.argtypes = [vp, dbl, dbl, i32, i32, vp, ctypes.POINTER(i32),
                                     ctypes.POINTER(dbl), vp]
+    lib.merbit_spmm.argtypes = [vp, vp, i64, vp, i64, i32, vp]
+    lib.merbit_spmm_dual.argtypes = [vp, vp, i64, vp, i64, vp, i64, i32, vp]
+    lib.merbit_spmm_zero_boundary.argtypes = [vp, vp, i64, i32, vp]
+    lib.merbit_pagerank_personalized.argtypes = [vp, dbl, dbl, i32, i32, vp, i32, vp,
+                                                 ctypes.POINTER(i32), vp, vp]
+    lib.merbit_pagerank_multi.argtypes = [vp, vp, i32, dbl, dbl, i32, i32, vp,
+                                          ctypes.POINTER(i32), vp, vp]
+    lib.merbit_transpose.argtypes = [vp, vp, vp, vp, vp]
+    lib.merbit_sddmm.argtypes = [vp, vp, vp, dbl, vp, vp]
+    lib.merbit_gather_values.argtypes = [i32, i64, vp, vp, vp, vp, vp]
+    lib.merbit_column_scale.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
+    lib.merbit_pagerank_adjoint.argtypes = [vp, vp, dbl, dbl, i32, i32, vp, vp,
+                                            ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
+    lib.merbit_tune.argtypes = [i64, i64, i64, vp, vp, vp, i32, vp, i32, vp, i32, i32,
+                                ctypes.POINTER(Opts), vp, vp]
     lib.merbit_profile_enable.argtypes = [vp, i32]
     lib.merbit_profile_read.argtypes = [vp, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     lib.merbit_plan_destroy.argtypes = [vp]
@@ -85,7 +104,12 @@ def load():
     lib.merbit_version.restype = ctypes.c_char_p
     for name in ("merbit_plan_create", "merbit_plan_set_values", "merbit_plan_info",
                  "merbit_plan_export", "merbit_spmv", "merbit_spmv_dual", "merbit_zero_boundary",
-                 "merbit_pagerank", "merbit_profile_enable", "merbit_profile_read"):
+                 "merbit_pagerank", "merbit_spmm", "merbit_spmm_dual",
+                 "merbit_spmm_zero_boundary", "merbit_pagerank_personalized",
+                 "merbit_pagerank_multi", "merbit_transpose", "merbit_sddmm",
+                 "merbit_gather_values", "merbit_column_scale", "merbit_pagerank_adjoint",
+                 "merbit_tune", "merbit_profile_enable",
+                 "merbit_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -127,7 +151,7 @@ class Plan:
     def __init__(self, row_ptr: torch.Tensor, col_ind: torch.Tensor, values: torch.Tensor,
                  n_cols: int, *, sigma: int = 0, block_lanes: int = 0, hot_columns: int = -1,
                  commit: str = "auto", blocks_per_cu: int = 0, validate: bool = True,
-                 stream=None):
+                 eager_loops: bool = False, stream=None):
         lib = load()
         self.dtype = values.dtype
         self._code = _vdtype(values)
@@ -148,6 +172,7 @@ class Plan:
         opts.hot_columns = hot_columns
         opts.validate = 1 if validate else 0
         opts.blocks_per_cu = blocks_per_cu
+        opts.eager_loops = 1 if eager_loops else 0
         h = ctypes.c_void_p()
         _check(lib.merbit_plan_create(self.n_rows, self.n_cols, self.nnz, rp, ci, va, self._code,
                                       ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
@@ -244,6 +269,138 @@ class Plan:
                     allow=(OK, NOT_CONVERGED))
         return it.value, res.value, rc == OK
 
+    # -- batched forms ------------------------------------------------------
+    def _mat(self, t, rows, name):
+        """Row-major [rows, k] GPU tensor with unit column stride -> (ptr, ld, k)."""
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+            raise TypeError(f"{name} must be a GPU tensor")
+        if t.dtype != self.dtype:
+            raise TypeError(f"{name} must be {self.dtype}, got {t.dtype}")
+        if t.dim() != 2 or t.shape[0] != rows:
+            raise ValueError(f"{name} must have shape ({rows}, k)")
+        if t.shape[1] > 1 and t.stride(1) != 1:
+            raise TypeError(f"{name} must have unit column stride")
+        ld = t.stride(0) if t.shape[0] > 1 else t.shape[1]
+        return ctypes.c_void_p(t.data_ptr() if t.numel() else 0), max(ld, t.shape[1]), t.shape[1]
+
+    def spmm(self, X: torch.Tensor, out: torch.Tensor | None = None, stream=None):
+        """Y = A X for X of shape (n_cols, k) (overwrites out, shape (n_rows, k))."""
+        if out is None:
+            out = torch.empty(self.n_rows, X.shape[1], dtype=self.dtype, device=X.device)
+        xp, ldx, k = self._mat(X, self.n_cols, "X")
+        yp, ldy, ky = self._mat(out, self.n_rows, "Y")
+        if ky != k:
+            raise ValueError("X and Y differ in column count")
+        _check(load().merbit_spmm(self._handle(), xp, ldx, yp, ldy, k, _stream(stream)))
+        return out
+
+    def spmm_dual(self, X, Y, Z, stream=None):
+        """Y = A X with Y zero at the boundary rows on entry; leaves Z zero there."""
+        xp, ldx, k = self._mat(X, self.n_cols, "X")
+        yp, ldy, ky = self._mat(Y, self.n_rows, "Y")
+        zp, ldz, kz = self._mat(Z, self.n_rows, "Z")
+        if not k == ky == kz:
+            raise ValueError("X, Y, Z differ in column count")
+        _check(load().merbit_spmm_dual(self._handle(), xp, ldx, yp, ldy, zp, ldz, k,
+                                       _stream(stream)))
+        return Y
+
+    def spmm_zero_boundary(self, Y, stream=None):
+        yp, ldy, k = self._mat(Y, self.n_rows, "Y")
+        _check(load().merbit_spmm_zero_boundary(self._handle(), yp, ldy, k, _stream(stream)))
+        return Y
+
+    def pagerank_personalized(self, sources, X: torch.Tensor | None = None, alpha: float = 0.85,
+                              tol: float = 0.0, max_iter: int = 100, check_every: int = 10,
+                              stream=None):
+        """Personalised PageRank for up to 64 sources at once.  X (n, k) holds
+        the initial vectors (default: column j = e_{sources[j]}) and gets the
+        ranks.  Returns (X, iterations, per-column last l1 change, converged)."""
+        import numpy as np
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.int64).reshape(-1))
+        k = src.size
+        # checked here, before any device work touches them
+        if not 1 <= k <= 64:
+            raise MerbitError(EINVAL, "need 1..64 sources")
+        if src.min() < 0 or src.max() >= self.n_rows:
+            raise MerbitError(EINVAL, "source out of range")
+        src = src.astype(np.int32)
+        if X is None:
+            X = torch.zeros(self.n_rows, k, dtype=self.dtype, device="cuda")
+            X[torch.as_tensor(src, dtype=torch.int64, device="cuda"),
+              torch.arange(k, device="cuda")] = 1.0
+        if tuple(X.shape) != (self.n_rows, k) or not X.is_contiguous():
+            raise ValueError(f"X must be a contiguous ({self.n_rows}, {k}) tensor")
+        it = ctypes.c_int()
+        res = np.zeros(max(k, 1), np.float64)
+        rc = _check(load().merbit_pagerank_personalized(
+            self._handle(), float(alpha), float(tol), int(max_iter), int(check_every),
+            src.ctypes.data_as(ctypes.c_void_p), int(k), _dev(X, self.dtype, "X"),
+            ctypes.byref(it), res.ctypes.data_as(ctypes.c_void_p), _stream(stream)),
+            allow=(OK, NOT_CONVERGED))
+        return X, it.value, res[:k], rc == OK
+
+    def pagerank_multi(self, graph_ptr, x: torch.Tensor, alpha: float = 0.85, tol: float = 0.0,
+                       max_iter: int = 100, check_every: int = 10, stream=None):
+        """PageRank of every graph on the diagonal (graph g = rows
+        graph_ptr[g] .. graph_ptr[g+1]-1), in place on x.  Returns
+        (iterations, per-graph last l1 change, converged)."""
+        import numpy as np
+        gp = np.ascontiguousarray(np.asarray(graph_ptr, dtype=np.int64).reshape(-1))
+        G = gp.size - 1
+        if x.numel() != self.n_rows:
+            raise ValueError("x length mismatch")
+        it = ctypes.c_int()
+        res = np.zeros(max(G, 1), np.float64)
+        rc = _check(load().merbit_pagerank_multi(
+            self._handle(), gp.ctypes.data_as(ctypes.c_void_p), int(G), float(alpha), float(tol),
+            int(max_iter), int(check_every), _dev(x, self.dtype, "x"), ctypes.byref(it),
+            res.ctypes.data_as(ctypes.c_void_p), _stream(stream)), allow=(OK, NOT_CONVERGED))
+        return it.value, res[:max(G, 0)], rc == OK
+
+    # -- adjoint pieces -----------------------------------------------------
+    def transpose(self, stream=None):
+        """CSR of A^T on the device: (rowT_ptr int32[n_cols+1], colT int32[nnz],
+        perm int32[nnz]); A^T's values are values[perm]."""
+        dev = self._keep[1].device
+        rowT = torch.empty(self.n_cols + 1, dtype=torch.int32, device=dev)
+        colT = torch.empty(self.nnz, dtype=torch.int32, device=dev)
+        perm = torch.empty(self.nnz, dtype=torch.int32, device=dev)
+        _check(load().merbit_transpose(self._handle(), _dev(rowT, torch.int32, "rowT"),
+                                       _dev(colT, torch.int32, "colT"),
+                                       _dev(perm, torch.int32, "perm"), _stream(stream)))
+        return rowT, colT, perm
+
+    def sddmm(self, g: torch.Tensor, x: torch.Tensor, scale: float = 1.0,
+              out: torch.Tensor | None = None, stream=None):
+        """out[e] = scale g[row(e)] x[col(e)] on the plan's nonzeros."""
+        if g.numel() != self.n_rows or x.numel() != self.n_cols:
+            raise ValueError("g / x length mismatch")
+        if out is None:
+            out = torch.empty(self.nnz, dtype=self.dtype, device=g.device)
+        if out.numel() != self.nnz:
+            raise ValueError("out length mismatch")
+        _check(load().merbit_sddmm(self._handle(), _dev(g, self.dtype, "g"),
+                                   _dev(x, self.dtype, "x"), float(scale),
+                                   _dev(out, self.dtype, "out"), _stream(stream)))
+        return out
+
+    def pagerank_adjoint(self, plan_t: "Plan", g: torch.Tensor, lam: torch.Tensor,
+                         alpha: float = 0.85, tol: float = 0.0, max_iter: int = 100,
+                         check_every: int = 10, stream=None):
+        """In place on lam: lambda = g + alpha P^T lambda + (alpha/n)(1^T lambda) d.
+        plan_t is the plan of this matrix's transpose.  Returns
+        (iterations, last l1 change, converged)."""
+        if g.numel() != self.n_rows or lam.numel() != self.n_rows:
+            raise ValueError("g / lambda length mismatch")
+        it = ctypes.c_int()
+        res = ctypes.c_double()
+        rc = _check(load().merbit_pagerank_adjoint(
+            self._handle(), plan_t._handle(), float(alpha), float(tol), int(max_iter),
+            int(check_every), _dev(g, self.dtype, "g"), _dev(lam, self.dtype, "lambda"),
+            ctypes.byref(it), ctypes.byref(res), _stream(stream)), allow=(OK, NOT_CONVERGED))
+        return it.value, res.value, rc == OK
+
     # -- timing -------------------------------------------------------------
     def profile_enable(self, on: bool = True):
         _check(load().merbit_profile_enable(self._handle(), 1 if on else 0))
@@ -254,6 +411,70 @@ class Plan:
         ms = ctypes.c_double()
         _check(load().merbit_profile_read(self._handle(), ctypes.byref(n), ctypes.byref(ms)))
         return n.value, ms.value
+
+
+def gather_values(perm: torch.Tensor, src: torch.Tensor, src2: torch.Tensor | None = None,
+                  out: torch.Tensor | None = None, stream=None):
+    """out[i] = src[perm[i]] (* src2[perm[i]])."""
+    code = _vdtype(src)
+    if out is None:
+        out = torch.empty(perm.numel(), dtype=src.dtype, device=src.device)
+    if src.numel() != perm.numel() or out.numel() != perm.numel() or (
+            src2 is not None and src2.numel() != perm.numel()):
+        raise ValueError("length mismatch")
+    _check(load().merbit_gather_values(
+        code, perm.numel(), _dev(perm, torch.int32, "perm"), _dev(src, src.dtype, "src"),
+        None if src2 is None else _dev(src2, src.dtype, "src2"), _dev(out, src.dtype, "out"),
+        _stream(stream)))
+    return out
+
+
+def column_scale(col: torch.Tensor, a: torch.Tensor, s: torch.Tensor,
+                 t: torch.Tensor | None = None, out: torch.Tensor | None = None, stream=None):
+    """out[e] = (a[e] - t[col[e]]) / s[col[e]] (t optional)."""
+    code = _vdtype(a)
+    if out is None:
+        out = torch.empty_like(a)
+    if a.numel() != col.numel() or out.numel() != col.numel():
+        raise ValueError("length mismatch")
+    _check(load().merbit_column_scale(
+        code, col.numel(), _dev(col, torch.int32, "col"), _dev(a, a.dtype, "a"),
+        None if t is None else _dev(t, a.dtype, "t"), _dev(s, a.dtype, "s"),
+        _dev(out, a.dtype, "out"), _stream(stream)))
+    return out
+
+
+def tune(row_ptr: torch.Tensor, col_ind: torch.Tensor, values: torch.Tensor, n_cols: int, *,
+         sigmas=None, block_lanes=None, reps: int = 20, commit: str = "auto",
+         hot_columns: int = -1, stream=None):
+    """Time the fused SpMV for every (sigma, block_lanes) candidate on this
+    matrix.  Returns ({"sigma": s, "block_lanes": b}, {(s, b): mean us})."""
+    import numpy as np
+    lib = load()
+    code = _vdtype(values)
+    n_rows = row_ptr.numel() - 1
+    if sigmas is None:
+        sigmas = list(range(7, 13)) if code == F32 else list(range(4, 11))
+    if block_lanes is None:
+        block_lanes = [256, 512, 1024]
+    sg = np.ascontiguousarray(sigmas, np.int32)
+    bl = np.ascontiguousarray(block_lanes, np.int32)
+    us = np.full(sg.size * bl.size, -1.0, np.float32)
+    opts = Opts()
+    lib.merbit_opts_init(ctypes.byref(opts))
+    opts.commit = _COMMIT[commit]
+    opts.hot_columns = hot_columns
+    _check(lib.merbit_tune(n_rows, int(n_cols), col_ind.numel(),
+                           _dev(row_ptr, torch.int32, "row_ptr"),
+                           _dev(col_ind, torch.int32, "col_ind"),
+                           _dev(values, values.dtype, "values"), code,
+                           sg.ctypes.data_as(ctypes.c_void_p), int(sg.size),
+                           bl.ctypes.data_as(ctypes.c_void_p), int(bl.size), int(reps),
+                           ctypes.byref(opts), us.ctypes.data_as(ctypes.c_void_p),
+                           _stream(stream)))
+    table = {(int(s), int(b)): float(us[i * bl.size + j])
+             for i, s in enumerate(sg) for j, b in enumerate(bl)}
+    return {"sigma": opts.sigma, "block_lanes": opts.block_lanes}, table
 
 
 def version() -> str:

@@ -59,3 +59,42 @@ def check_spmv(y_gpu, row_ptr, col, vals64, x64, dtype, label=""):
 def seeded_x(n, seed, dtype):
     x = graphgen.uniform(seed, 77, n, -1.0, 1.0)
     return x.astype(np.float32 if dtype == torch.float32 else np.float64).astype(np.float64)
+
+
+def spmv_cases():
+    """Named row_ptr patterns (with their column counts) for the parity tests:
+    degenerate shapes, long rows, random and fuzzed sizes, a Chung-Lu graph."""
+    cases = {}
+    cases["one_row"] = (np.array([0, 1], np.int32), 3)
+    cases["all_rows_empty"] = (np.zeros(301, np.int32), 4)
+    cases["single_long_row"] = (np.array([0, 20000], np.int32), 20000)
+    cases["long_then_empty"] = (np.array([0, 2000, 2000, 2000, 2001, 4500] + [4500] * 700,
+                                         np.int32), 3000)
+    for seed, (n, nc, dens, emp) in enumerate([(50, 40, 0.3, 0.2), (700, 300, 0.02, 0.5),
+                                               (1200, 800, 0.02, 0.1), (333, 64, 0.02, 0.0),
+                                               (200, 3000, 0.01, 0.3), (3000, 50, 0.05, 0.2)]):
+        rp, _, _ = graphgen.random_csr(n, nc, dens, seed, empty_frac=emp, long_rows=(n // 3,))
+        cases[f"random{seed}_{n}x{nc}"] = (rp, nc)
+    cases["one_column"] = (np.arange(1001, dtype=np.int32), 1)
+    rp, _ = graphgen.chung_lu_pattern(10_000, 100_000, 2.1, 0.1, seed=1)
+    cases["chung_lu_10k"] = (rp, 10_000)
+    # fuzz: random sizes, densities, empty fractions
+    rng = np.random.default_rng(2024)
+    for f in range(6):
+        n = int(rng.integers(1, 4000))
+        nc = int(rng.integers(1, 4000))
+        dens = float(rng.uniform(0.0005, 0.02))
+        rp, _, _ = graphgen.random_csr(n, nc, dens, 100 + f, empty_frac=float(rng.uniform(0, .7)))
+        cases[f"fuzz{f}_{n}x{nc}"] = (rp, nc)
+    return cases
+
+
+def case_matrix(cases, name, seed=0):
+    """Seeded columns and values in [-1, 1) on the named pattern."""
+    rp, nc = cases[name]
+    m = int(rp[-1])
+    rng = np.random.default_rng(seed)
+    col = rng.integers(0, nc, m).astype(np.int32)
+    # columns need not be sorted within a row
+    vals = rng.uniform(-1, 1, m)
+    return rp, col, vals, nc

@@ -148,3 +148,48 @@ def test_rmat22_pagerank_iterates(dtype):
     assert abs(got.sum() - 1.0) <= (1e-4 if dtype == torch.float32 else 1e-12)
     assert abs(resid - resid_ref[-1]) <= 1e-3 * resid_ref[-1]
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+def test_graph_replays_match_eager(dtype):
+    """Iteration chunks recorded in HIP graphs: the first call captures the
+    chunk, later calls replay it.  Five calls with eager work (a plain SpMV,
+    an eager-mode plan) and synchronisations between them; every replay is
+    checked against the oracle and against the eager plan."""
+    dev = require_gpu()
+    w = workload("chung_lu_10k")
+    n = w["n_rows"]
+    plan, keep = _plan(w, dtype, dev)
+    eager, keep2 = _plan(w, dtype, dev, eager_loops=True)
+    x0_64, x0 = _x0(n, dtype, dev)
+    vals = host_values(w["values"], dtype)
+    ref, _, _ = oracle.pagerank(w["row_ptr"], w["col"], vals, ALPHA, 12, x0_64)
+    x = x0.clone()
+    for rep in range(5):
+        x.copy_(x0)
+        iters, _, _ = plan.pagerank(x, ALPHA, tol=0.0, max_iter=12, check_every=4)
+        assert iters == 12
+        xe = x0.clone()
+        eager.pagerank(xe, ALPHA, tol=0.0, max_iter=12, check_every=4)
+        y = plan.spmv(xe)  # eager work on the same plan between replays
+        torch.cuda.synchronize()
+        got = x.double().cpu().numpy()
+        rel = np.abs(got - ref) / ref
+        assert rel.max() <= PR_TOL[dtype], f"replay {rep}: {rel.max():.3e}"
+        rel_e = (np.abs(got - xe.double().cpu().numpy()) / ref).max()
+        assert rel_e <= 2 * PR_TOL[dtype], f"replay {rep} vs eager: {rel_e:.3e}"
+        assert torch.isfinite(y).all()
+    # a different x buffer and alpha are captured as a new graph
+    x2 = x0.clone()
+    plan.pagerank(x2, 0.5, tol=0.0, max_iter=8, check_every=4)
+    ref2, _, _ = oracle.pagerank(w["row_ptr"], w["col"], vals, 0.5, 8, x0_64)
+    assert (np.abs(x2.double().cpu().numpy() - ref2) / ref2).max() <= PR_TOL[dtype]
+    # new values on the same plan: captured graphs are dropped and re-recorded
+    v2 = keep[2] * 1.0
+    plan.set_values(v2)
+    x.copy_(x0)
+    plan.pagerank(x, ALPHA, tol=0.0, max_iter=12, check_every=4)
+    torch.cuda.synchronize()
+    assert (np.abs(x.double().cpu().numpy() - ref) / ref).max() <= PR_TOL[dtype]
+    plan.close()
+    eager.close()

@@ -6,8 +6,8 @@ import torch
 
 import graphgen
 import oracle
-from helpers import (workload, OMEGA, SPMV_TOL, check_spmv, host_values, require_gpu, seeded_x,
-                     to_device)
+from helpers import (workload, OMEGA, SPMV_TOL, case_matrix, check_spmv, host_values, require_gpu,
+                     seeded_x, spmv_cases, to_device)
 
 pytestmark = pytest.mark.gpu
 
@@ -22,43 +22,11 @@ def _boundary_rows(sigma, block_lanes):
     return lens
 
 
-def _cases():
-    cases = {}
-    cases["one_row"] = (np.array([0, 1], np.int32), 3)
-    cases["all_rows_empty"] = (np.zeros(301, np.int32), 4)
-    cases["single_long_row"] = (np.array([0, 20000], np.int32), 20000)
-    cases["long_then_empty"] = (np.array([0, 2000, 2000, 2000, 2001, 4500] + [4500] * 700,
-                                         np.int32), 3000)
-    for seed, (n, nc, dens, emp) in enumerate([(50, 40, 0.3, 0.2), (700, 300, 0.02, 0.5),
-                                               (1200, 800, 0.02, 0.1), (333, 64, 0.02, 0.0),
-                                               (200, 3000, 0.01, 0.3), (3000, 50, 0.05, 0.2)]):
-        rp, _, _ = graphgen.random_csr(n, nc, dens, seed, empty_frac=emp, long_rows=(n // 3,))
-        cases[f"random{seed}_{n}x{nc}"] = (rp, nc)
-    cases["one_column"] = (np.arange(1001, dtype=np.int32), 1)
-    rp, _ = graphgen.chung_lu_pattern(10_000, 100_000, 2.1, 0.1, seed=1)
-    cases["chung_lu_10k"] = (rp, 10_000)
-    # fuzz: random sizes, densities, empty fractions
-    rng = np.random.default_rng(2024)
-    for f in range(6):
-        n = int(rng.integers(1, 4000))
-        nc = int(rng.integers(1, 4000))
-        dens = float(rng.uniform(0.0005, 0.02))
-        rp, _, _ = graphgen.random_csr(n, nc, dens, 100 + f, empty_frac=float(rng.uniform(0, .7)))
-        cases[f"fuzz{f}_{n}x{nc}"] = (rp, nc)
-    return cases
-
-
-CASES = _cases()
+CASES = spmv_cases()
 
 
 def _matrix(name, seed=0):
-    rp, nc = CASES[name]
-    m = int(rp[-1])
-    rng = np.random.default_rng(seed)
-    col = rng.integers(0, nc, m).astype(np.int32)
-    # sort each row's columns so the pattern is a valid CSR (order is free anyway)
-    vals = rng.uniform(-1, 1, m)
-    return rp, col, vals, nc
+    return case_matrix(CASES, name, seed)
 
 
 @pytest.mark.parametrize("sigma", [1, 4, 7, 12])
@@ -312,3 +280,30 @@ def test_stress24_fp64_full_size(commit, hot):
     hub = w["meta"]["hub_rows"][0]
     assert rp[hub + 1] - rp[hub] == 2_000_000
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+def test_autotuner_picks_a_measured_candidate(dtype):
+    """The tuner times every built (sigma, block size) pair, reports -1 for a
+    pair the kernels do not build, and returns the fastest; a plan with its
+    choice is exact against the oracle."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    rp, col, vals, nc = _matrix("chung_lu_10k", seed=2)
+    r, c, v = to_device(rp, col, vals, dtype, dev)
+    best, table = pkg.tune(r, c, v, nc, sigmas=[5, 12, 13], block_lanes=[256, 1024, 192],
+                           reps=5)
+    assert table[(13, 256)] == -1.0 and table[(12, 192)] == -1.0
+    measured = {k: t for k, t in table.items() if t >= 0}
+    assert len(measured) == 4 and all(t > 0 for t in measured.values())
+    assert (best["sigma"], best["block_lanes"]) == min(measured, key=measured.get)
+    plan = pkg.Plan(r, c, v, nc, **best)
+    x64 = seeded_x(nc, 1, dtype)
+    y = plan.spmv(torch.from_numpy(x64).to(dtype).to(dev))
+    torch.cuda.synchronize()
+    check_spmv(y, rp, col, host_values(vals, dtype), x64, dtype, "tuned")
+    plan.close()
+    # default candidate sets
+    best, table = pkg.tune(r, c, v, nc, reps=3)
+    assert len(table) == (6 if dtype == torch.float32 else 7) * 3
+    assert best["sigma"] in {s for s, _ in table}

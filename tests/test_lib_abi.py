@@ -46,7 +46,8 @@ def test_argument_errors_without_gpu():
 
     d = mb.Opts()
     lib.merbit_opts_init(ctypes.byref(d))
-    assert (d.sigma, d.block_lanes, d.commit, d.hot_columns, d.validate) == (0, 0, 0, -1, 1)
+    assert (d.sigma, d.block_lanes, d.commit, d.hot_columns, d.validate,
+            d.eager_loops) == (0, 0, 0, -1, 1, 0)
     # NULL out pointer
     assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, None, None, None) == mb.EINVAL
     # unsupported dtype
@@ -72,6 +73,30 @@ def test_argument_errors_without_gpu():
     # calls on a NULL plan
     assert lib.merbit_spmv(None, None, None, None) == mb.EINVAL
     assert lib.merbit_pagerank(None, 0.85, 0.0, 1, 1, None, None, None, None) == mb.EINVAL
+    assert lib.merbit_spmm(None, None, 1, None, 1, 1, None) == mb.EINVAL
+    assert lib.merbit_spmm_dual(None, None, 1, None, 1, None, 1, 1, None) == mb.EINVAL
+    assert lib.merbit_spmm_zero_boundary(None, None, 1, 1, None) == mb.EINVAL
+    assert lib.merbit_pagerank_personalized(None, 0.85, 0.0, 1, 1, None, 1, None, None, None,
+                                            None) == mb.EINVAL
+    assert lib.merbit_pagerank_multi(None, None, 1, 0.85, 0.0, 1, 1, None, None, None,
+                                     None) == mb.EINVAL
+    # adjoint pieces
+    assert lib.merbit_transpose(None, None, None, None, None) == mb.EINVAL
+    assert lib.merbit_sddmm(None, None, None, 1.0, None, None) == mb.EINVAL
+    assert lib.merbit_gather_values(7, 1, vp(8), vp(8), None, vp(16), None) == mb.EUNSUPPORTED
+    assert lib.merbit_gather_values(0, -1, vp(8), vp(8), None, vp(16), None) == mb.EINVAL
+    assert lib.merbit_gather_values(0, 1, vp(8), vp(8), None, vp(8), None) == mb.EINVAL  # alias
+    assert lib.merbit_gather_values(0, 0, None, None, None, None, None) == mb.OK  # nothing to do
+    assert lib.merbit_column_scale(1, 1, None, vp(8), None, vp(8), vp(8), None) == mb.EINVAL
+    assert lib.merbit_pagerank_adjoint(None, None, 0.85, 0.0, 1, 1, None, None, None, None,
+                                       None) == mb.EINVAL
+    # tuner
+    assert lib.merbit_tune(1, 1, 0, vp(8), None, None, 0, None, 0, None, 0, 5, None, None,
+                           None) == mb.EINVAL
+    assert lib.merbit_tune(1, 1, 0, vp(8), None, None, 7, None, 0, None, 0, 5,
+                           ctypes.byref(d), None, None) == mb.EUNSUPPORTED
+    assert lib.merbit_tune(1, 1, 0, vp(8), None, None, 0, None, 0, None, 0, 0,
+                           ctypes.byref(d), None, None) == mb.EINVAL
 
 
 def test_oracle_is_not_imported_by_the_package():
