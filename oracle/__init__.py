@@ -24,6 +24,10 @@ for Iterative Workloads") it follows.  Functions and their pins:
 * ``pagerank_multi`` (independent graphs on the diagonal of one matrix) --
   each graph's PageRank computed on its own slice; pinned by the block
   structure (a graph's ranks do not depend on the other graphs).
+* ``bicgstab`` (Sec. 5.5.2, unpreconditioned BiCGSTAB) -- pinned by dense
+  solves of well-conditioned systems, exact termination in one iteration on
+  a multiple of the identity, the true residual ||b - A x|| at exit, and the
+  textbook recurrences checked step by step in numpy.
 * ``transpose`` (CSR of A^T, stable) -- pinned by dense transposes, the
   double-transpose identity and the adjoint identity <A x, g> = <x, A^T g>.
 * ``pagerank_adjoint``, ``pagerank_value_grad``, ``colnorm`` /
@@ -93,6 +97,9 @@ def _load():
     lib.or_transpose.argtypes = [c_i64, c_i64, _i32, _i32, _i32, _i32, _i32]
     lib.or_pagerank_adjoint.restype = c_int
     lib.or_pagerank_adjoint.argtypes = [c_i64, _i32, _i32, _f64, c_dbl, c_int, _f64, _f64]
+    lib.or_bicgstab.restype = c_int
+    lib.or_bicgstab.argtypes = [c_i64, _i32, _i32, _f64, _f64, _f64, c_dbl, c_int, _f64,
+                                ctypes.c_void_p, ctypes.POINTER(c_int)]
     lib.or_pagerank.restype = c_int
     lib.or_pagerank.argtypes = [c_i64, _i32, _i32, _f64, c_dbl, c_int, _f64, _f64,
                                 ctypes.c_void_p, ctypes.c_void_p]
@@ -348,9 +355,7 @@ def colnorm(col, w, n_cols: int):
     """P[e] = w[e] / s[col(e)], s[c] = sum of w over column c (column
     normalisation of positive edge weights).  Returns (P, s)."""
     col = np.asarray(col, np.int64)
-    s = np.zeros(n_cols)
-    for k in range(len(col)):
-        s[col[k]] += w[k]
+    s = np.bincount(col, weights=np.asarray(w, np.float64), minlength=n_cols)
     return np.asarray(w) / s[col], s
 
 
@@ -359,9 +364,7 @@ def colnorm_backward(col, w, G, n_cols: int) -> np.ndarray:
     G = dL/dP, from differentiating P[e'] = w[e'] / s[col(e')]."""
     col = np.asarray(col, np.int64)
     P, s = colnorm(col, w, n_cols)
-    t = np.zeros(n_cols)
-    for k in range(len(col)):
-        t[col[k]] += G[k] * P[k]
+    t = np.bincount(col, weights=np.asarray(G, np.float64) * P, minlength=n_cols)
     return (np.asarray(G) - t[col]) / s[col]
 
 
@@ -377,3 +380,26 @@ def pagerank_loss_grad(row_ptr, col, w, target, alpha: float, iters: int):
     lam = pagerank_adjoint(row_ptr, col, P, alpha, iters, 2.0 * r)
     G = pagerank_value_grad(row_ptr, col, lam, x, alpha)
     return float(r @ r), colnorm_backward(col, w, G, n), x, lam
+
+
+# -------------------------------------------------------------- BiCGSTAB --
+
+BICGSTAB_STATUS = {0: "converged", 1: "iteration cap", 2: "breakdown"}
+
+
+def bicgstab(row_ptr, col, values, b, x0, tol: float, max_iter: int):
+    """Sec. 5.5.2: unpreconditioned BiCGSTAB for A x = b, stopping when the
+    updated residual satisfies ||r|| / ||b|| < tol.  Returns
+    (x, iterations, status, relative-residual history)."""
+    row_ptr = _i32a(row_ptr)
+    n = len(row_ptr) - 1
+    x = np.empty(max(n, 1), np.float64)
+    hist = np.zeros(max(max_iter, 1), np.float64)
+    st = ctypes.c_int()
+    it = _load().or_bicgstab(n, row_ptr, _i32a(col) if len(col) else np.zeros(1, np.int32),
+                             _f64a(values) if len(values) else np.zeros(1), _f64a(b), _f64a(x0),
+                             float(tol), int(max_iter), x, hist.ctypes.data_as(ctypes.c_void_p),
+                             ctypes.byref(st))
+    if it < 0:
+        raise MemoryError("or_bicgstab failed")
+    return x[:n], it, BICGSTAB_STATUS[st.value], hist[:it]

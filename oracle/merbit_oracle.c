@@ -20,6 +20,7 @@
  *   or_transpose     CSR of A^T with the permutation of the nonzeros
  *   or_pagerank_adjoint   the adjoint fixed point of the PageRank step
  *                    (derivative of Sec. 5.5.1's iteration map)
+ *   or_bicgstab      BiCGSTAB (Sec. 5.5.2, van der Vorst 1992)
  *
  * Conventions.  CSR: row_ptr has n_rows + 1 entries (Sec. 3.1 says "length n";
  * the algorithms read offset[y + 1], so the array has n + 1 entries), col and
@@ -371,4 +372,102 @@ int or_pagerank_adjoint(int64_t n, const int32_t* row_ptr, const int32_t* col,
     free(l);
     free(pt);
     return 0;
+}
+
+/* ------------------------------------------------------------ BiCGSTAB -- */
+
+/* Unpreconditioned BiCGSTAB (van der Vorst, 1992), the second iterative
+ * workload of Sec. 5.5.2: solve A x = b from x0, shadow residual r^ = r_0.
+ * Each iteration:
+ *     rho = (r^, r);  beta = (rho / rho_prev) (alpha / omega)
+ *     p = r + beta (p - omega v);  v = A p;  alpha = rho / (r^, v)
+ *     s = r - alpha v;  t = A s;  omega = (t, s) / (t, t)
+ *     x = x + alpha p + omega s;  r = s - omega t
+ * and stops when ||r||_2 / ||b||_2 < tol (r is the updated residual, equal to
+ * b - A x in exact arithmetic) or after max_iter iterations.  Breakdown
+ * (rho, (r^, v) or (t, t) equal to 0) stops early.  Dots and vectors in long
+ * double.  resid_hist (optional, max_iter entries): ||r|| / ||b|| per
+ * iteration.  Returns the iteration count, or -2 on allocation failure;
+ * *status = 0 converged, 1 iteration cap, 2 breakdown. */
+int or_bicgstab(int64_t n, const int32_t* row_ptr, const int32_t* col, const double* values,
+                const double* b, const double* x0, double tol, int max_iter, double* x_out,
+                double* resid_hist, int* status) {
+    long double *x = 0, *r = 0, *rh = 0, *p = 0, *v = 0, *s = 0, *t = 0;
+    const size_t sz = sizeof(long double) * (size_t)(n > 0 ? n : 1);
+    x = malloc(sz); r = malloc(sz); rh = malloc(sz); p = malloc(sz); v = malloc(sz);
+    s = malloc(sz); t = malloc(sz);
+    if (!x || !r || !rh || !p || !v || !s || !t) {
+        free(x); free(r); free(rh); free(p); free(v); free(s); free(t);
+        return -2;
+    }
+    long double bnorm = 0.0L;
+    for (int64_t i = 0; i < n; ++i) {
+        x[i] = x0[i];
+        bnorm += (long double)b[i] * b[i];
+    }
+    bnorm = sqrtl(bnorm);
+    for (int64_t i = 0; i < n; ++i) {  /* r = b - A x0 */
+        long double ax = 0.0L;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) ax += (long double)values[k] * x[col[k]];
+        r[i] = (long double)b[i] - ax;
+        rh[i] = r[i];
+        p[i] = v[i] = 0.0L;
+    }
+    long double rho_prev = 1.0L, alpha = 1.0L, omega = 1.0L;
+    int it = 0;
+    *status = 1;
+    if (bnorm == 0.0L) bnorm = 1.0L;
+    {
+        long double rr = 0.0L;
+        for (int64_t i = 0; i < n; ++i) rr += r[i] * r[i];
+        if (sqrtl(rr) / bnorm < tol) { *status = 0; max_iter = 0; }
+    }
+    while (it < max_iter) {
+        long double rho = 0.0L;
+        for (int64_t i = 0; i < n; ++i) rho += rh[i] * r[i];
+        if (rho == 0.0L) { *status = 2; break; }
+        const long double beta = (rho / rho_prev) * (alpha / omega);
+        for (int64_t i = 0; i < n; ++i) p[i] = r[i] + beta * (p[i] - omega * v[i]);
+        long double rhv = 0.0L;
+        for (int64_t i = 0; i < n; ++i) {
+            long double a = 0.0L;
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) a += (long double)values[k] * p[col[k]];
+            v[i] = a;
+            rhv += rh[i] * a;
+        }
+        if (rhv == 0.0L) { *status = 2; break; }
+        alpha = rho / rhv;
+        for (int64_t i = 0; i < n; ++i) s[i] = r[i] - alpha * v[i];
+        long double ts = 0.0L, tt = 0.0L;
+        for (int64_t i = 0; i < n; ++i) {
+            long double a = 0.0L;
+            for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) a += (long double)values[k] * s[col[k]];
+            t[i] = a;
+            ts += a * s[i];
+            tt += a * a;
+        }
+        if (tt == 0.0L) {  /* s = 0 exactly: x + alpha p solves the system */
+            for (int64_t i = 0; i < n; ++i) { x[i] += alpha * p[i]; r[i] = s[i]; }
+            ++it;
+            if (resid_hist) resid_hist[it - 1] = 0.0;
+            *status = 0;
+            break;
+        }
+        omega = ts / tt;
+        long double rr = 0.0L;
+        for (int64_t i = 0; i < n; ++i) {
+            x[i] += alpha * p[i] + omega * s[i];
+            r[i] = s[i] - omega * t[i];
+            rr += r[i] * r[i];
+        }
+        ++it;
+        const long double rel = sqrtl(rr) / bnorm;
+        if (resid_hist) resid_hist[it - 1] = (double)rel;
+        rho_prev = rho;
+        if (rel < tol) { *status = 0; break; }
+        if (omega == 0.0L) { *status = 2; break; }
+    }
+    for (int64_t i = 0; i < n; ++i) x_out[i] = (double)x[i];
+    free(x); free(r); free(rh); free(p); free(v); free(s); free(t);
+    return it;
 }
