@@ -235,6 +235,48 @@ def run_multi(steps: int, warmup: int, alpha: float):
             "seed": w["meta"]["seed"]}
 
 
+def run_bicgstab(scale: int, steps: int):
+    """BiCGSTAB (Sec. 5.5.2) on the symmetric 0/1 R-MAT system of the given
+    scale, FP64, b = A x_true: `steps` iterations (two fused SpMVs and five
+    vector kernels each) after 5 warm-up iterations.  Returns per-iteration
+    time, the SpMV share and the residual reached."""
+    import torch
+
+    import graphgen
+    import paper_2605_07391_amd as pkg
+    dev = torch.device("cuda:0")
+    w = graphgen.workload(f"rmat{scale}_sym")
+    n = w["n_rows"]
+    r = torch.from_numpy(w["row_ptr"]).to(dev)
+    c = torch.from_numpy(w["col"]).to(dev)
+    v = torch.from_numpy(w["values"]).to(dev)
+    plan = pkg.Plan(r, c, v, n, validate=False)
+    b = plan.spmv(torch.from_numpy(w["x"]).to(dev))
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    plan.bicgstab(b, x, tol=0.0, max_iter=5)
+    x.zero_()
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    it, res, _ = plan.bicgstab(b, x, tol=0.0, max_iter=steps, check_every=10)
+    t1.record()
+    torch.cuda.synchronize()
+    it_ms = t0.elapsed_time(t1) / steps
+    x.zero_()
+    plan.profile_enable(True)
+    plan.bicgstab(b, x, tol=0.0, max_iter=steps, check_every=10)
+    launches, kernel_ms = plan.profile_read()
+    plan.close()
+    spmv_ms = kernel_ms / max(launches, 1)
+    nnz = w["nnz"]
+    return {"workload": f"rmat{scale}_sym_bicgstab", "dtype": "f64", "n": n, "nnz": int(nnz),
+            "iterations": it, "ms_per_iteration": round(it_ms, 4),
+            "spmv_us": round(spmv_ms * 1e3, 1),
+            "spmv_share": round(2 * spmv_ms / it_ms, 3),
+            "gnzs": round(2 * nnz / (it_ms * 1e-3) / 1e9, 3),
+            "rel_residual": res, "seed": scale}
+
+
 def cpu_baseline(w, iters: int, alpha: float, dtype_name: str = "f32"):
     import numpy as np
 
@@ -281,6 +323,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched runs (64-source PPR, 256 graphs)")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--no-bicgstab", action="store_true",
+                    help="skip the BiCGSTAB run on the symmetric 0/1 R-MAT system")
+    ap.add_argument("--bicgstab-scale", type=int, default=21)
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default sigma / block size instead of the autotuner")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -343,6 +388,11 @@ def main():
         print(f"[bench] multi256: step {multi['ms_per_step']:.3f} ms", file=sys.stderr,
               flush=True)
         batched = {"ppr64_" + args.workload + "_f32": ppr, "chung_lu_multi256_f32": multi}
+    bicg = None
+    if not args.no_bicgstab and w["meta"]["generator"] == "rmat":
+        bicg = run_bicgstab(args.bicgstab_scale, args.batched_steps * 10)
+        print(f"[bench] bicgstab: {bicg['ms_per_iteration']:.3f} ms / iteration", file=sys.stderr,
+              flush=True)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_iters, args.alpha, args.dtype)
@@ -387,6 +437,7 @@ def main():
         "tuning": main_run["tuning"],
         "f64": extra,
         "batched": batched,
+        "bicgstab": bicg,
     }
     print(json.dumps(out), flush=True)
 

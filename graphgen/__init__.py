@@ -18,6 +18,10 @@ Workloads (all int32 CSR, rows = destinations, duplicates merged):
   Vertex counts log-uniform in [1,000, 200,000] (seed 40, stream 22), 8 edge
   draws per vertex, exponent 2.1, 10 % empty rows; graph g uses seed 1000 + g.
   Values 1/outdeg.  The key ``graph_ptr`` holds the offsets.
+* ``rmat<s>_sym`` -- the R-MAT pattern above made undirected (A + A^T,
+  duplicates merged, self-loops kept) with every value 1: the symmetric 0/1
+  systems of the BiCGSTAB workload.  x_true uniform in [-1, 1) (seed s,
+  stream 85); b = A x_true is formed on the device by the caller.
 * ``stress24`` -- R-MAT scale 24 as above (seed 24), 30 % of rows cleared,
   8 rows replaced by 2,000,000 uniformly chosen distinct columns.  Values
   uniform in (0, 1] (seed 24, stream 20), x uniform in [-1, 1) (seed 25,
@@ -179,8 +183,35 @@ def chung_lu_multi(n_graphs: int = 256, lo: int = 1000, hi: int = 200_000, degre
     return row_ptr.astype(np.int32), np.concatenate(parts_col), graph_ptr
 
 
+STREAM_XTRUE = 85
+
+
+def symmetrize_pattern(row_ptr, col, n: int):
+    """Pattern of A + A^T (duplicates merged, columns sorted within rows)."""
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(np.asarray(row_ptr, np.int64)))
+    c = np.asarray(col, np.int64)
+    keys = np.unique(np.concatenate([rows * n + c, c * n + rows]))
+    r2 = keys // n
+    out_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(r2, minlength=n), out=out_ptr[1:])
+    if out_ptr[-1] >= 2**31:
+        raise ValueError("too many nonzeros for int32 row_ptr")
+    return out_ptr.astype(np.int32), (keys % n).astype(np.int32)
+
+
 def workload(name: str) -> Workload:
     """Build one of the named synthetic workloads (see module docstring)."""
+    if name.startswith("rmat") and name.endswith("_sym"):
+        scale = int(name[4:-4])
+        rp, cl = rmat_pattern(scale, 16, 0.57, 0.19, 0.19, seed=scale)
+        n = 1 << scale
+        row_ptr, col = symmetrize_pattern(rp, cl, n)
+        del rp, cl
+        meta = {"generator": "rmat_sym", "scale": scale, "edge_factor": 16,
+                "abc": [0.57, 0.19, 0.19], "seed": scale, "x_true_seed": scale,
+                "x_true_stream": STREAM_XTRUE}
+        return Workload(row_ptr=row_ptr, col=col, values=np.ones(len(col)), n_rows=n, n_cols=n,
+                        nnz=len(col), x=uniform(scale, STREAM_XTRUE, n, -1.0, 1.0), meta=meta)
     if name.startswith("chung_lu_multi"):
         count = int(name[len("chung_lu_multi"):] or 256)
         row_ptr, col, graph_ptr = chung_lu_multi(count)

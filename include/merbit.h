@@ -39,7 +39,9 @@ typedef enum {
     MERBIT_ENOMEM = -2,       /* device allocation failed                      */
     MERBIT_EHIP = -3,         /* a HIP runtime call failed (message has it)    */
     MERBIT_EUNSUPPORTED = -4, /* dtype / sigma / block size not built          */
-    MERBIT_NOT_CONVERGED = 1  /* merbit_pagerank reached max_iter above tol    */
+    MERBIT_NOT_CONVERGED = 1, /* an iterative driver reached max_iter above tol */
+    MERBIT_BREAKDOWN = 2      /* BiCGSTAB: rho = (r^, r) became 0 (or the
+                                 residual non-finite) before convergence       */
 } merbit_status;
 
 typedef enum { MERBIT_F32 = 0, MERBIT_F64 = 1 } merbit_dtype;
@@ -288,6 +290,27 @@ int merbit_column_scale(int dtype, int64_t nnz, const int32_t* col, const void* 
 int merbit_pagerank_adjoint(merbit_plan* plan, merbit_plan* plan_t, double alpha, double tol,
                             int max_iter, int check_every, const void* g, void* lambda_inout,
                             int* iters_out, double* resid_out, void* stream);
+
+/* ------------------------------------------------------------- BiCGSTAB -- */
+
+/* Solve A x = b with unpreconditioned BiCGSTAB (van der Vorst 1992), the
+ * second iterative workload of Sec. 5.5.2, on the plan's square matrix.  Two
+ * fused SpMVs per iteration (dual output buffers, no resets) and five vector
+ * kernels whose dot products are reduced deterministically in double.
+ *   b          device [n], plan dtype
+ *   x_inout    device [n], plan dtype: x_0 in, solution out (not aliased with b)
+ *   tol        stop when ||r||_2 / ||b||_2 < tol, r the updated residual
+ *              (= b - A x in exact arithmetic), tested before the first
+ *              iteration and then every check_every iterations; tol <= 0
+ *              runs exactly max_iter iterations
+ *   iters_out  host, optional: iterations run
+ *   resid_out  host, optional: ||r|| / ||b|| at the last test
+ * Returns MERBIT_OK (converged), MERBIT_NOT_CONVERGED (max_iter reached) or
+ * MERBIT_BREAKDOWN (rho = 0 or a non-finite residual at a test; x then holds
+ * the last iterate).  Iteration chunks are recorded in HIP graphs as for
+ * PageRank.  Synchronises `stream`. */
+int merbit_bicgstab(merbit_plan* plan, const void* b, void* x_inout, double tol, int max_iter,
+                    int check_every, int* iters_out, double* resid_out, void* stream);
 
 /* ------------------------------------------------------------ autotuner -- */
 

@@ -2,6 +2,7 @@
 // checks, dispatch to the kernels, PageRank driver loop, error reporting.
 #include <hip/hip_runtime.h>
 
+#include <math.h>
 #include <stdint.h>
 #include <stdio.h>
 #include <string.h>
@@ -11,6 +12,7 @@
 #include <vector>
 
 #include "../../include/merbit.h"
+
 #include "merbit_internal.hpp"
 
 using namespace merbit;
@@ -66,6 +68,10 @@ struct merbit_plan {
   double* multi_part = nullptr;
   double* multi_gsum[2] = {nullptr, nullptr};
   int32_t multi_chunks = 0;
+  // BiCGSTAB state: r, r^, p, v (two), s, t; pair arrays of the dot products
+  void* bvec[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* bpart[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int bicg_G = 0;
   // HIP graphs of iteration chunks (the PageRank drivers); a graph holds the
   // pointers and scalars it was captured with, so any change of a captured
   // buffer bumps `generation` and drops the graphs
@@ -122,7 +128,9 @@ static void plan_free_all(merbit_plan* p) {
                   p->colx, p->x_hot, p->pbuf[0], p->pbuf[1], p->pbuf[2], p->ppart,
                   p->psums[0], p->psums[1], p->psrc, p->multi_chunk_row,
                   p->multi_chunk_graph, p->multi_chunk_ptr, p->multi_gsize, p->multi_part,
-                  p->multi_gsum[0], p->multi_gsum[1]};
+                  p->multi_gsum[0], p->multi_gsum[1], p->bvec[0], p->bvec[1], p->bvec[2],
+                  p->bvec[3], p->bvec[4], p->bvec[5], p->bvec[6], p->bpart[0], p->bpart[1],
+                  p->bpart[2], p->bpart[3], p->bpart[4], p->bpart[5], p->bpart[6]};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& ev : p->events) {
@@ -184,7 +192,8 @@ static int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_
   return MERBIT_OK;
 }
 
-enum { kLoopPageRank = 1, kLoopPersonalized = 2, kLoopMulti = 3, kLoopAdjoint = 4 };
+enum { kLoopPageRank = 1, kLoopPersonalized = 2, kLoopMulti = 3, kLoopAdjoint = 4,
+       kLoopBicgstab = 5 };
 
 // Enqueue one chunk of iterations on `st`.  The first time a chunk with this
 // key is seen, `enqueue` is recorded on the plan's capture stream into a HIP
@@ -1330,6 +1339,133 @@ int merbit_pagerank_adjoint(merbit_plan* p, merbit_plan* pt, double alpha, doubl
   if (iters_out) *iters_out = t;
   if (resid_out) *resid_out = resid;
   return (tol > 0.0 && !converged) ? MERBIT_NOT_CONVERGED : MERBIT_OK;
+}
+
+// ------------------------------------------------------------ BiCGSTAB --
+
+int merbit_bicgstab(merbit_plan* p, const void* b, void* x_inout, double tol, int max_iter,
+                    int check_every, int* iters_out, double* resid_out, void* stream) {
+  if (iters_out) *iters_out = 0;
+  if (resid_out) *resid_out = 0.0;
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->n_rows != p->n_cols) return fail(MERBIT_EINVAL, "BiCGSTAB needs a square matrix");
+  if (max_iter < 0) return fail(MERBIT_EINVAL, "max_iter < 0");
+  if (p->n_rows == 0) return MERBIT_OK;
+  if (!b || !x_inout) return fail(MERBIT_EINVAL, "b or x is NULL");
+  if (b == x_inout) return fail(MERBIT_EINVAL, "b and x alias");
+  if (check_every <= 0) check_every = 10;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const int64_t n = p->n_rows;
+  if (!p->bvec[0]) {
+    for (int k = 0; k < 7; ++k) HIP_TRY(hipMalloc(&p->bvec[k], vsize(p->dtype) * (size_t)n));
+    p->bicg_G = bicg_grid(n);
+    for (int k = 0; k < 7; ++k)
+      HIP_TRY(hipMalloc(&p->bpart[k], sizeof(double) * 2 * (size_t)p->bicg_G));
+  }
+  // bvec: 0 r, 1 r^, 2 p, 3 v (even iterations), 4 v (odd), 5 s, 6 t
+  // bpart: 0/1 (r^.r, r.r) by parity, 2/3 (r^.v, 0), 4/5 ((t,s), (t,t)), 6 (b.b, 0)
+  BicgArgs a;
+  memset(&a, 0, sizeof a);
+  a.n = n;
+  a.G = p->bicg_G;
+  a.b = b;
+  a.x = x_inout;
+  a.r = p->bvec[0];
+  a.rh = p->bvec[1];
+  a.p = p->bvec[2];
+  a.s = p->bvec[5];
+  a.t = p->bvec[6];
+  // r_0 = b - A x_0 (t holds A x_0; the launch leaves v_even zero at the
+  // boundary rows for iteration 0)
+  HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->chunk_num, p->unit_tiles, a.t,
+                               st));
+  int rc = run_fused(p, x_inout, a.t, p->bvec[3], st);
+  if (rc != MERBIT_OK) return rc;
+  a.pa_next = p->bpart[0];
+  a.pb_norm = p->bpart[6];
+  HIP_TRY(launch_bicg(p->dtype, a, kBicgInit, st));
+  std::vector<double> host(4 * (size_t)p->bicg_G);
+  HIP_TRY(hipMemcpyAsync(host.data(), p->bpart[6], sizeof(double) * 2 * p->bicg_G,
+                         hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(host.data() + 2 * p->bicg_G, p->bpart[0],
+                         sizeof(double) * 2 * p->bicg_G, hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  double bb = 0.0, rr = 0.0;
+  for (int k = 0; k < p->bicg_G; ++k) {
+    bb += host[2 * (size_t)k];
+    rr += host[2 * ((size_t)p->bicg_G + k) + 1];
+  }
+  const double bnorm = bb > 0.0 ? std::sqrt(bb) : 1.0;
+  double rel = std::sqrt(rr) / bnorm;
+  if (resid_out) *resid_out = rel;
+  p->last_stream = st;
+  if (tol > 0.0 && rel < tol) return MERBIT_OK;
+  int t = 0;
+  int status = MERBIT_NOT_CONVERGED;
+  while (t < max_iter) {
+    int len = check_every - t % check_every;
+    if (len > max_iter - t) len = max_iter - t;
+    const int t0 = t;
+    auto enqueue = [&](hipStream_t s) -> int {
+      for (int i = 0; i < len; ++i) {
+        const int it = t0 + i, c = it & 1;
+        BicgArgs q = a;
+        q.first = it == 0;
+        q.pa_cur = p->bpart[c];
+        q.pa_prev = p->bpart[c ^ 1];
+        q.pb_prev = p->bpart[2 + (c ^ 1)];
+        q.pc_prev = p->bpart[4 + (c ^ 1)];
+        q.pb_cur = p->bpart[2 + c];
+        q.pc_cur = p->bpart[4 + c];
+        q.pa_next = p->bpart[c ^ 1];
+        void* v_cur = p->bvec[3 + c];
+        void* v_prev = p->bvec[3 + (c ^ 1)];
+        q.v = v_prev;
+        HIP_TRY(launch_bicg(p->dtype, q, kBicgUpdateP, s));
+        int r = run_fused(p, q.p, v_cur, q.t, s);  // v = A p; clears t's boundary rows
+        if (r != MERBIT_OK) return r;
+        q.v = v_cur;
+        HIP_TRY(launch_bicg(p->dtype, q, kBicgDot1, s));
+        HIP_TRY(launch_bicg(p->dtype, q, kBicgUpdateS, s));
+        r = run_fused(p, q.s, q.t, v_prev, s);  // t = A s; clears v_prev for it + 1
+        if (r != MERBIT_OK) return r;
+        HIP_TRY(launch_bicg(p->dtype, q, kBicgDot2, s));
+        HIP_TRY(launch_bicg(p->dtype, q, kBicgUpdateXR, s));
+      }
+      return MERBIT_OK;
+    };
+    rc = len == check_every ? run_chunk(p, kLoopBicgstab, t0 & 1, t0 == 0, len, 0, x_inout, 0.0,
+                                        enqueue, st, b)
+                            : enqueue(st);
+    if (rc != MERBIT_OK) return rc;
+    t += len;
+    if (tol > 0.0 || t == max_iter) {
+      HIP_TRY(hipMemcpyAsync(host.data(), p->bpart[t & 1], sizeof(double) * 2 * p->bicg_G,
+                             hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      double rho = 0.0;
+      rr = 0.0;
+      for (int k = 0; k < p->bicg_G; ++k) {
+        rho += host[2 * (size_t)k];
+        rr += host[2 * (size_t)k + 1];
+      }
+      rel = std::sqrt(rr) / bnorm;
+      if (resid_out) *resid_out = rel;
+      if (tol > 0.0 && rel < tol) {
+        status = MERBIT_OK;
+        break;
+      }
+      if (!std::isfinite(rel) || (tol > 0.0 && rho == 0.0)) {
+        status = MERBIT_BREAKDOWN;
+        break;
+      }
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  p->last_stream = st;
+  if (iters_out) *iters_out = t;
+  if (tol <= 0.0 && status == MERBIT_NOT_CONVERGED) status = MERBIT_OK;
+  return status;
 }
 
 int merbit_profile_enable(merbit_plan* p, int enable) {

@@ -288,6 +288,20 @@ hipError_t launch_adj_update(int dtype, const void* y, const void* lam_old, void
                              const double* part_in, int n_in, double* part_out, int grid,
                              hipStream_t st);
 
+// BiCGSTAB.
+enum { kBicgInit = 0, kBicgUpdateP, kBicgDot1, kBicgUpdateS, kBicgDot2, kBicgUpdateXR };
+struct BicgArgs {
+  int64_t n;
+  int G;       // blocks of every vector kernel = pairs per reduction
+  int first;   // iteration 0: p = r
+  const void* b;
+  void *x, *r, *rh, *p, *v, *s, *t;
+  const double *pa_cur, *pa_prev, *pb_prev, *pc_prev;
+  double *pb_cur, *pc_cur, *pa_next, *pb_norm;
+};
+int bicg_grid(int64_t n);
+hipError_t launch_bicg(int dtype, const BicgArgs& a, int stage, hipStream_t st);
+
 // Batched forms.
 struct MultiTables {  // device row-chunk tables of a block-diagonal matrix
   const int32_t* chunk_row;    // [n_chunks + 1]

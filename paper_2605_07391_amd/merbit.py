@@ -15,14 +15,14 @@ import torch  # imported first so that libmerbit binds to torch's HIP runtime
 _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmerbit.so")
 _lib = None
 
-OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, NOT_CONVERGED = 0, -1, -2, -3, -4, 1
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, NOT_CONVERGED, BREAKDOWN = 0, -1, -2, -3, -4, 1, 2
 F32, F64 = 0, 1
 EXPORTED = ("merbit_opts_init", "merbit_plan_create", "merbit_plan_set_values", "merbit_plan_info",
             "merbit_plan_export", "merbit_spmv", "merbit_spmv_dual", "merbit_zero_boundary",
             "merbit_pagerank", "merbit_spmm", "merbit_spmm_dual", "merbit_spmm_zero_boundary",
             "merbit_pagerank_personalized", "merbit_pagerank_multi", "merbit_transpose",
             "merbit_sddmm", "merbit_gather_values", "merbit_column_scale",
-            "merbit_pagerank_adjoint", "merbit_tune",
+            "merbit_pagerank_adjoint", "merbit_bicgstab", "merbit_tune",
             "merbit_profile_enable", "merbit_profile_read",
             "merbit_plan_destroy", "merbit_last_error", "merbit_version")
 
@@ -94,6 +94,8 @@ def load():
     lib.merbit_column_scale.argtypes = [i32, i64, vp, vp, vp, vp, vp, vp]
     lib.merbit_pagerank_adjoint.argtypes = [vp, vp, dbl, dbl, i32, i32, vp, vp,
                                             ctypes.POINTER(i32), ctypes.POINTER(dbl), vp]
+    lib.merbit_bicgstab.argtypes = [vp, vp, vp, dbl, i32, i32, ctypes.POINTER(i32),
+                                    ctypes.POINTER(dbl), vp]
     lib.merbit_tune.argtypes = [i64, i64, i64, vp, vp, vp, i32, vp, i32, vp, i32, i32,
                                 ctypes.POINTER(Opts), vp, vp]
     lib.merbit_profile_enable.argtypes = [vp, i32]
@@ -108,7 +110,7 @@ def load():
                  "merbit_spmm_zero_boundary", "merbit_pagerank_personalized",
                  "merbit_pagerank_multi", "merbit_transpose", "merbit_sddmm",
                  "merbit_gather_values", "merbit_column_scale", "merbit_pagerank_adjoint",
-                 "merbit_tune", "merbit_profile_enable",
+                 "merbit_bicgstab", "merbit_tune", "merbit_profile_enable",
                  "merbit_profile_read"):
         getattr(lib, name).restype = ctypes.c_int
     _lib = lib
@@ -400,6 +402,26 @@ class Plan:
             int(check_every), _dev(g, self.dtype, "g"), _dev(lam, self.dtype, "lambda"),
             ctypes.byref(it), ctypes.byref(res), _stream(stream)), allow=(OK, NOT_CONVERGED))
         return it.value, res.value, rc == OK
+
+    # -- BiCGSTAB -----------------------------------------------------------
+    def bicgstab(self, b: torch.Tensor, x: torch.Tensor, tol: float = 1e-10,
+                 max_iter: int = 20000, check_every: int = 10, stream=None):
+        """Solve A x = b in place on x (x_0 in).  Returns (iterations,
+        ||r|| / ||b|| at the last test, status) with status one of
+        "converged", "iteration cap", "breakdown"."""
+        if b.numel() != self.n_rows or x.numel() != self.n_rows:
+            raise ValueError("b / x length mismatch")
+        it = ctypes.c_int()
+        res = ctypes.c_double()
+        rc = _check(load().merbit_bicgstab(self._handle(), _dev(b, self.dtype, "b"),
+                                           _dev(x, self.dtype, "x"), float(tol), int(max_iter),
+                                           int(check_every), ctypes.byref(it), ctypes.byref(res),
+                                           _stream(stream)), allow=(OK, NOT_CONVERGED, BREAKDOWN))
+        if rc == OK:
+            status = "converged" if tol > 0 else "done"
+        else:
+            status = {NOT_CONVERGED: "iteration cap", BREAKDOWN: "breakdown"}[rc]
+        return it.value, res.value, status
 
     # -- timing -------------------------------------------------------------
     def profile_enable(self, on: bool = True):

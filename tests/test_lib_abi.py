@@ -90,6 +90,7 @@ def test_argument_errors_without_gpu():
     assert lib.merbit_column_scale(1, 1, None, vp(8), None, vp(8), vp(8), None) == mb.EINVAL
     assert lib.merbit_pagerank_adjoint(None, None, 0.85, 0.0, 1, 1, None, None, None, None,
                                        None) == mb.EINVAL
+    assert lib.merbit_bicgstab(None, None, None, 1e-10, 1, 1, None, None, None) == mb.EINVAL
     # tuner
     assert lib.merbit_tune(1, 1, 0, vp(8), None, None, 0, None, 0, None, 0, 5, None, None,
                            None) == mb.EINVAL
