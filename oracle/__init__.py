@@ -15,6 +15,10 @@ for Iterative Workloads") it follows.  Functions and their pins:
 * ``plan`` (Sec. 4.1) -- pinned by the worked example of Sec. 4.1.1, by the
   closed forms for tile_num / lane_num / field widths, by invariants and by
   ``plan_replay`` reproducing ``spmv`` bit for bit.
+* ``plan64`` / ``plan_replay64`` (the same TILE with 64-bit descriptors,
+  sigma up to 40) -- pinned by the brute-force TILE built from the step
+  string, equality with ``plan`` for sigma <= 12, the fit condition and the
+  replay reproducing ``spmv`` bit for bit.
 * ``pagerank`` (Sec. 5.5.1) -- pinned by closed-form cases, by a dense direct
   solve of the stationary equation and by the mass / contraction invariants.
 * ``spmm`` (Sec. 3.1 per column) -- pinned by dense brute force.
@@ -88,6 +92,12 @@ def _load():
     lib.or_plan_replay.restype = c_int
     lib.or_plan_replay.argtypes = [c_i64, c_i64, c_int, c_int, _i32, _u32, _u32, _i32, _f64,
                                    _f64, _f64, ctypes.c_void_p]
+    _u64 = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+    lib.or_plan64.restype = c_int
+    lib.or_plan64.argtypes = [c_i64, _i32, c_int, c_int, _i32, _u32, _u64]
+    lib.or_plan_replay64.restype = c_int
+    lib.or_plan_replay64.argtypes = [c_i64, c_i64, c_int, c_int, _i32, _u32, _u64, _i32, _f64,
+                                     _f64, _f64]
     lib.or_spmm.restype = None
     lib.or_spmm.argtypes = [c_i64, _i32, _i32, _f64, c_int, _f64, _f64]
     lib.or_pagerank_teleport.restype = c_int
@@ -182,6 +192,40 @@ def plan(row_ptr, omega: int, sigma: int):
     if rc != 0:
         raise ValueError(f"descriptor does not fit: 2*{offset_bits(omega, sigma)}+{sigma} > 32")
     return tile_x, tile_y, lane_desc[:lanes]
+
+
+def plan64(row_ptr, omega: int, sigma: int):
+    """TILE with 64-bit lane descriptors (fit condition 2b + sigma <= 64):
+    (tile_x int32[T+1], tile_y uint32[T+1], lane_desc uint64[lanes])."""
+    row_ptr = _i32a(row_ptr)
+    n = len(row_ptr) - 1
+    T, lanes = plan_sizes(n, int(row_ptr[-1]), omega, sigma)
+    tile_x = np.empty(T + 1, np.int32)
+    tile_y = np.empty(T + 1, np.uint32)
+    lane_desc = np.empty(max(lanes, 1), np.uint64)
+    rc = _load().or_plan64(n, row_ptr, omega, sigma, tile_x, tile_y, lane_desc)
+    if rc != 0:
+        raise ValueError(f"descriptor does not fit: 2*{offset_bits(omega, sigma)}+{sigma} > 64")
+    return tile_x, tile_y, lane_desc[:lanes]
+
+
+def plan_replay64(row_ptr, col, values, x, tile, omega: int, sigma: int):
+    """Decode + replay of a 64-bit-descriptor TILE; returns y."""
+    tile_x, tile_y, lane_desc = tile
+    row_ptr = _i32a(row_ptr)
+    n = len(row_ptr) - 1
+    m = int(row_ptr[-1])
+    y = np.empty(max(n, 1), np.float64)
+    rc = _load().or_plan_replay64(n, m, omega, sigma, _i32a(tile_x),
+                                  np.ascontiguousarray(tile_y, np.uint32),
+                                  np.ascontiguousarray(lane_desc if len(lane_desc) else [0],
+                                                       np.uint64),
+                                  _i32a(col) if m else np.zeros(1, np.int32),
+                                  _f64a(values) if m else np.zeros(1),
+                                  _f64a(x) if len(x) else np.zeros(1), y)
+    if rc != 0:
+        raise ValueError(f"plan replay failed ({rc})")
+    return y[:n]
 
 
 def unpack_desc(lane_desc, omega: int, sigma: int):

@@ -13,6 +13,7 @@
  *   or_merge_search  the diagonal binary search of Algorithm 1 (merge_search)
  *   or_plan          the TILE arrays of Sec. 4.1.1 / 4.1.2 from one sequential walk
  *   or_plan_replay   decode TILE (Sec. 4.1.1 coordinate formula) and redo y = A x
+ *   or_plan64 / or_plan_replay64   the same with 64-bit lane descriptors
  *   or_pagerank      power method of Sec. 5.5.1, damping alpha, dangling mass
  *                    spread uniformly
  *   or_spmm          Sec. 3.1 applied to every column of a multi-vector
@@ -162,6 +163,87 @@ int or_plan(int64_t n_rows, const int32_t* row_ptr, int omega, int sigma,
     (void)lane_num;
     tile_x[tile_num] = (int32_t)m;
     tile_y[tile_num] = (uint32_t)n_rows;
+    return 0;
+}
+
+/* The same TILE with 64-bit lane descriptors: identical walk and field
+ * layout (flags << 2b | y_off << b | x_off), fit condition 2b + sigma <= 64,
+ * which admits sigma up to 40 at omega = 64.  For sigma <= 12 every
+ * descriptor has the value or_plan gives.  Returns 0 or -1 (does not fit). */
+int or_plan64(int64_t n_rows, const int32_t* row_ptr, int omega, int sigma,
+              int32_t* tile_x, uint32_t* tile_y, uint64_t* lane_desc) {
+    const int64_t m = row_ptr[n_rows];
+    const int64_t L = m + n_rows;
+    const int64_t ws = (int64_t)omega * sigma;
+    const int64_t tile_num = (L + ws - 1) / ws;
+    const int b = or_offset_bits(omega, sigma);
+    if (2 * b + sigma > 64) return -1;
+
+    int64_t x = 0, y = 0, tx = 0, ty = 0;
+    int tile_has_down = 0;
+    uint64_t flags = 0, lane_x_off = 0, lane_y_off = 0;
+    for (int64_t d = 0; d < L; ++d) {
+        if (d % ws == 0) {
+            tx = x;
+            ty = y;
+            tile_has_down = 0;
+        }
+        if (d % sigma == 0) {
+            lane_x_off = (uint64_t)(x - tx);
+            lane_y_off = (uint64_t)(y - ty);
+            flags = 0;
+        }
+        const int k = (int)(d % sigma);
+        if (x < row_ptr[y + 1]) {
+            ++x;
+        } else {
+            ++y;
+            flags |= (uint64_t)1 << k;
+            tile_has_down = 1;
+        }
+        if (k == sigma - 1 || d == L - 1)
+            lane_desc[d / sigma] = (flags << (2 * b)) | (lane_y_off << b) | lane_x_off;
+        if ((d + 1) % ws == 0 || d == L - 1) {
+            const int64_t i = d / ws;
+            tile_x[i] = (int32_t)tx;
+            tile_y[i] = (uint32_t)ty | (tile_has_down ? 0u : 0x80000000u);
+        }
+    }
+    tile_x[tile_num] = (int32_t)m;
+    tile_y[tile_num] = (uint32_t)n_rows;
+    return 0;
+}
+
+/* or_plan_replay for 64-bit descriptors (same decode, wider words). */
+int or_plan_replay64(int64_t n_rows, int64_t m, int omega, int sigma,
+                     const int32_t* tile_x, const uint32_t* tile_y, const uint64_t* lane_desc,
+                     const int32_t* col, const double* values, const double* xv, double* y) {
+    const int64_t L = m + n_rows;
+    const int64_t lane_num = (L + sigma - 1) / sigma;
+    const int b = or_offset_bits(omega, sigma);
+    const uint64_t fmask = ((uint64_t)1 << b) - 1u;
+    long double* acc = (long double*)calloc((size_t)(n_rows > 0 ? n_rows : 1), sizeof(long double));
+    if (!acc) return -2;
+    for (int64_t j = 0; j < lane_num; ++j) {
+        const int64_t i = j / omega;
+        const uint64_t desc = lane_desc[j];
+        int64_t x = (int64_t)tile_x[i] + (int64_t)(desc & fmask);
+        int64_t yy = (int64_t)(tile_y[i] & 0x7FFFFFFFu) + (int64_t)((desc >> b) & fmask);
+        const uint64_t flags = desc >> (2 * b);
+        const int64_t steps = (L - j * sigma) < sigma ? (L - j * sigma) : sigma;
+        for (int64_t k = 0; k < steps; ++k) {
+            if ((flags >> k) & 1u) {
+                if (yy >= n_rows) { free(acc); return -3; }
+                ++yy;
+            } else {
+                if (x >= m || yy >= n_rows) { free(acc); return -4; }
+                acc[yy] += (long double)values[x] * (long double)xv[col[x]];
+                ++x;
+            }
+        }
+    }
+    for (int64_t r = 0; r < n_rows; ++r) y[r] = (double)acc[r];
+    free(acc);
     return 0;
 }
 

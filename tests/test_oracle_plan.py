@@ -51,7 +51,7 @@ def plan_from_steps(row_ptr, omega, sigma):
         tile_y[i] = ys[s] | (0 if steps[s:e].any() else 1 << 31)
     tile_x[T] = row_ptr[-1]
     tile_y[T] = len(row_ptr) - 1
-    desc = np.zeros(lanes, np.int64)
+    desc = np.zeros(lanes, np.uint64)  # up to 64-bit descriptors
     for j in range(lanes):
         s = j * sigma
         t0 = (j // omega) * omega * sigma
@@ -235,3 +235,43 @@ def test_tile_memory_formula():
         formula = oracle.tile_mem_bytes(n, m, OMEGA, sigma, r_f)
         assert abs(formula - actual) <= 4 * OMEGA
     assert oracle.smem_bytes(256, 12, 4) == 257 * 12 * 4
+
+
+# ------------------------------------------------- 64-bit lane descriptors --
+
+@pytest.mark.parametrize("sigma", [1, 7, 12, 13, 16, 24, 33, 40])
+@pytest.mark.parametrize("name,row_ptr", CASES + _random_cases())
+def test_plan64_matches_step_string(name, row_ptr, sigma):
+    tx, ty, d = oracle.plan64(row_ptr, OMEGA, sigma)
+    bx, by, bd = plan_from_steps(row_ptr, OMEGA, sigma)
+    assert np.array_equal(tx, bx) and np.array_equal(ty.astype(np.int64), by)
+    assert np.array_equal(d.astype(np.uint64), bd.astype(np.uint64))
+    if sigma <= 12:  # the 32-bit plan holds the same values
+        t32 = oracle.plan(row_ptr, OMEGA, sigma)
+        assert np.array_equal(t32[2].astype(np.uint64), d)
+    b = oracle.offset_bits(OMEGA, sigma)
+    assert 2 * b + sigma <= 64 and np.all((d >> np.uint64(2 * b)) < (np.uint64(1) << np.uint64(sigma)))
+
+
+def test_plan64_fit_condition_and_replay():
+    # sigma 40 is the largest that fits: b = 12, 24 + 40 = 64; sigma 41 does not
+    assert oracle.offset_bits(64, 40) == 12 and oracle.offset_bits(64, 41) == 12
+    with pytest.raises(ValueError):
+        oracle.plan64(np.array([0, 1], np.int32), OMEGA, 41)
+    with pytest.raises(ValueError):
+        oracle.plan(np.array([0, 1], np.int32), OMEGA, 13)
+    rp, col, vals = graphgen.random_csr(700, 500, 0.03, 11, empty_frac=0.4, long_rows=(9, 300))
+    x = np.random.default_rng(11).uniform(-1, 1, 500)
+    ref = oracle.spmv(rp, col, vals, x)
+    for sigma in (16, 24, 40):
+        y = oracle.plan_replay64(rp, col, vals, x, oracle.plan64(rp, OMEGA, sigma), OMEGA, sigma)
+        assert np.array_equal(y, ref)
+    # a corrupted descriptor (one flag bit flipped) is rejected or changes y
+    t = oracle.plan64(rp, OMEGA, 24)
+    bad = (t[0], t[1], t[2].copy())
+    bad[2][3] ^= np.uint64(1) << np.uint64(2 * oracle.offset_bits(OMEGA, 24))
+    try:
+        y = oracle.plan_replay64(rp, col, vals, x, bad, OMEGA, 24)
+        assert not np.array_equal(y, ref)
+    except ValueError:
+        pass
