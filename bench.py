@@ -79,11 +79,19 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
     torch.cuda.synchronize()
     tuning = None
     if tune:
-        # sigma and block size by measurement on this matrix (untimed)
+        # sigma and block size by measurement on this matrix (untimed); the
+        # 64-bit-descriptor kernels are swept too and reported beside it
         best, table = pkg.tune(r, c, v, n, reps=10, commit=commit, hot_columns=hot_columns)
         sigma, block_lanes = best["sigma"], best["block_lanes"]
+        best64, table64 = pkg.tune(r, c, v, n, reps=10, hot_columns=hot_columns, desc_bits=64,
+                                   block_lanes=[256, 512])
         tuning = {"best": best, "us_per_spmv": {f"s{a}_b{b}": round(t, 1)
-                                                for (a, b), t in table.items()}}
+                                                for (a, b), t in table.items()},
+                  "desc64": {"best": best64,
+                             "us_per_spmv": {f"s{a}_b{b}": round(t, 1)
+                                             for (a, b), t in table64.items()},
+                             "vs_32bit": round(min(t for t in table.values() if t > 0)
+                                               / min(t for t in table64.values() if t > 0), 3)}}
     # plan build, timed on its own (kernel + allocation of TILE)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()

@@ -83,7 +83,11 @@ typedef struct {
     int32_t eager_loops;   /* 0: the PageRank drivers record each chunk of iterations
                               between two convergence checks into a HIP graph on first
                               use and replay it; nonzero: launch every kernel directly  */
-    int32_t reserved;
+    int32_t desc_bits;     /* lane descriptor width: 0 or 32 (sigma <= 12), or 64
+                              (2 ceil(log2(64 sigma)) + sigma <= 64, sigma <= 40; wave
+                              commit only; built: FP32 sigma 16, 20, 24, FP64 14, 16,
+                              block_lanes 256 or 512).  SpMM and the adjoint pieces
+                              need 32-bit plans.                                        */
 } merbit_opts_t;
 
 typedef struct merbit_plan merbit_plan;
@@ -107,6 +111,8 @@ typedef struct {
                               partial sums (Sec. 4.3) + the hot x values               */
     int32_t commit;        /* merbit_commit of the plan                                 */
     double hot_coverage;   /* fraction of nonzeros whose column is hot                  */
+    int32_t desc_bits;     /* lane descriptor width: 32 or 64                           */
+    int32_t reserved;
 } merbit_plan_info_t;
 
 /* Fill *opts (host pointer) with the defaults. */
@@ -140,10 +146,12 @@ int merbit_plan_set_values(merbit_plan* plan, const void* values);
 int merbit_plan_info(merbit_plan* plan, merbit_plan_info_t* info);
 
 /* Copy TILE to host buffers (Sec. 4.1.1 layout).  Any output pointer may be
- * NULL; tile_x / tile_y need tile_num + 1 entries, lane_desc lane_num entries.
- * tile_num / lane_num (host, optional) receive the sizes.  Synchronous. */
+ * NULL; tile_x / tile_y need tile_num + 1 entries, lane_desc lane_num
+ * descriptors of desc_bits / 8 bytes each (uint32_t, or uint64_t for a 64-bit
+ * plan).  tile_num / lane_num (host, optional) receive the sizes.
+ * Synchronous. */
 int merbit_plan_export(merbit_plan* plan, int32_t* tile_x, uint32_t* tile_y,
-                       uint32_t* lane_desc, int64_t* tile_num, int64_t* lane_num);
+                       void* lane_desc, int64_t* tile_num, int64_t* lane_num);
 
 /* y <- A x (Sec. 4.2, Algorithm "MERBIT SpMV"), overwriting y whatever it
  * held.  x: device [n_cols], y: device [n_rows], both of the plan's dtype, not

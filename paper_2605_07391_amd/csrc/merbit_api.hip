@@ -30,6 +30,8 @@ struct merbit_plan {
   int32_t* tile_x = nullptr;
   uint32_t* tile_y = nullptr;
   uint32_t* lane_desc = nullptr;
+  uint64_t* lane_desc64 = nullptr;  // set instead of lane_desc for 64-bit descriptors
+  int desc_bits = 32;
   const int32_t* col = nullptr;
   const void* values = nullptr;
   hipStream_t last_stream = nullptr;
@@ -123,7 +125,7 @@ static void plan_free_all(merbit_plan* p) {
   (void)hipDeviceSynchronize();
   drop_graphs(p);
   if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-  void* bufs[] = {p->tile_x, p->tile_y, p->lane_desc, p->scratch, p->dmask, p->ybuf[0],
+  void* bufs[] = {p->tile_x, p->tile_y, p->lane_desc, p->lane_desc64, p->scratch, p->dmask, p->ybuf[0],
                   p->ybuf[1], p->xwork, p->partials[0], p->partials[1], p->hot_cols,
                   p->colx, p->x_hot, p->pbuf[0], p->pbuf[1], p->pbuf[2], p->ppart,
                   p->psums[0], p->psums[1], p->psrc, p->multi_chunk_row,
@@ -145,6 +147,7 @@ static SpmvArgs spmv_args(const merbit_plan* p, const void* x, void* y, void* z)
   a.tile_x = p->tile_x;
   a.tile_y = p->tile_y;
   a.lane_desc = p->lane_desc;
+  a.lane_desc64 = p->lane_desc64;
   a.col = p->hot_n > 0 ? p->colx : p->col;
   a.val = p->values;
   a.x = x;
@@ -183,7 +186,7 @@ static int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_
   }
   if (p->commit == MERBIT_COMMIT_WAVE)
     HIP_TRY(launch_spmv_wave(p->dtype, p->sigma, p->waves, p->hot_n > 0, p->hot_lds_bytes,
-                             spmv_args(p, x, y, z), st));
+                             spmv_args(p, x, y, z), st, p->desc_bits == 64));
   else
     HIP_TRY(launch_spmv(p->dtype, p->sigma, p->waves, p->hot_n > 0, p->hot_lds_bytes,
                         spmv_args(p, x, y, z), st));
@@ -259,7 +262,8 @@ static size_t static_lds_bytes(const merbit_plan* p) {
 }
 
 static bool kernel_supported(const merbit_plan* p, bool hot) {
-  return p->commit == MERBIT_COMMIT_WAVE ? spmv_wave_supported(p->dtype, p->sigma, p->waves, hot)
+  return p->commit == MERBIT_COMMIT_WAVE
+             ? spmv_wave_supported(p->dtype, p->sigma, p->waves, hot, p->desc_bits == 64)
                                          : spmv_supported(p->dtype, p->sigma, p->waves, hot);
 }
 
@@ -399,7 +403,8 @@ static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
     }
     p->hot_lds_bytes = vs * (size_t)p->hot_n;
     if (p->commit == MERBIT_COMMIT_WAVE)
-      HIP_TRY(spmv_wave_set_hot_lds(p->dtype, p->sigma, p->waves, p->hot_lds_bytes));
+      HIP_TRY(spmv_wave_set_hot_lds(p->dtype, p->sigma, p->waves, p->hot_lds_bytes,
+                                    p->desc_bits == 64));
     else
       HIP_TRY(spmv_set_hot_lds(p->dtype, p->sigma, p->waves, p->hot_lds_bytes));
   }
@@ -437,17 +442,27 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   if (nnz > 0 && n_rows == 0) return fail(MERBIT_EINVAL, "nonzeros without rows");
   if (sigma == 0) sigma = dtype == MERBIT_F32 ? 12 : 7;
   if (block_lanes == 0) block_lanes = commit == MERBIT_COMMIT_WAVE ? 512 : 256;
-  if (sigma < 1 || sigma > kMaxSigma)
-    return fail(MERBIT_EUNSUPPORTED, "sigma must be in 1..12");
+  const int desc_bits = opts.desc_bits == 0 ? 32 : opts.desc_bits;
+  if (desc_bits != 32 && desc_bits != 64) return fail(MERBIT_EINVAL, "desc_bits must be 32 or 64");
+  if (desc_bits == 64 && commit != MERBIT_COMMIT_WAVE)
+    return fail(MERBIT_EUNSUPPORTED, "64-bit descriptors need the wave commit kernel");
+  if (sigma < 1 || sigma > (desc_bits == 64 ? kMaxSigma64 : kMaxSigma))
+    return fail(MERBIT_EUNSUPPORTED,
+                desc_bits == 64 ? "sigma must be in 1..40" : "sigma must be in 1..12");
   const int bits = ceil_log2(kOmega * sigma);
-  if (2 * bits + sigma > 32) return fail(MERBIT_EUNSUPPORTED, "descriptor exceeds 32 bits");
+  if (2 * bits + sigma > desc_bits)
+    return fail(MERBIT_EUNSUPPORTED, "descriptor exceeds its width");
   if (block_lanes % kOmega != 0) return fail(MERBIT_EINVAL, "block_lanes % 64 != 0");
   const int waves = block_lanes / kOmega;
-  if (commit == MERBIT_COMMIT_WAVE ? !spmv_wave_supported(dtype, sigma, waves, false)
+  if (commit == MERBIT_COMMIT_WAVE ? !spmv_wave_supported(dtype, sigma, waves, false,
+                                                          desc_bits == 64)
                                    : !spmv_supported(dtype, sigma, waves, false))
-    return fail(MERBIT_EUNSUPPORTED, commit == MERBIT_COMMIT_WAVE
-                                         ? "block_lanes must be 256, 512 or 1024"
-                                         : "block_lanes must be 128, 256, 512 or 1024");
+    return fail(MERBIT_EUNSUPPORTED,
+                desc_bits == 64 ? (dtype == MERBIT_F32
+                                       ? "64-bit descriptors: sigma 16, 20 or 24, 256 or 512 lanes"
+                                       : "64-bit descriptors: sigma 14 or 16, 256 or 512 lanes")
+                : commit == MERBIT_COMMIT_WAVE ? "block_lanes must be 256, 512 or 1024"
+                                               : "block_lanes must be 128, 256, 512 or 1024");
   if (opts.blocks_per_cu < 0) return fail(MERBIT_EINVAL, "blocks_per_cu < 0");
 
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -463,6 +478,7 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   p->commit = commit;
   p->blocks_per_cu_req = opts.blocks_per_cu;
   p->eager_loops = opts.eager_loops != 0;
+  p->desc_bits = desc_bits;
   p->col = col_ind;
   p->values = values;
   p->last_stream = st;
@@ -485,7 +501,12 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   CREATE_TRY(hipMalloc(&p->scratch, 64));
   CREATE_TRY(hipMalloc(&p->tile_x, sizeof(int32_t) * (size_t)(p->tile_num + 1)));
   CREATE_TRY(hipMalloc(&p->tile_y, sizeof(uint32_t) * (size_t)(p->tile_num + 1)));
-  CREATE_TRY(hipMalloc(&p->lane_desc, sizeof(uint32_t) * (size_t)(p->lane_num > 0 ? p->lane_num : 1)));
+  if (desc_bits == 64)
+    CREATE_TRY(hipMalloc(&p->lane_desc64,
+                         sizeof(uint64_t) * (size_t)(p->lane_num > 0 ? p->lane_num : 1)));
+  else
+    CREATE_TRY(hipMalloc(&p->lane_desc,
+                         sizeof(uint32_t) * (size_t)(p->lane_num > 0 ? p->lane_num : 1)));
 
   if (validate && (n_rows > 0 || nnz > 0)) {
     CREATE_TRY(hipMemsetAsync(p->scratch, 0, 64, st));
@@ -519,6 +540,7 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
     pa.tile_x = p->tile_x;
     pa.tile_y = p->tile_y;
     pa.lane_desc = p->lane_desc;
+    pa.lane_desc64 = p->lane_desc64;
     CREATE_TRY(launch_plan(pa, st));
   }
 #undef CREATE_TRY
@@ -561,6 +583,7 @@ int merbit_plan_info(merbit_plan* p, merbit_plan_info_t* info) {
   info->offset_bits = p->bits;
   info->dtype = p->dtype;
   info->lds_bytes = (int32_t)(static_lds_bytes(p) + p->hot_lds_bytes);
+  info->desc_bits = p->desc_bits;
   if (p->tile_num > 0) {
     hipStream_t st = p->last_stream;
     unsigned long long cnt = 0;
@@ -573,7 +596,7 @@ int merbit_plan_info(merbit_plan* p, merbit_plan_info_t* info) {
   return MERBIT_OK;
 }
 
-int merbit_plan_export(merbit_plan* p, int32_t* tile_x, uint32_t* tile_y, uint32_t* lane_desc,
+int merbit_plan_export(merbit_plan* p, int32_t* tile_x, uint32_t* tile_y, void* lane_desc,
                        int64_t* tile_num, int64_t* lane_num) {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (tile_num) *tile_num = p->tile_num;
@@ -587,7 +610,9 @@ int merbit_plan_export(merbit_plan* p, int32_t* tile_x, uint32_t* tile_y, uint32
     HIP_TRY(hipMemcpy(tile_y, p->tile_y, sizeof(uint32_t) * (size_t)(p->tile_num + 1),
                       hipMemcpyDeviceToHost));
   if (lane_desc && p->lane_num > 0)
-    HIP_TRY(hipMemcpy(lane_desc, p->lane_desc, sizeof(uint32_t) * (size_t)p->lane_num,
+    HIP_TRY(hipMemcpy(lane_desc,
+                      p->desc_bits == 64 ? (const void*)p->lane_desc64 : (const void*)p->lane_desc,
+                      (size_t)(p->desc_bits / 8) * (size_t)p->lane_num,
                       hipMemcpyDeviceToHost));
   return MERBIT_OK;
 }
@@ -784,6 +809,8 @@ static int run_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t
 int merbit_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy, int k,
                 void* stream) {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->desc_bits != 32)
+    return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
   if (k < 1) return fail(MERBIT_EINVAL, "k < 1");
   if (ldx < k || ldy < k) return fail(MERBIT_EINVAL, "leading dimension < k");
   if (p->n_rows == 0) return MERBIT_OK;
@@ -802,6 +829,8 @@ int merbit_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy
 int merbit_spmm_dual(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy, void* Z,
                      int64_t ldz, int k, void* stream) {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->desc_bits != 32)
+    return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
   if (k < 1) return fail(MERBIT_EINVAL, "k < 1");
   if (ldx < k || ldy < k || ldz < k) return fail(MERBIT_EINVAL, "leading dimension < k");
   if (p->n_rows == 0) return MERBIT_OK;
@@ -855,6 +884,8 @@ int merbit_pagerank_personalized(merbit_plan* p, double alpha, double tol, int m
                                  int* iters_out, double* resid_out, void* stream) {
   if (iters_out) *iters_out = 0;
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->desc_bits != 32)
+    return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
   if (p->n_rows != p->n_cols) return fail(MERBIT_EINVAL, "PageRank needs a square matrix");
   if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(MERBIT_EINVAL, "alpha must be in [0, 1]");
   if (k < 1 || k > 64) return fail(MERBIT_EINVAL, "k must be in 1..64");
@@ -1188,6 +1219,8 @@ static TileRowsArgs tile_rows_args(const merbit_plan* p) {
 int merbit_transpose(merbit_plan* p, int32_t* rowT_ptr, int32_t* colT, int32_t* perm,
                      void* stream) {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->desc_bits != 32)
+    return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
   if (!rowT_ptr || (p->nnz > 0 && (!colT || !perm)))
     return fail(MERBIT_EINVAL, "output array is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1229,6 +1262,8 @@ int merbit_transpose(merbit_plan* p, int32_t* rowT_ptr, int32_t* colT, int32_t* 
 int merbit_sddmm(merbit_plan* p, const void* g, const void* x, double scale, void* out,
                  void* stream) {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->desc_bits != 32)
+    return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
   if (p->nnz == 0) return MERBIT_OK;
   if (!g || !x || !out) return fail(MERBIT_EINVAL, "g, x or out is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);

@@ -11,6 +11,7 @@ constexpr int kOmega = 64;                 // lanes per tile = CDNA wavefront si
 constexpr uint32_t kRowMask = 0x7FFFFFFFu; // tile_y: row index
 constexpr uint32_t kFastBit = 0x80000000u; // tile_y: long-row (single-row) tile mark
 constexpr int kMaxSigma = 12;              // 2 ceil(log2(64 sigma)) + sigma <= 32
+constexpr int kMaxSigma64 = 40;            // 2 ceil(log2(64 sigma)) + sigma <= 64
 constexpr int kHotHistBins = 65536;        // column-count histogram of the hot cache
 
 // ceil(log2(v)) for v >= 1: width of the x_offset / y_offset fields.
@@ -169,13 +170,15 @@ struct PlanArgs {
   int64_t tile_num;
   int32_t* tile_x;
   uint32_t* tile_y;
-  uint32_t* lane_desc;
+  uint32_t* lane_desc;      // 32-bit descriptors, or
+  uint64_t* lane_desc64;    // 64-bit descriptors (exactly one is set)
 };
 
 struct SpmvArgs {
   const int32_t* tile_x;
   const uint32_t* tile_y;
   const uint32_t* lane_desc;
+  const uint64_t* lane_desc64;  // 64-bit descriptor plans (wave kernel only)
   const int32_t* col;   // column stream: col_ind, or the recoded one with hot slots < 0
   const void* val;
   const void* x;
@@ -224,10 +227,11 @@ hipError_t launch_spmv(int dtype, int sigma, int waves, bool hot, size_t hot_lds
 // allow the hot variant to use `bytes` of dynamic LDS
 hipError_t spmv_set_hot_lds(int dtype, int sigma, int waves, size_t bytes);
 // wave-granular persistent kernel (commit unit = one tile)
-bool spmv_wave_supported(int dtype, int sigma, int waves, bool hot);
+bool spmv_wave_supported(int dtype, int sigma, int waves, bool hot, bool desc64 = false);
 hipError_t launch_spmv_wave(int dtype, int sigma, int waves, bool hot, size_t hot_lds_bytes,
-                            const SpmvArgs& a, hipStream_t st);
-hipError_t spmv_wave_set_hot_lds(int dtype, int sigma, int waves, size_t bytes);
+                            const SpmvArgs& a, hipStream_t st, bool desc64 = false);
+hipError_t spmv_wave_set_hot_lds(int dtype, int sigma, int waves, size_t bytes,
+                                 bool desc64 = false);
 
 // Hot-column cache.
 hipError_t hot_count_columns(const int32_t* col, int64_t nnz, int64_t n_cols, int32_t* counts,

@@ -5,7 +5,7 @@
 // thread finds its lane's start on the merge path by a binary search along
 // its diagonal j * sigma, takes the tile start from lane 0 of its wavefront,
 // walks its sigma steps recording a 1 bit per down step, packs the
-// descriptor, and the wavefront votes whether any of its lanes left the tile's
+// descriptor (32 or 64 bits wide), and the wavefront votes whether any of its lanes left the tile's
 // start row (if none did, the tile is a single-row "fast" tile and bit 31 of
 // tile_y is set).  Cost O(lane_num (log n + sigma)); the row_ptr reads are
 // served from L2 after the first probes.
@@ -57,7 +57,9 @@ __device__ __forceinline__ int32_t merge_search_rows(const int32_t* __restrict__
   return lo;
 }
 
-__global__ __launch_bounds__(256) void plan_kernel(PlanArgs a) {
+// D = uint32_t or uint64_t: the descriptor word (flags << 2b | y_off << b | x_off)
+template <typename D>
+__global__ __launch_bounds__(256) void plan_kernel(PlanArgs a, D* __restrict__ lane_desc) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int lid = threadIdx.x & (kOmega - 1);
   const int32_t L = a.nnz + a.n_rows;
@@ -69,20 +71,20 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanArgs a) {
     // lane of this wavefront is)
     const int32_t tx = __shfl(cx, 0, kOmega);
     const int32_t ty = __shfl(cy, 0, kOmega);
-    const uint32_t x_off = (uint32_t)(cx - tx);
-    const uint32_t y_off = (uint32_t)(cy - ty);
+    const D x_off = (D)(cx - tx);
+    const D y_off = (D)(cy - ty);
     const int32_t steps = (L - diag) < a.sigma ? (L - diag) : a.sigma;
-    uint32_t flags = 0;
+    D flags = 0;
     for (int32_t k = 0; k < steps; ++k) {
       if (cy >= a.n_rows) break;  // only reachable for a malformed row_ptr
       if (cx < a.row_ptr[cy + 1]) {
         ++cx;
       } else {
-        flags |= 1u << k;
+        flags |= (D)1 << k;
         ++cy;
       }
     }
-    a.lane_desc[j] = (flags << (2 * a.bits)) | (y_off << a.bits) | x_off;
+    lane_desc[j] = (flags << (2 * a.bits)) | (y_off << a.bits) | x_off;
     const unsigned long long active = __ballot(1);
     const unsigned long long stayed = __ballot(cy == ty);
     if (lid == 0) {
@@ -99,7 +101,12 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanArgs a) {
 hipError_t launch_plan(const PlanArgs& a, hipStream_t st) {
   const int64_t threads = a.lane_num + 1;
   const int64_t grid = (threads + 255) / 256;
-  hipLaunchKernelGGL(plan_kernel, dim3((unsigned)grid), dim3(256), 0, st, a);
+  if (a.lane_desc64)
+    hipLaunchKernelGGL(plan_kernel<uint64_t>, dim3((unsigned)grid), dim3(256), 0, st, a,
+                       a.lane_desc64);
+  else
+    hipLaunchKernelGGL(plan_kernel<uint32_t>, dim3((unsigned)grid), dim3(256), 0, st, a,
+                       a.lane_desc);
   return hipGetLastError();
 }
 

@@ -26,28 +26,40 @@
 
 namespace merbit {
 
-template <typename V, int SIGMA>
+// D: the descriptor word, uint32_t (sigma <= 12) or uint64_t (sigma <= 40)
+template <typename V, int SIGMA, typename D>
 struct WaveTile {
   int x_ws;
   int x_se;
   uint32_t tyw;
   int y_we;
-  uint32_t desc;
+  D desc;
   int cc[SIGMA];
   V vv[SIGMA];
 };
 
-template <typename V, int SIGMA>
+template <typename D>
+__device__ __forceinline__ D load_desc(const SpmvArgs& a, int j);
+template <>
+__device__ __forceinline__ uint32_t load_desc<uint32_t>(const SpmvArgs& a, int j) {
+  return a.lane_desc[j];
+}
+template <>
+__device__ __forceinline__ uint64_t load_desc<uint64_t>(const SpmvArgs& a, int j) {
+  return a.lane_desc64[j];
+}
+
+template <typename V, int SIGMA, typename D>
 __device__ __forceinline__ void wave_load_tile(const SpmvArgs& a, const int32_t* __restrict__ col,
                                                const V* __restrict__ val, int t, int lid,
-                                               WaveTile<V, SIGMA>& s) {
+                                               WaveTile<V, SIGMA, D>& s) {
   s.x_ws = a.tile_x[t];
   s.x_se = a.tile_x[t + 1] - s.x_ws;
   s.tyw = a.tile_y[t];
   s.y_we = (int)(a.tile_y[t + 1] & kRowMask);
   const bool normal = s.x_se > 0 && !(s.tyw & kFastBit);
   s.desc = 0;
-  if (normal) s.desc = a.lane_desc[min(t * kOmega + lid, a.lane_num - 1)];
+  if (normal) s.desc = load_desc<D>(a, min(t * kOmega + lid, a.lane_num - 1));
   // A tile without nonzeros reads nothing: col / val may be empty (nnz = 0).
   // The branch is uniform across the wavefront.
   if (s.x_se > 0) {
@@ -66,10 +78,11 @@ __device__ __forceinline__ void wave_load_tile(const SpmvArgs& a, const int32_t*
   }
 }
 
-template <typename V, int SIGMA, int WAVES, bool HOT>
+template <typename V, int SIGMA, int WAVES, bool HOT, typename D>
 __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
   constexpr int BITS = ceil_log2(kOmega * SIGMA);
   constexpr uint32_t FMASK = (1u << BITS) - 1u;
+  static_assert(2 * BITS + SIGMA <= 8 * (int)sizeof(D), "descriptor does not fit");
   constexpr int WLDS = kOmega * SIGMA;  // per wavefront: products, then inner-row slots
   __shared__ V s_stage[WAVES * WLDS];
 
@@ -95,8 +108,8 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
 
   const int stride = a.grid * WAVES;
   int t = blockIdx.x * WAVES + wid;
-  WaveTile<V, SIGMA> cur;
-  if (t < a.tile_num) wave_load_tile<V, SIGMA>(a, col, val, t, lid, cur);
+  WaveTile<V, SIGMA, D> cur;
+  if (t < a.tile_num) wave_load_tile<V, SIGMA, D>(a, col, val, t, lid, cur);
   while (t < a.tile_num) {
     // gathers of the current tile (none for a tile without nonzeros: x may be
     // empty then)
@@ -115,8 +128,8 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
     }
     // loads of the next tile go out before the gathers are consumed
     const int tn = t + stride;
-    WaveTile<V, SIGMA> nxt;
-    if (tn < a.tile_num) wave_load_tile<V, SIGMA>(a, col, val, tn, lid, nxt);
+    WaveTile<V, SIGMA, D> nxt;
+    if (tn < a.tile_num) wave_load_tile<V, SIGMA, D>(a, col, val, tn, lid, nxt);
 
     const int x_se = cur.x_se;
     const int y_ws = (int)(cur.tyw & kRowMask);
@@ -150,12 +163,12 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
         int xo = (int)(cur.desc & FMASK);
         int yo = (int)((cur.desc >> BITS) & FMASK);
         start_off = yo;
-        const uint32_t flags = cur.desc >> (2 * BITS);
+        const D flags = cur.desc >> (2 * BITS);
         const int steps = min(SIGMA, a.path_len - j * SIGMA);
 #pragma unroll
         for (int k = 0; k < SIGMA; ++k) {
           if (k < steps) {
-            if ((flags >> k) & 1u) {
+            if ((flags >> k) & 1) {
               if (has_down) s_w[x_se + yo - 1] = sum;
               else first_sum = sum;
               has_down = true;
@@ -190,16 +203,16 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
   }
 }
 
-template <typename V, int S, int W, bool H>
+template <typename V, int S, int W, bool H, typename D>
 static hipError_t launch_wave_t(const SpmvArgs& a, size_t dyn, hipStream_t st) {
-  hipLaunchKernelGGL((spmv_wave_kernel<V, S, W, H>), dim3((unsigned)a.grid), dim3(W * kOmega), dyn,
-                     st, a);
+  hipLaunchKernelGGL((spmv_wave_kernel<V, S, W, H, D>), dim3((unsigned)a.grid), dim3(W * kOmega),
+                     dyn, st, a);
   return hipGetLastError();
 }
 
-template <typename V, int S, int W, bool H>
+template <typename V, int S, int W, bool H, typename D>
 static hipError_t set_wave_lds_t(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&spmv_wave_kernel<V, S, W, H>),
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&spmv_wave_kernel<V, S, W, H, D>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
@@ -208,21 +221,46 @@ struct WaveEntry {
   hipError_t (*set_lds)(size_t);
 };
 
+#define MERBIT_WCASE(S, D) \
+  case S: return WaveEntry{launch_wave_t<V, S, W, H, D>, set_wave_lds_t<V, S, W, H, D>};
+
 template <typename V, int W, bool H>
 static WaveEntry wave_pick_sigma(int sigma) {
   switch (sigma) {
-#define MERBIT_WCASE(S) \
-  case S: return WaveEntry{launch_wave_t<V, S, W, H>, set_wave_lds_t<V, S, W, H>};
-    MERBIT_WCASE(1) MERBIT_WCASE(2) MERBIT_WCASE(3) MERBIT_WCASE(4) MERBIT_WCASE(5)
-    MERBIT_WCASE(6) MERBIT_WCASE(7) MERBIT_WCASE(8) MERBIT_WCASE(9) MERBIT_WCASE(10)
-    MERBIT_WCASE(11) MERBIT_WCASE(12)
-#undef MERBIT_WCASE
+    MERBIT_WCASE(1, uint32_t) MERBIT_WCASE(2, uint32_t) MERBIT_WCASE(3, uint32_t)
+    MERBIT_WCASE(4, uint32_t) MERBIT_WCASE(5, uint32_t) MERBIT_WCASE(6, uint32_t)
+    MERBIT_WCASE(7, uint32_t) MERBIT_WCASE(8, uint32_t) MERBIT_WCASE(9, uint32_t)
+    MERBIT_WCASE(10, uint32_t) MERBIT_WCASE(11, uint32_t) MERBIT_WCASE(12, uint32_t)
     default: return WaveEntry{nullptr, nullptr};
   }
 }
 
+// 64-bit descriptors: longer lanes than 32 bits allow.  FP32: sigma 16, 20,
+// 24; FP64 (twice the registers per value): sigma 14, 16.  256 or 512 lanes.
+template <typename V, int W, bool H>
+static WaveEntry wave_pick_sigma64(int sigma) {
+  if (sizeof(V) == 4) {
+    switch (sigma) {
+      MERBIT_WCASE(16, uint64_t) MERBIT_WCASE(20, uint64_t) MERBIT_WCASE(24, uint64_t)
+      default: return WaveEntry{nullptr, nullptr};
+    }
+  }
+  switch (sigma) {
+    MERBIT_WCASE(14, uint64_t) MERBIT_WCASE(16, uint64_t)
+    default: return WaveEntry{nullptr, nullptr};
+  }
+}
+#undef MERBIT_WCASE
+
 template <typename V, bool H>
-static WaveEntry wave_pick_waves(int sigma, int waves) {
+static WaveEntry wave_pick_waves(int sigma, int waves, bool desc64) {
+  if (desc64) {
+    switch (waves) {
+      case 4: return wave_pick_sigma64<V, 4, H>(sigma);
+      case 8: return wave_pick_sigma64<V, 8, H>(sigma);
+      default: return WaveEntry{nullptr, nullptr};
+    }
+  }
   switch (waves) {
     case 4: return wave_pick_sigma<V, 4, H>(sigma);
     case 8: return wave_pick_sigma<V, 8, H>(sigma);
@@ -231,27 +269,27 @@ static WaveEntry wave_pick_waves(int sigma, int waves) {
   }
 }
 
-static WaveEntry wave_pick(int dtype, int sigma, int waves, bool hot) {
-  if (dtype == 0) return hot ? wave_pick_waves<float, true>(sigma, waves)
-                             : wave_pick_waves<float, false>(sigma, waves);
-  if (dtype == 1) return hot ? wave_pick_waves<double, true>(sigma, waves)
-                             : wave_pick_waves<double, false>(sigma, waves);
+static WaveEntry wave_pick(int dtype, int sigma, int waves, bool hot, bool desc64) {
+  if (dtype == 0) return hot ? wave_pick_waves<float, true>(sigma, waves, desc64)
+                             : wave_pick_waves<float, false>(sigma, waves, desc64);
+  if (dtype == 1) return hot ? wave_pick_waves<double, true>(sigma, waves, desc64)
+                             : wave_pick_waves<double, false>(sigma, waves, desc64);
   return WaveEntry{nullptr, nullptr};
 }
 
-bool spmv_wave_supported(int dtype, int sigma, int waves, bool hot) {
-  return wave_pick(dtype, sigma, waves, hot).launch != nullptr;
+bool spmv_wave_supported(int dtype, int sigma, int waves, bool hot, bool desc64) {
+  return wave_pick(dtype, sigma, waves, hot, desc64).launch != nullptr;
 }
 
 hipError_t launch_spmv_wave(int dtype, int sigma, int waves, bool hot, size_t hot_lds_bytes,
-                            const SpmvArgs& a, hipStream_t st) {
-  WaveEntry k = wave_pick(dtype, sigma, waves, hot);
+                            const SpmvArgs& a, hipStream_t st, bool desc64) {
+  WaveEntry k = wave_pick(dtype, sigma, waves, hot, desc64);
   if (!k.launch) return hipErrorInvalidValue;
   return k.launch(a, hot ? hot_lds_bytes : 0, st);
 }
 
-hipError_t spmv_wave_set_hot_lds(int dtype, int sigma, int waves, size_t bytes) {
-  WaveEntry k = wave_pick(dtype, sigma, waves, true);
+hipError_t spmv_wave_set_hot_lds(int dtype, int sigma, int waves, size_t bytes, bool desc64) {
+  WaveEntry k = wave_pick(dtype, sigma, waves, true, desc64);
   if (!k.set_lds) return hipErrorInvalidValue;
   return k.set_lds(bytes);
 }

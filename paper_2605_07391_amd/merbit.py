@@ -42,14 +42,15 @@ class PlanInfo(ctypes.Structure):
                 ("sigma", ctypes.c_int32), ("block_lanes", ctypes.c_int32),
                 ("offset_bits", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("commit", ctypes.c_int32),
-                ("hot_coverage", ctypes.c_double)]
+                ("hot_coverage", ctypes.c_double), ("desc_bits", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_int32), ("block_lanes", ctypes.c_int32),
                 ("commit", ctypes.c_int32), ("hot_columns", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("eager_loops", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("eager_loops", ctypes.c_int32), ("desc_bits", ctypes.c_int32)]
 
 
 COMMIT_AUTO, COMMIT_BLOCK, COMMIT_WAVE = 0, 1, 2
@@ -153,7 +154,7 @@ class Plan:
     def __init__(self, row_ptr: torch.Tensor, col_ind: torch.Tensor, values: torch.Tensor,
                  n_cols: int, *, sigma: int = 0, block_lanes: int = 0, hot_columns: int = -1,
                  commit: str = "auto", blocks_per_cu: int = 0, validate: bool = True,
-                 eager_loops: bool = False, stream=None):
+                 eager_loops: bool = False, desc_bits: int = 32, stream=None):
         lib = load()
         self.dtype = values.dtype
         self._code = _vdtype(values)
@@ -175,6 +176,7 @@ class Plan:
         opts.validate = 1 if validate else 0
         opts.blocks_per_cu = blocks_per_cu
         opts.eager_loops = 1 if eager_loops else 0
+        opts.desc_bits = desc_bits
         h = ctypes.c_void_p()
         _check(lib.merbit_plan_create(self.n_rows, self.n_cols, self.nnz, rp, ci, va, self._code,
                                       ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
@@ -214,7 +216,8 @@ class Plan:
         return {name: getattr(inf, name) for name, _ in PlanInfo._fields_}
 
     def export(self):
-        """Host copies (numpy) of tile_x int32[T+1], tile_y uint32[T+1], lane_desc uint32[lanes]."""
+        """Host copies (numpy) of tile_x int32[T+1], tile_y uint32[T+1] and
+        lane_desc uint32[lanes] (uint64 for a 64-bit-descriptor plan)."""
         import numpy as np
         T, lanes = ctypes.c_int64(), ctypes.c_int64()
         lib = load()
@@ -222,7 +225,8 @@ class Plan:
                                       ctypes.byref(lanes)))
         tx = np.empty(T.value + 1, np.int32)
         ty = np.empty(T.value + 1, np.uint32)
-        ld = np.empty(max(lanes.value, 1), np.uint32)
+        ld = np.empty(max(lanes.value, 1), np.uint64 if self.info()["desc_bits"] == 64
+                      else np.uint32)
         _check(lib.merbit_plan_export(self._handle(), tx.ctypes.data_as(ctypes.c_void_p),
                                       ty.ctypes.data_as(ctypes.c_void_p),
                                       ld.ctypes.data_as(ctypes.c_void_p), None, None))
@@ -468,14 +472,16 @@ def column_scale(col: torch.Tensor, a: torch.Tensor, s: torch.Tensor,
 
 def tune(row_ptr: torch.Tensor, col_ind: torch.Tensor, values: torch.Tensor, n_cols: int, *,
          sigmas=None, block_lanes=None, reps: int = 20, commit: str = "auto",
-         hot_columns: int = -1, stream=None):
+         hot_columns: int = -1, desc_bits: int = 32, stream=None):
     """Time the fused SpMV for every (sigma, block_lanes) candidate on this
     matrix.  Returns ({"sigma": s, "block_lanes": b}, {(s, b): mean us})."""
     import numpy as np
     lib = load()
     code = _vdtype(values)
     n_rows = row_ptr.numel() - 1
-    if sigmas is None:
+    if sigmas is None and desc_bits == 64:
+        sigmas = [16, 20, 24] if code == F32 else [14, 16]
+    elif sigmas is None:
         sigmas = list(range(7, 13)) if code == F32 else list(range(4, 11))
     if block_lanes is None:
         block_lanes = [256, 512, 1024]
@@ -486,6 +492,7 @@ def tune(row_ptr: torch.Tensor, col_ind: torch.Tensor, values: torch.Tensor, n_c
     lib.merbit_opts_init(ctypes.byref(opts))
     opts.commit = _COMMIT[commit]
     opts.hot_columns = hot_columns
+    opts.desc_bits = desc_bits
     _check(lib.merbit_tune(n_rows, int(n_cols), col_ind.numel(),
                            _dev(row_ptr, torch.int32, "row_ptr"),
                            _dev(col_ind, torch.int32, "col_ind"),

@@ -307,3 +307,67 @@ def test_autotuner_picks_a_measured_candidate(dtype):
     best, table = pkg.tune(r, c, v, nc, reps=3)
     assert len(table) == (6 if dtype == torch.float32 else 7) * 3
     assert best["sigma"] in {s for s, _ in table}
+
+
+# 64-bit lane descriptors: (dtype, sigma) pairs the wave kernel builds
+DESC64 = [(torch.float32, 16), (torch.float32, 20), (torch.float32, 24), (torch.float64, 14),
+          (torch.float64, 16)]
+
+
+@pytest.mark.parametrize("block_lanes,hot", [(256, 0), (512, -1), (512, 37)])
+@pytest.mark.parametrize("dtype,sigma", DESC64, ids=[f"{'f32' if d == torch.float32 else 'f64'}s{s}"
+                                                     for d, s in DESC64])
+@pytest.mark.parametrize("name", ["one_row", "all_rows_empty", "single_long_row", "long_then_empty",
+                                  "random1_700x300", "random4_200x3000", "chung_lu_10k",
+                                  "fuzz2_3471x315", "one_column"])
+def test_desc64_plan_and_spmv(name, dtype, sigma, block_lanes, hot):
+    """Plans with 64-bit descriptors are bit exact against the oracle's
+    64-bit TILE and give y = A x within the SpMV tolerance."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    rp, col, vals, nc = _matrix(name, seed=sigma)
+    r, c, v = to_device(rp, col, vals, dtype, dev)
+    plan = pkg.Plan(r, c, v, nc, sigma=sigma, block_lanes=block_lanes, hot_columns=hot,
+                    desc_bits=64)
+    info = plan.info()
+    assert info["desc_bits"] == 64 and info["sigma"] == sigma and info["commit"] == 2
+    tx, ty, ld = plan.export()
+    ox, oy, od = oracle.plan64(rp, OMEGA, sigma)
+    assert ld.dtype == np.uint64
+    assert np.array_equal(tx, ox) and np.array_equal(ty, oy) and np.array_equal(ld, od)
+    x64 = seeded_x(nc, sigma, dtype)
+    y = torch.full((len(rp) - 1,), float("nan"), dtype=dtype, device=dev)
+    plan.spmv(torch.from_numpy(x64).to(dtype).to(dev), out=y)
+    torch.cuda.synchronize()
+    check_spmv(y, rp, col, host_values(vals, dtype), x64, dtype, f"{name} desc64 s{sigma}")
+    if len(col):
+        with pytest.raises(pkg.MerbitError):  # SpMM walks 32-bit descriptors only
+            plan.spmm(torch.zeros(nc, 2, dtype=dtype, device=dev))
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype,sigma", [(torch.float32, 24), (torch.float64, 16)],
+                         ids=["f32s24", "f64s16"])
+def test_desc64_rmat22_full_size(dtype, sigma):
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    w = workload("rmat22")
+    rp, col, vals, n = w["row_ptr"], w["col"], w["values"], w["n_rows"]
+    r, c, v = to_device(rp, col, vals, dtype, dev)
+    plan = pkg.Plan(r, c, v, n, sigma=sigma, desc_bits=64)
+    tx, ty, ld = plan.export()
+    ox, oy, od = oracle.plan64(rp, OMEGA, sigma)
+    assert np.array_equal(tx, ox) and np.array_equal(ty, oy) and np.array_equal(ld, od)
+    del tx, ty, ld, ox, oy, od
+    x64 = seeded_x(n, 22, dtype)
+    y = plan.spmv(torch.from_numpy(x64).to(dtype).to(dev))
+    torch.cuda.synchronize()
+    check_spmv(y, rp, col, host_values(vals, dtype), x64, dtype, f"rmat22 desc64 s{sigma}")
+    # PageRank on the 64-bit plan, a few iterations against the oracle
+    x = torch.full((n,), 1.0 / n, dtype=dtype, device=dev)
+    plan.pagerank(x, 0.85, max_iter=4)
+    x0 = np.full(n, 1.0 / n).astype(np.float32 if dtype == torch.float32 else np.float64)
+    ref, _, _ = oracle.pagerank(rp, col, host_values(vals, dtype), 0.85, 4, x0.astype(np.float64))
+    rel = np.abs(x.double().cpu().numpy() - ref) / ref
+    assert rel.max() <= (1e-4 if dtype == torch.float32 else 1e-11)
+    plan.close()

@@ -47,7 +47,7 @@ def test_argument_errors_without_gpu():
     d = mb.Opts()
     lib.merbit_opts_init(ctypes.byref(d))
     assert (d.sigma, d.block_lanes, d.commit, d.hot_columns, d.validate,
-            d.eager_loops) == (0, 0, 0, -1, 1, 0)
+            d.eager_loops, d.desc_bits) == (0, 0, 0, -1, 1, 0, 0)
     # NULL out pointer
     assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, None, None, None) == mb.EINVAL
     # unsupported dtype
@@ -68,6 +68,21 @@ def test_argument_errors_without_gpu():
                                   ctypes.byref(out)) == mb.EINVAL
     assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0,
                                   opts(commit=2, block_lanes=128), None,
+                                  ctypes.byref(out)) == mb.EUNSUPPORTED
+    # descriptor width: only 32 or 64; 64 bits need the wave kernel and a built sigma
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, opts(desc_bits=48), None,
+                                  ctypes.byref(out)) == mb.EINVAL
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0,
+                                  opts(desc_bits=64, sigma=24, commit=1), None,
+                                  ctypes.byref(out)) == mb.EUNSUPPORTED
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, opts(desc_bits=64, sigma=41),
+                                  None, ctypes.byref(out)) == mb.EUNSUPPORTED
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, opts(desc_bits=64, sigma=18),
+                                  None, ctypes.byref(out)) == mb.EUNSUPPORTED
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 1, opts(desc_bits=64, sigma=24),
+                                  None, ctypes.byref(out)) == mb.EUNSUPPORTED
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0,
+                                  opts(desc_bits=64, sigma=24, block_lanes=1024), None,
                                   ctypes.byref(out)) == mb.EUNSUPPORTED
     assert not out.value
     # calls on a NULL plan
