@@ -164,43 +164,61 @@ hipError_t launch_spmm_zero(int dtype, const uint32_t* tile_y, int32_t tile_num,
 // Column j of X is the rank vector of source src[j]:
 //   X'[r, j] = alpha Y[r, j] + (r == src[j]) (alpha delta_j + 1 - alpha),
 // with delta_j the dangling mass of column j.  Every block writes, per column,
-// its part of the next dangling mass and of the l1 change; a small kernel
-// sums those parts in block order (deterministic) for the next step and the
-// host.  Threads are laid out so that thread t always handles column t % 64.
+// its part of the next dangling mass and of the l1 change; a second kernel
+// (one block per column) sums those parts in a fixed order for the next step
+// and the host.  Thread t always handles column t % 64, so each wavefront
+// reads and writes whole rows of X and Y (coalesced); a wavefront takes
+// kPprRows rows per pass with all their loads issued first.
 
 constexpr int kPprThreads = 256;
+constexpr int kPprWaves = kPprThreads / 64;
+constexpr int kPprRows = 4;
 
 template <typename V>
 __global__ __launch_bounds__(kPprThreads) void ppr_update_kernel(
     const V* __restrict__ Y, const V* __restrict__ X_old, V* __restrict__ X_new,
     const uint32_t* __restrict__ dmask, int64_t n, int k, double alpha,
-    const int32_t* __restrict__ src, const double* __restrict__ delta_in,
+    const int32_t* __restrict__ src, const double* __restrict__ delta_in,  // (dangling mass, l1 change) per column
     double* __restrict__ part_out) {
   __shared__ double s_d[kPprThreads], s_r[kPprThreads];
   const int j = threadIdx.x & 63;
-  const int rsub = threadIdx.x >> 6;  // 4 rows per block iteration
+  const int w = threadIdx.x >> 6;
   const bool on = j < k;
   const V a = (V)alpha;
   double dsum = 0.0, rsum = 0.0;
   const int sj = on ? src[j] : -1;
   const V tele = on ? (V)(alpha * delta_in[2 * j] + 1.0 - alpha) : V(0);
-  for (int64_t r = (int64_t)blockIdx.x * 4 + rsub; r < n; r += (int64_t)gridDim.x * 4) {
-    if (!on) continue;
-    const int64_t e = r * k + j;
-    V xn = a * Y[e];
-    if (r == sj) xn += tele;
-    X_new[e] = xn;
-    rsum += fabs((double)xn - (double)X_old[e]);
-    if ((dmask[r >> 5] >> (r & 31)) & 1u) dsum += (double)xn;
+  const int64_t step = (int64_t)gridDim.x * kPprWaves * kPprRows;
+  for (int64_t r0 = ((int64_t)blockIdx.x * kPprWaves + w) * kPprRows; on && r0 < n; r0 += step) {
+    V yv[kPprRows], xo[kPprRows];
+    uint32_t mw[kPprRows];
+#pragma unroll
+    for (int u = 0; u < kPprRows; ++u) {
+      const int64_t r = min(r0 + u, n - 1);
+      yv[u] = Y[r * k + j];
+      xo[u] = X_old[r * k + j];
+      mw[u] = dmask[r >> 5];
+    }
+#pragma unroll
+    for (int u = 0; u < kPprRows; ++u) {
+      const int64_t r = r0 + u;
+      if (r < n) {
+        V xn = a * yv[u];
+        if (r == sj) xn += tele;
+        X_new[r * k + j] = xn;
+        rsum += fabs((double)xn - (double)xo[u]);
+        if ((mw[u] >> (r & 31)) & 1u) dsum += (double)xn;
+      }
+    }
   }
   s_d[threadIdx.x] = dsum;
   s_r[threadIdx.x] = rsum;
   __syncthreads();
   if (threadIdx.x < 64) {
     double d = 0.0, rr = 0.0;
-    for (int w = 0; w < kPprThreads / 64; ++w) {
-      d += s_d[w * 64 + threadIdx.x];
-      rr += s_r[w * 64 + threadIdx.x];
+    for (int q = 0; q < kPprWaves; ++q) {
+      d += s_d[q * 64 + threadIdx.x];
+      rr += s_r[q * 64 + threadIdx.x];
     }
     part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2] = d;
     part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2 + 1] = rr;
@@ -214,39 +232,56 @@ __global__ __launch_bounds__(kPprThreads) void ppr_dangling_kernel(
     double* __restrict__ part_out) {
   __shared__ double s_d[kPprThreads];
   const int j = threadIdx.x & 63;
-  const int rsub = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6;
   double dsum = 0.0;
-  if (j < k)
-    for (int64_t r = (int64_t)blockIdx.x * 4 + rsub; r < n; r += (int64_t)gridDim.x * 4)
-      if ((dmask[r >> 5] >> (r & 31)) & 1u) dsum += (double)X[r * k + j];
+  const int64_t step = (int64_t)gridDim.x * kPprWaves * kPprRows;
+  for (int64_t r0 = ((int64_t)blockIdx.x * kPprWaves + w) * kPprRows; j < k && r0 < n;
+       r0 += step) {
+#pragma unroll
+    for (int u = 0; u < kPprRows; ++u) {
+      const int64_t r = r0 + u;
+      if (r < n && ((dmask[r >> 5] >> (r & 31)) & 1u)) dsum += (double)X[r * k + j];
+    }
+  }
   s_d[threadIdx.x] = dsum;
   __syncthreads();
   if (threadIdx.x < 64) {
     double d = 0.0;
-    for (int w = 0; w < kPprThreads / 64; ++w) d += s_d[w * 64 + threadIdx.x];
+    for (int q = 0; q < kPprWaves; ++q) d += s_d[q * 64 + threadIdx.x];
     part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2] = d;
     part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2 + 1] = 0.0;
   }
 }
 
-// sums[j] = (sum over blocks of part[b][j][0], ... [1]), block order
-__global__ void ppr_sum_parts_kernel(const double* __restrict__ part, int nblocks,
-                                     double* __restrict__ sums) {
-  const int j = threadIdx.x;  // 64 threads
+// sums[2j], sums[2j+1] = totals over the blocks of column j's parts: block j
+// of this kernel; thread t adds parts t, t + 256, ... in order, then a
+// fixed-order block reduction
+__global__ __launch_bounds__(kReduceThreads) void ppr_sum_parts_kernel(
+    const double* __restrict__ part, int nblocks, double* __restrict__ sums) {
+  const int j = blockIdx.x;
   double d = 0.0, r = 0.0;
-  for (int b = 0; b < nblocks; ++b) {
+  for (int b = threadIdx.x; b < nblocks; b += kReduceThreads) {
     d += part[((int64_t)b * 64 + j) * 2];
     r += part[((int64_t)b * 64 + j) * 2 + 1];
   }
-  sums[2 * j] = d;
-  sums[2 * j + 1] = r;
+  block_sum2(d, r);
+  if (threadIdx.x == 0) {
+    sums[2 * j] = d;
+    sums[2 * j + 1] = r;
+  }
 }
 
 int ppr_grid(int64_t n) {
-  int64_t g = (n + 4 * 16 - 1) / (4 * 16);
-  if (g > 512) g = 512;
+  int64_t g = (n + kPprWaves * kPprRows * 8 - 1) / (kPprWaves * kPprRows * 8);
+  if (g > 4096) g = 4096;
   if (g < 1) g = 1;
   return (int)g;
+}
+
+static hipError_t launch_ppr_sum(const double* part, int grid, double* sums, hipStream_t st) {
+  hipLaunchKernelGGL(ppr_sum_parts_kernel, dim3(64), dim3(kReduceThreads), 0, st, part, grid,
+                     sums);
+  return hipGetLastError();
 }
 
 hipError_t launch_ppr_dangling(int dtype, const void* X, const uint32_t* dmask, int64_t n, int k,
@@ -259,8 +294,7 @@ hipError_t launch_ppr_dangling(int dtype, const void* X, const uint32_t* dmask, 
                        static_cast<const double*>(X), dmask, n, k, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ppr_sum_parts_kernel, dim3(1), dim3(64), 0, st, part, grid, sums);
-  return hipGetLastError();
+  return launch_ppr_sum(part, grid, sums, st);
 }
 
 hipError_t launch_ppr_update(int dtype, const void* Y, const void* X_old, void* X_new,
@@ -277,8 +311,7 @@ hipError_t launch_ppr_update(int dtype, const void* Y, const void* X_old, void* 
                        static_cast<double*>(X_new), dmask, n, k, alpha, src, sums_in, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(ppr_sum_parts_kernel, dim3(1), dim3(64), 0, st, part, grid, sums_out);
-  return hipGetLastError();
+  return launch_ppr_sum(part, grid, sums_out, st);
 }
 
 // ------------------------------------------------ PageRank of many graphs --
@@ -352,24 +385,32 @@ __global__ __launch_bounds__(kReduceThreads) void multi_dangling_kernel(
   }
 }
 
-__global__ void multi_sum_kernel(const double* __restrict__ part,
-                                 const int32_t* __restrict__ chunk_ptr, int n_graphs,
-                                 double* __restrict__ gsum_out) {
-  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per graph: lane l adds chunks chunk_ptr[g] + l, + l + 64, ...
+// in order, then a fixed-order wavefront reduction.
+__global__ __launch_bounds__(256) void multi_sum_kernel(const double* __restrict__ part,
+                                                         const int32_t* __restrict__ chunk_ptr,
+                                                         int n_graphs,
+                                                         double* __restrict__ gsum_out) {
+  const int g = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lid = threadIdx.x & 63;
   if (g >= n_graphs) return;
   double d = 0.0, r = 0.0;
-  for (int c = chunk_ptr[g]; c < chunk_ptr[g + 1]; ++c) {
+  for (int c = chunk_ptr[g] + lid; c < chunk_ptr[g + 1]; c += 64) {
     d += part[2 * c];
     r += part[2 * c + 1];
   }
-  gsum_out[2 * g] = d;
-  gsum_out[2 * g + 1] = r;
+  d = wave_sum(d);
+  r = wave_sum(r);
+  if (lid == 0) {
+    gsum_out[2 * g] = d;
+    gsum_out[2 * g + 1] = r;
+  }
 }
 
 static hipError_t launch_multi_sum(const double* part, const int32_t* chunk_ptr, int n_graphs,
                                    double* gsum_out, hipStream_t st) {
-  hipLaunchKernelGGL(multi_sum_kernel, dim3((unsigned)((n_graphs + 255) / 256)), dim3(256), 0,
-                     st, part, chunk_ptr, n_graphs, gsum_out);
+  hipLaunchKernelGGL(multi_sum_kernel, dim3((unsigned)((n_graphs + 3) / 4)), dim3(256), 0, st,
+                     part, chunk_ptr, n_graphs, gsum_out);
   return hipGetLastError();
 }
 

@@ -20,14 +20,28 @@ __global__ void col_count_kernel(const int32_t* __restrict__ col, int64_t nnz,
     atomicAdd(&counts[col[k]], 1);
 }
 
-// hist[min(count, kHotHistBins - 1)] += 1 over the columns
-__global__ void count_hist_kernel(const int32_t* __restrict__ counts, int64_t n_cols,
-                                  int32_t* __restrict__ hist) {
+// hist[min(count, kHotHistBins - 1)] += 1 over the columns.  Most columns
+// have small counts, so the low bins are counted per block in LDS and added
+// to the global histogram once per block; only large counts go straight to
+// global atomics.
+constexpr int kHistLdsBins = 2048;
+
+__global__ __launch_bounds__(256) void count_hist_kernel(const int32_t* __restrict__ counts,
+                                                         int64_t n_cols,
+                                                         int32_t* __restrict__ hist) {
+  __shared__ int32_t s_hist[kHistLdsBins];
+  for (int b = threadIdx.x; b < kHistLdsBins; b += blockDim.x) s_hist[b] = 0;
+  __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < n_cols; c += stride) {
     const int32_t v = counts[c];
-    atomicAdd(&hist[v < kHotHistBins - 1 ? v : kHotHistBins - 1], 1);
+    const int32_t bin = v < kHotHistBins - 1 ? v : kHotHistBins - 1;
+    if (bin < kHistLdsBins) atomicAdd(&s_hist[bin], 1);
+    else atomicAdd(&hist[bin], 1);
   }
+  __syncthreads();
+  for (int b = threadIdx.x; b < kHistLdsBins; b += blockDim.x)
+    if (s_hist[b]) atomicAdd(&hist[b], s_hist[b]);
 }
 
 // Selection in column order: block b owns columns [b * kSelSpan, (b+1) * kSelSpan).
@@ -124,7 +138,7 @@ hipError_t hot_count_columns(const int32_t* col, int64_t nnz, int64_t n_cols, in
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(count_hist_kernel, dim3(grid_for(n_cols, 4096)), dim3(256), 0, st, counts,
+  hipLaunchKernelGGL(count_hist_kernel, dim3(grid_for(n_cols, 512)), dim3(256), 0, st, counts,
                      n_cols, hist);
   return hipGetLastError();
 }
