@@ -285,6 +285,25 @@ def run_bicgstab(scale: int, steps: int):
             "rel_residual": res, "seed": scale}
 
 
+def measured_copy_gbs(mib: int = 1024, reps: int = 5) -> float:
+    """Device-to-device copy bandwidth (read + write bytes / time), a measured
+    second denominator beside the published HBM peak."""
+    import torch
+    n = (mib << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(w, iters: int, alpha: float, dtype_name: str = "f32"):
     import numpy as np
 
@@ -405,6 +424,7 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, args.cpu_iters, args.alpha, args.dtype)
     ach = main_run["achieved_gbs"]
+    copy_gbs = measured_copy_gbs()
     out = {
         "metric": METRIC,
         "value": round(main_run["value_gnzs"], 3),
@@ -436,6 +456,8 @@ def main():
                      "kernel": KERNELS[info["commit"]][0],
                      "alg_bytes_per_launch": int(main_run["alg_bytes"]),
                      "mean_launch_us": round(main_run["spmv_ms"] * 1e3, 2),
+                     "measured_copy_gbs": round(copy_gbs, 1),
+                     "frac_of_measured_copy": round(ach / copy_gbs, 4),
                      "launches_timed": main_run["launches"]},
         "cpu_baseline": cpu,
         "spmv_gnzs": round(main_run["spmv_gnzs"], 3),

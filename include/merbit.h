@@ -110,7 +110,9 @@ typedef struct {
     int32_t lds_bytes;     /* LDS per block: (b sigma + 1) values for products and row
                               partial sums (Sec. 4.3) + the hot x values               */
     int32_t commit;        /* merbit_commit of the plan                                 */
-    double hot_coverage;   /* fraction of nonzeros whose column is hot                  */
+    double hot_coverage;   /* fraction of nonzeros whose column is hot (estimated from
+                              a 1-in-s sample of the column stream, s <= 8, when the
+                              cache holds only part of the columns)                     */
     int32_t desc_bits;     /* lane descriptor width: 32 or 64                           */
     int32_t reserved;
 } merbit_plan_info_t;

@@ -333,7 +333,10 @@ static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
     HIP_TRY(hipMalloc(&counts, sizeof(int32_t) * (size_t)nc));
     HIP_TRY(hipMalloc(&hist, sizeof(int32_t) * kHotHistBins));
     std::vector<int32_t> h(kHotHistBins);
-    hipError_t e = hot_count_columns(p->col, p->nnz, nc, counts, hist, st);
+    // sampled counts: one nonzero in `sample`, about two samples per column
+    int64_t sample = p->nnz / (2 * nc);
+    sample = sample < 1 ? 1 : (sample > 8 ? 8 : sample);
+    hipError_t e = hot_count_columns(p->col, p->nnz, nc, (int)sample, counts, hist, st);
     if (e == hipSuccess)
       e = hipMemcpyAsync(h.data(), hist, sizeof(int32_t) * kHotHistBins, hipMemcpyDeviceToHost,
                          st);
@@ -343,7 +346,7 @@ static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
       (void)hipFree(hist);
       return fail_hip("hot column counts", e);
     }
-    // smallest threshold t >= 1 with at most cap columns of count >= t
+    // smallest threshold t >= 1 with at most cap columns of (sampled) count >= t
     int64_t taken = 0;
     double covered = 0.0;
     int32_t t = kHotHistBins;
@@ -353,7 +356,8 @@ static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
       covered += (double)b * h[b];
       t = b;
     }
-    p->hot_coverage = covered / (double)p->nnz;
+    p->hot_coverage = covered * (double)sample / (double)p->nnz;  // estimate when sampled
+    if (p->hot_coverage > 1.0) p->hot_coverage = 1.0;
     const bool keep = taken > 0 && (cap_req > 0 || p->hot_coverage >= 0.2);
     if (keep) {
       const int nb = hot_select_blocks(nc);

@@ -13,11 +13,17 @@
 
 namespace merbit {
 
-__global__ void col_count_kernel(const int32_t* __restrict__ col, int64_t nnz,
+// counts[c] = number of sampled nonzeros in column c: every `sample`-th
+// nonzero of the stream (1 = exact counts).  The selection only needs the
+// order of the large counts, which a 1-in-8 sample keeps (R-MAT scale 22:
+// 52.9 % coverage of the top 32K columns either way) at an eighth of the
+// global atomics.
+__global__ void col_count_kernel(const int32_t* __restrict__ col, int64_t nnz, int sample,
                                  int32_t* __restrict__ counts) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += stride)
-    atomicAdd(&counts[col[k]], 1);
+  const int64_t ns = (nnz + sample - 1) / sample;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += stride)
+    atomicAdd(&counts[col[i * sample]], 1);
 }
 
 // hist[min(count, kHotHistBins - 1)] += 1 over the columns.  Most columns
@@ -126,15 +132,15 @@ static unsigned grid_for(int64_t n, int64_t cap) {
   return (unsigned)g;
 }
 
-hipError_t hot_count_columns(const int32_t* col, int64_t nnz, int64_t n_cols, int32_t* counts,
-                             int32_t* hist, hipStream_t st) {
+hipError_t hot_count_columns(const int32_t* col, int64_t nnz, int64_t n_cols, int sample,
+                             int32_t* counts, int32_t* hist, hipStream_t st) {
   hipError_t e = hipMemsetAsync(counts, 0, sizeof(int32_t) * (size_t)n_cols, st);
   if (e != hipSuccess) return e;
   e = hipMemsetAsync(hist, 0, sizeof(int32_t) * kHotHistBins, st);
   if (e != hipSuccess) return e;
   if (nnz > 0) {
-    hipLaunchKernelGGL(col_count_kernel, dim3(grid_for(nnz, 8192)), dim3(256), 0, st, col, nnz,
-                       counts);
+    hipLaunchKernelGGL(col_count_kernel, dim3(grid_for(nnz / sample + 1, 8192)), dim3(256), 0,
+                       st, col, nnz, sample, counts);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -234,8 +234,8 @@ hipError_t spmv_wave_set_hot_lds(int dtype, int sigma, int waves, size_t bytes,
                                  bool desc64 = false);
 
 // Hot-column cache.
-hipError_t hot_count_columns(const int32_t* col, int64_t nnz, int64_t n_cols, int32_t* counts,
-                             int32_t* hist, hipStream_t st);
+hipError_t hot_count_columns(const int32_t* col, int64_t nnz, int64_t n_cols, int sample,
+                             int32_t* counts, int32_t* hist, hipStream_t st);
 int hot_select_blocks(int64_t n_cols);
 hipError_t hot_select_count(const int32_t* counts, int64_t n_cols, int32_t threshold,
                             int32_t* block_counts, hipStream_t st);
