@@ -83,10 +83,22 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
         # 64-bit-descriptor kernels are swept too and reported beside it
         best, table = pkg.tune(r, c, v, n, reps=10, commit=commit, hot_columns=hot_columns)
         sigma, block_lanes = best["sigma"], best["block_lanes"]
+        table_block = None
+        if commit == "auto":
+            # the paper's block-commit layout, b = 128 .. 1024 lanes, swept as well
+            best_b, table_block = pkg.tune(r, c, v, n, reps=10, commit="block",
+                                           hot_columns=hot_columns,
+                                           block_lanes=[128, 256, 512, 1024])
+            tb = min(t for t in table_block.values() if t > 0)
+            tw = min(t for t in table.values() if t > 0)
+            if tb < tw:
+                sigma, block_lanes, commit = best_b["sigma"], best_b["block_lanes"], "block"
         best64, table64 = pkg.tune(r, c, v, n, reps=10, hot_columns=hot_columns, desc_bits=64,
                                    block_lanes=[256, 512])
-        tuning = {"best": best, "us_per_spmv": {f"s{a}_b{b}": round(t, 1)
-                                                for (a, b), t in table.items()},
+        tuning = {"best": {"sigma": sigma, "block_lanes": block_lanes, "commit": commit},
+                  "us_per_spmv": {f"s{a}_b{b}": round(t, 1) for (a, b), t in table.items()},
+                  "block_commit_us_per_spmv": None if table_block is None else {
+                      f"s{a}_b{b}": round(t, 1) for (a, b), t in table_block.items()},
                   "desc64": {"best": best64,
                              "us_per_spmv": {f"s{a}_b{b}": round(t, 1)
                                              for (a, b), t in table64.items()},
@@ -400,7 +412,8 @@ def main():
             "hot_columns": r64["info"]["hot_columns"],
             "hot_coverage": round(r64["info"]["hot_coverage"], 4),
             "traffic": load_traffic(args.workload, "f64", r64["info"]["commit"]),
-            "block_lanes": r64["info"]["block_lanes"], "tuning": r64["tuning"],
+            "block_lanes": r64["info"]["block_lanes"],
+            "commit": {1: "block", 2: "wave"}[r64["info"]["commit"]], "tuning": r64["tuning"],
         }
         print(f"[bench] f64: step {r64['step_ms'] * 1e3:.1f} us, spmv "
               f"{r64['spmv_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)

@@ -69,8 +69,9 @@ typedef struct {
                               to the paper's method: on gfx950 scattered x gathers are
                               bounded by the L2 request rate and power-law matrices
                               concentrate their nonzeros on few columns.  -1 = automatic
-                              (largest cache that fits one block per CU, kept only when
-                              the hot columns hold >= 20 % of the nonzeros), 0 = off,
+                              (wave commit only: largest cache that fits one block per
+                              CU, kept only when the hot columns hold >= 20 % of the
+                              nonzeros; the block kernel gets none), 0 = off,
                               k > 0 = at most k columns (MERBIT_EUNSUPPORTED if k values
                               do not fit in LDS).  With the cache the plan owns a
                               recoded copy of col_ind (int32[nnz]) and each SpMV first

@@ -308,6 +308,11 @@ static int size_grid(merbit_plan* p) {
 static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
   p->hot_n = 0;
   if (cap_req == 0 || p->nnz == 0 || p->n_cols == 0) return MERBIT_OK;
+  // Automatic sizing enables the cache for the wave kernel only: with the
+  // block kernel the LDS fill leaves one block per CU and its barriers make
+  // every wavefront of a block wait for the slowest, which measured slower
+  // than no cache at every size (R-MAT 22).  An explicit size is honoured.
+  if (cap_req < 0 && p->commit != MERBIT_COMMIT_WAVE) return MERBIT_OK;
   if (!kernel_supported(p, true))
     return cap_req > 0 ? fail(MERBIT_EUNSUPPORTED, "hot cache not built for this block size")
                        : MERBIT_OK;
