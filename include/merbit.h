@@ -347,10 +347,12 @@ int merbit_tune(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* row_
                 merbit_opts_t* opts_inout, float* us_out, void* stream);
 
 /* Kernel timing for the SpMV launches of this plan.  While enabled, every
- * fused SpMV launch (from merbit_spmv, merbit_spmv_dual and merbit_pagerank)
- * and every SpMM slab launch is bracketed by HIP events on its stream.  merbit_profile_read (synchronous)
- * returns the number of timed launches and their summed duration in ms, then
- * clears the record.  Host pointers. */
+ * fused SpMV launch (from merbit_spmv, merbit_spmv_dual and the iterative
+ * drivers) and every SpMM slab launch is bracketed by HIP events on its
+ * stream, and the drivers launch their kernels directly instead of replaying
+ * HIP graphs.  merbit_profile_read (synchronous) returns the number of timed
+ * launches and their summed duration in ms, then clears the record.  Host
+ * pointers. */
 int merbit_profile_enable(merbit_plan* plan, int enable);
 int merbit_profile_read(merbit_plan* plan, int64_t* launches, double* total_ms);
 

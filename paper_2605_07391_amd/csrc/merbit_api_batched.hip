@@ -1,0 +1,222 @@
+// C ABI of libmerbit, batched forms: SpMM over up to 64 right-hand sides per
+// launch and personalised PageRank for many sources at once.
+#include <math.h>
+#include <string.h>
+
+#include "merbit_host.hpp"
+
+using namespace merbit;
+
+extern "C" {
+
+static SpmmArgs spmm_args(const merbit_plan* p, const void* X, int64_t ldx, void* Y,
+                          int64_t ldy, void* Z, int64_t ldz, int k) {
+  SpmmArgs a;
+  a.tile_x = p->tile_x;
+  a.tile_y = p->tile_y;
+  a.lane_desc = p->lane_desc;
+  a.col = p->col;
+  a.val = p->values;
+  a.X = X;
+  a.Y = Y;
+  a.Z = Z;
+  a.ldx = ldx;
+  a.ldy = ldy;
+  a.ldz = ldz;
+  a.k = k;
+  a.tile_num = (int32_t)p->tile_num;
+  a.lane_num = (int32_t)p->lane_num;
+  a.path_len = (int32_t)(p->nnz + p->n_rows);
+  a.n_rows = (int32_t)p->n_rows;
+  return a;
+}
+
+// One SpMM launch per slab of at most 64 columns, bracketed by events when
+// profiling is on.
+static int run_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy, void* Z,
+                    int64_t ldz, int k, hipStream_t st) {
+  const size_t vs = vsize(p->dtype);
+  for (int c0 = 0; c0 < k; c0 += 64) {
+    const int kk = k - c0 < 64 ? k - c0 : 64;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (p->profiling) {
+      if (p->events_used == p->events.size()) {
+        hipEvent_t a, b;
+        HIP_TRY(hipEventCreate(&a));
+        HIP_TRY(hipEventCreate(&b));
+        p->events.emplace_back(a, b);
+      }
+      e0 = p->events[p->events_used].first;
+      e1 = p->events[p->events_used].second;
+      ++p->events_used;
+      HIP_TRY(hipEventRecord(e0, st));
+    }
+    HIP_TRY(launch_spmm(p->dtype, p->sigma,
+                        spmm_args(p, static_cast<const char*>(X) + vs * c0, ldx,
+                                  static_cast<char*>(Y) + vs * c0, ldy,
+                                  Z ? static_cast<char*>(Z) + vs * c0 : nullptr, ldz, kk),
+                        st));
+    if (p->profiling) HIP_TRY(hipEventRecord(e1, st));
+  }
+  p->last_stream = st;
+  return MERBIT_OK;
+}
+
+int merbit_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy, int k,
+                void* stream) {
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->desc_bits != 32)
+    return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
+  if (k < 1) return fail(MERBIT_EINVAL, "k < 1");
+  if (ldx < k || ldy < k) return fail(MERBIT_EINVAL, "leading dimension < k");
+  if (p->n_rows == 0) return MERBIT_OK;
+  if (!Y || (p->nnz > 0 && !X)) return fail(MERBIT_EINVAL, "X or Y is NULL");
+  if (X == Y) return fail(MERBIT_EINVAL, "X and Y alias");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t vs = vsize(p->dtype);
+  for (int c0 = 0; c0 < k; c0 += 64) {
+    const int kk = k - c0 < 64 ? k - c0 : 64;
+    HIP_TRY(launch_spmm_zero(p->dtype, p->tile_y, (int32_t)p->tile_num,
+                             static_cast<char*>(Y) + vs * c0, ldy, kk, st));
+  }
+  return run_spmm(p, X, ldx, Y, ldy, nullptr, 0, k, st);
+}
+
+int merbit_spmm_dual(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy, void* Z,
+                     int64_t ldz, int k, void* stream) {
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->desc_bits != 32)
+    return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
+  if (k < 1) return fail(MERBIT_EINVAL, "k < 1");
+  if (ldx < k || ldy < k || ldz < k) return fail(MERBIT_EINVAL, "leading dimension < k");
+  if (p->n_rows == 0) return MERBIT_OK;
+  if (!Y || !Z || (p->nnz > 0 && !X)) return fail(MERBIT_EINVAL, "X, Y or Z is NULL");
+  if (X == Y || Y == Z || X == Z) return fail(MERBIT_EINVAL, "X, Y, Z must be distinct");
+  return run_spmm(p, X, ldx, Y, ldy, Z, ldz, k, static_cast<hipStream_t>(stream));
+}
+
+int merbit_spmm_zero_boundary(merbit_plan* p, void* Y, int64_t ldy, int k, void* stream) {
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (k < 1 || ldy < k) return fail(MERBIT_EINVAL, "bad k / leading dimension");
+  if (p->tile_num == 0) return MERBIT_OK;
+  if (!Y) return fail(MERBIT_EINVAL, "Y is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t vs = vsize(p->dtype);
+  for (int c0 = 0; c0 < k; c0 += 64) {
+    const int kk = k - c0 < 64 ? k - c0 : 64;
+    HIP_TRY(launch_spmm_zero(p->dtype, p->tile_y, (int32_t)p->tile_num,
+                             static_cast<char*>(Y) + vs * c0, ldy, kk, st));
+  }
+  p->last_stream = st;
+  return MERBIT_OK;
+}
+
+static int ensure_ppr_state(merbit_plan* p, int k, hipStream_t st) {
+  int rc = ensure_dmask(p, st);
+  if (rc != MERBIT_OK) return rc;
+  if (p->ppr_k != k) {
+    invalidate_graphs(p);
+    for (int b = 0; b < 3; ++b) {
+      if (p->pbuf[b]) (void)hipFree(p->pbuf[b]);
+      p->pbuf[b] = nullptr;
+    }
+    const size_t bytes = vsize(p->dtype) * (size_t)p->n_rows * (size_t)k;
+    for (int b = 0; b < 3; ++b) HIP_TRY(hipMalloc(&p->pbuf[b], bytes));
+    p->ppr_k = k;
+    p->ppr_zeroed = -1;
+  }
+  if (!p->ppart) {
+    p->ppr_grid_n = ppr_grid(p->n_rows);
+    HIP_TRY(hipMalloc(&p->ppart, sizeof(double) * 2 * 64 * (size_t)p->ppr_grid_n));
+    HIP_TRY(hipMalloc(&p->psums[0], sizeof(double) * 2 * 64));
+    HIP_TRY(hipMalloc(&p->psums[1], sizeof(double) * 2 * 64));
+    HIP_TRY(hipMalloc(&p->psrc, sizeof(int32_t) * 64));
+  }
+  return MERBIT_OK;
+}
+
+int merbit_pagerank_personalized(merbit_plan* p, double alpha, double tol, int max_iter,
+                                 int check_every, const int32_t* sources, int k, void* X_inout,
+                                 int* iters_out, double* resid_out, void* stream) {
+  if (iters_out) *iters_out = 0;
+  if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->desc_bits != 32)
+    return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
+  if (p->n_rows != p->n_cols) return fail(MERBIT_EINVAL, "PageRank needs a square matrix");
+  if (!(alpha >= 0.0 && alpha <= 1.0)) return fail(MERBIT_EINVAL, "alpha must be in [0, 1]");
+  if (k < 1 || k > 64) return fail(MERBIT_EINVAL, "k must be in 1..64");
+  if (max_iter < 0) return fail(MERBIT_EINVAL, "max_iter < 0");
+  if (!sources) return fail(MERBIT_EINVAL, "sources is NULL");
+  for (int j = 0; j < k; ++j)
+    if (sources[j] < 0 || sources[j] >= p->n_rows)
+      return fail(MERBIT_EINVAL, "source out of range");
+  if (resid_out)
+    for (int j = 0; j < k; ++j) resid_out[j] = 0.0;
+  if (p->n_rows == 0 || max_iter == 0) return MERBIT_OK;
+  if (!X_inout) return fail(MERBIT_EINVAL, "X is NULL");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int rc = ensure_ppr_state(p, k, st);
+  if (rc != MERBIT_OK) return rc;
+  if (check_every <= 0) check_every = 10;
+  const int64_t n = p->n_rows;
+  const size_t bytes = vsize(p->dtype) * (size_t)n * (size_t)k;
+  HIP_TRY(hipMemcpyAsync(p->psrc, sources, sizeof(int32_t) * (size_t)k, hipMemcpyHostToDevice,
+                         st));
+  HIP_TRY(launch_ppr_dangling(p->dtype, X_inout, p->dmask, n, k, p->ppart, p->psums[0],
+                              p->ppr_grid_n, st));
+  int yb = p->ppr_zeroed;
+  if (yb < 0) {
+    yb = 0;
+    HIP_TRY(launch_spmm_zero(p->dtype, p->tile_y, (int32_t)p->tile_num, p->pbuf[0], k, k, st));
+  }
+  void* xs[2] = {X_inout, p->pbuf[2]};
+  double host_sums[128];
+  int t = 0;
+  bool converged = false;
+  while (t < max_iter) {
+    int len = check_every - t % check_every;
+    if (len > max_iter - t) len = max_iter - t;
+    const int t0 = t, yb0 = yb;
+    auto enqueue = [&](hipStream_t s) -> int {
+      for (int i = 0; i < len; ++i) {
+        const int cur = (t0 + i) & 1, b = yb0 ^ (i & 1);
+        const int r = run_spmm(p, xs[cur], k, p->pbuf[b], k, p->pbuf[b ^ 1], k, k, s);
+        if (r != MERBIT_OK) return r;
+        HIP_TRY(launch_ppr_update(p->dtype, p->pbuf[b], xs[cur], xs[cur ^ 1], p->dmask, n, k,
+                                  alpha, p->psrc, p->psums[cur], p->ppart, p->psums[cur ^ 1],
+                                  p->ppr_grid_n, s));
+      }
+      return MERBIT_OK;
+    };
+    rc = len == check_every
+             ? run_chunk(p, kLoopPersonalized, t0 & 1, yb0, len, k, X_inout, alpha, enqueue, st)
+             : enqueue(st);
+    if (rc != MERBIT_OK) return rc;
+    t += len;
+    yb ^= len & 1;
+    if (tol > 0.0 || t == max_iter) {
+      HIP_TRY(hipMemcpyAsync(host_sums, p->psums[t & 1], sizeof host_sums,
+                             hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      double worst = 0.0;
+      for (int j = 0; j < k; ++j) {
+        if (resid_out) resid_out[j] = host_sums[2 * j + 1];
+        if (host_sums[2 * j + 1] > worst) worst = host_sums[2 * j + 1];
+      }
+      if (tol > 0.0 && worst < tol) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  p->ppr_zeroed = yb;
+  p->last_stream = st;
+  if (t & 1) HIP_TRY(hipMemcpyAsync(X_inout, p->pbuf[2], bytes, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (iters_out) *iters_out = t;
+  return (tol > 0.0 && !converged) ? MERBIT_NOT_CONVERGED : MERBIT_OK;
+}
+
+// Row-chunk tables for the graphs of graph_ptr (rebuilt when it changes).
+
+}  // extern "C"

@@ -178,7 +178,8 @@ template <typename V>
 __global__ __launch_bounds__(kPprThreads) void ppr_update_kernel(
     const V* __restrict__ Y, const V* __restrict__ X_old, V* __restrict__ X_new,
     const uint32_t* __restrict__ dmask, int64_t n, int k, double alpha,
-    const int32_t* __restrict__ src, const double* __restrict__ delta_in,  // (dangling mass, l1 change) per column
+    const int32_t* __restrict__ src,
+    const double* __restrict__ delta_in,  // (dangling mass, l1 change) per column
     double* __restrict__ part_out) {
   __shared__ double s_d[kPprThreads], s_r[kPprThreads];
   const int j = threadIdx.x & 63;

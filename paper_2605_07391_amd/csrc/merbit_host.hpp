@@ -1,0 +1,162 @@
+// Host-side state of a plan and the helpers the C-ABI entry points share
+// (internal to libmerbit; the public interface is include/merbit.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/merbit.h"
+
+#include "merbit_internal.hpp"
+
+struct merbit_plan {
+  int64_t n_rows = 0, n_cols = 0, nnz = 0;
+  int dtype = 0, sigma = 0, block_lanes = 0, waves = 0, bits = 0;
+  int device = 0;
+  int commit = MERBIT_COMMIT_WAVE;  // kernel family
+  int blocks_per_cu_req = 0;
+  int64_t tile_num = 0, lane_num = 0;
+  int64_t chunk_num = 0;  // commit units
+  int unit_tiles = 1;     // tiles per commit unit: 1 (wave) or waves (block)
+  int grid = 0, chunks_per_block = 1;
+  int32_t* tile_x = nullptr;
+  uint32_t* tile_y = nullptr;
+  uint32_t* lane_desc = nullptr;
+  uint64_t* lane_desc64 = nullptr;  // set instead of lane_desc for 64-bit descriptors
+  int desc_bits = 32;
+  const int32_t* col = nullptr;
+  const void* values = nullptr;
+  hipStream_t last_stream = nullptr;
+  // small device scratch: [0] validation flags / fast-tile count
+  unsigned long long* scratch = nullptr;
+  // hot-column x cache (hot_n > 0: the fused kernel reads col from colx)
+  int32_t hot_n = 0;
+  bool hot_all = false;        // every column is hot: slot = column, x itself is copied
+  int32_t* hot_cols = nullptr; // [hot_n] column of each slot (partial mode)
+  int32_t* colx = nullptr;     // [nnz] recoded column stream
+  void* x_hot = nullptr;       // [hot_n] gathered hot x values (partial mode)
+  size_t hot_lds_bytes = 0;
+  double hot_coverage = 0.0;   // fraction of nonzeros whose column is hot
+  // PageRank state
+  uint32_t* dmask = nullptr;
+  void* ybuf[2] = {nullptr, nullptr};
+  void* xwork = nullptr;
+  // per-block (dangling mass, l1 change) pairs of the last two reductions
+  double* partials[2] = {nullptr, nullptr};
+  int reduce_grid = 0;
+  int zeroed_buf = -1;  // which ybuf is zero at the boundary rows, -1 if none
+  // personalised PageRank state (k columns)
+  int ppr_k = 0;
+  void* pbuf[3] = {nullptr, nullptr, nullptr};  // two SpMM outputs, one iterate
+  double* ppart = nullptr;                      // per-block, per-column pairs
+  double* psums[2] = {nullptr, nullptr};        // per-column (dangling mass, l1 change)
+  int32_t* psrc = nullptr;
+  int ppr_grid_n = 0;
+  int ppr_zeroed = -1;
+  // PageRank of the graphs on the diagonal (tables for the last graph_ptr)
+  std::vector<int64_t> multi_gp;
+  int32_t* multi_chunk_row = nullptr;
+  int32_t* multi_chunk_graph = nullptr;
+  int32_t* multi_chunk_ptr = nullptr;
+  double* multi_gsize = nullptr;
+  double* multi_part = nullptr;
+  double* multi_gsum[2] = {nullptr, nullptr};
+  int32_t multi_chunks = 0;
+  // BiCGSTAB state: r, r^, p, v (two), s, t; pair arrays of the dot products
+  void* bvec[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* bpart[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  int bicg_G = 0;
+  // HIP graphs of iteration chunks (the PageRank drivers); a graph holds the
+  // pointers and scalars it was captured with, so any change of a captured
+  // buffer bumps `generation` and drops the graphs
+  bool eager_loops = false;
+  hipStream_t cap_stream = nullptr;
+  uint64_t generation = 0;
+  struct LoopGraph {
+    int kind, parity, ybuf, len, k;
+    const void* x;
+    const void* aux;  // a second captured operand (adjoint: g)
+    double alpha;
+    uint64_t gen;
+    hipGraphExec_t exec;
+  };
+  std::vector<LoopGraph> loop_graphs;
+  // kernel timing
+  bool profiling = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used = 0;
+};
+
+namespace merbit {
+
+// Set the calling thread's error message; returns code.
+int fail(int code, const std::string& msg);
+// MERBIT_ENOMEM or MERBIT_EHIP with the HIP error string.
+int fail_hip(const char* what, hipError_t e);
+
+#define HIP_TRY(expr)                                  \
+  do {                                                 \
+    hipError_t _e = (expr);                            \
+    if (_e != hipSuccess) return merbit::fail_hip(#expr, _e);  \
+  } while (0)
+
+inline size_t vsize(int dtype) { return dtype == MERBIT_F64 ? sizeof(double) : sizeof(float); }
+
+void plan_free_all(merbit_plan* p);
+// The fused SpMV y = A x (z: the other dual buffer, cleared at boundary rows, or nullptr).
+int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st);
+// A buffer or value array that captured graphs use has changed: drop them.
+void invalidate_graphs(merbit_plan* p);
+// Dangling mask and the PageRank iteration buffers (allocated on first use).
+int ensure_dmask(merbit_plan* p, hipStream_t st);
+int ensure_pagerank_state(merbit_plan* p, hipStream_t st);
+
+enum { kLoopPageRank = 1, kLoopPersonalized = 2, kLoopMulti = 3, kLoopAdjoint = 4,
+       kLoopBicgstab = 5 };
+
+// Enqueue one chunk of iterations on `st`.  The first time a chunk with this
+// key is seen, `enqueue` is recorded on the plan's capture stream into a HIP
+// graph, which is instantiated and kept; later chunks with the same key launch
+// the graph (one launch instead of two or three per iteration).  Without
+// graphs (eager_loops, or while kernel timing is on) `enqueue` runs on `st`.
+template <typename F>
+int run_chunk(merbit_plan* p, int kind, int parity, int ybuf, int len, int k,
+                     const void* x, double alpha, F&& enqueue, hipStream_t st,
+                     const void* aux = nullptr) {
+  if (p->eager_loops || p->profiling) return enqueue(st);
+  for (auto& g : p->loop_graphs)
+    if (g.kind == kind && g.parity == parity && g.ybuf == ybuf && g.len == len && g.k == k &&
+        g.x == x && g.aux == aux && g.alpha == alpha && g.gen == p->generation) {
+      HIP_TRY(hipGraphLaunch(g.exec, st));
+      return MERBIT_OK;
+    }
+  if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
+  const int rc = enqueue(p->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+  if (rc != MERBIT_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail_hip("hipStreamEndCapture", e);
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return fail_hip("hipGraphInstantiate", e2);
+  if (p->loop_graphs.size() >= 8) {  // keep a few; the oldest goes first
+    HIP_TRY(hipStreamSynchronize(st));
+    (void)hipGraphExecDestroy(p->loop_graphs.front().exec);
+    p->loop_graphs.erase(p->loop_graphs.begin());
+  }
+  p->loop_graphs.push_back({kind, parity, ybuf, len, k, x, aux, alpha, p->generation, exec});
+  HIP_TRY(hipGraphLaunch(exec, st));
+  return MERBIT_OK;
+}
+
+}  // namespace merbit
