@@ -73,9 +73,9 @@ static SpmvArgs spmv_args(const merbit_plan* p, const void* x, void* y, void* z)
 
 // Launch the fused kernel (after the hot gather), bracketed by events when
 // profiling is on.
-int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st) {
+int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st, bool hot_ready) {
   if (p->chunk_num == 0) return MERBIT_OK;
-  if (p->hot_n > 0 && !p->hot_all)
+  if (p->hot_n > 0 && !p->hot_all && !hot_ready)
     HIP_TRY(launch_hot_gather(p->dtype, x, p->hot_cols, p->hot_n, p->x_hot, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (p->profiling) {

@@ -47,20 +47,27 @@ int merbit_pagerank(merbit_plan* p, double alpha, double tol, int max_iter, int 
     int len = check_every - t % check_every;
     if (len > max_iter - t) len = max_iter - t;
     const int t0 = t, yb0 = yb;
+    // with a partial hot-column cache the update also writes the next
+    // iterate's hot values, so only the call's first SpMV gathers them
+    const bool fuse_hot = p->hot_n > 0 && !p->hot_all;
     auto enqueue = [&](hipStream_t s) -> int {
       for (int i = 0; i < len; ++i) {
         const int cur = (t0 + i) & 1, b = yb0 ^ (i & 1);
-        const int r = run_fused(p, xs[cur], p->ybuf[b], p->ybuf[b ^ 1], s);
+        const int r = run_fused(p, xs[cur], p->ybuf[b], p->ybuf[b ^ 1], s,
+                                fuse_hot && t0 + i > 0);
         if (r != MERBIT_OK) return r;
         HIP_TRY(launch_pr_update(p->dtype, p->ybuf[b], xs[cur], xs[cur ^ 1], p->dmask, n, alpha,
                                  p->partials[cur], p->reduce_grid, p->partials[cur ^ 1],
-                                 p->reduce_grid, s));
+                                 p->reduce_grid, s, fuse_hot ? p->hot_cols : nullptr,
+                                 fuse_hot ? p->hot_n : 0, fuse_hot ? p->x_hot : nullptr));
       }
       return MERBIT_OK;
     };
-    rc = len == check_every
-             ? run_chunk(p, kLoopPageRank, t0 & 1, yb0, len, 0, x_inout, alpha, enqueue, st)
-             : enqueue(st);
+    // the call's first chunk gathers the hot values, later ones do not: a
+    // different graph (key k = 1 for the first chunk)
+    rc = len == check_every ? run_chunk(p, kLoopPageRank, t0 & 1, yb0, len, t0 == 0 ? 1 : 0,
+                                        x_inout, alpha, enqueue, st)
+                            : enqueue(st);
     if (rc != MERBIT_OK) return rc;
     t += len;
     yb ^= len & 1;

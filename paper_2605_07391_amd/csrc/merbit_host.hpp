@@ -108,8 +108,11 @@ int fail_hip(const char* what, hipError_t e);
 inline size_t vsize(int dtype) { return dtype == MERBIT_F64 ? sizeof(double) : sizeof(float); }
 
 void plan_free_all(merbit_plan* p);
-// The fused SpMV y = A x (z: the other dual buffer, cleared at boundary rows, or nullptr).
-int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st);
+// The fused SpMV y = A x (z: the other dual buffer, cleared at boundary rows,
+// or nullptr).  hot_ready: the plan's hot-column copy already holds x's hot
+// values (written by the PageRank update), so the gather launch is skipped.
+int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st,
+              bool hot_ready = false);
 // A buffer or value array that captured graphs use has changed: drop them.
 void invalidate_graphs(merbit_plan* p);
 // Dangling mask and the PageRank iteration buffers (allocated on first use).

@@ -258,7 +258,8 @@ hipError_t launch_dangling_sum(int dtype, const void* x, const uint32_t* dmask, 
 hipError_t launch_pr_update(int dtype, const void* y, const void* x_old, void* x_new,
                             const uint32_t* dmask, int64_t n, double alpha,
                             const double* partials_in, int n_in, double* partials_out, int grid,
-                            hipStream_t st);
+                            hipStream_t st, const int32_t* hot_cols = nullptr,
+                            int32_t hot_n = 0, void* x_hot = nullptr);
 int pr_reduce_grid(int64_t n);
 
 // Adjoint pieces.

@@ -112,11 +112,15 @@ hipError_t launch_dangling_sum(int dtype, const void* x, const uint32_t* dmask, 
 // x_new = alpha y + (alpha delta + 1 - alpha) / n, with delta the dangling
 // mass of x_old (summed from the previous kernel's partials).  Writes this
 // block's dangling mass of x_new and ||x_new - x_old||_1 to partials_out.
+// With hot_n > 0 it also writes the hot-column copy of x_new that the next
+// SpMV's LDS cache reads (x_hot[s] = x_new[hot_cols[s]], the same fused
+// multiply-add on the same operands), so that SpMV needs no gather launch.
 template <typename V>
 __global__ __launch_bounds__(kReduceThreads) void pr_update_kernel(
     const V* __restrict__ y, const V* __restrict__ x_old, V* __restrict__ x_new,
     const uint32_t* __restrict__ dmask, int64_t n, double alpha,
-    const double* __restrict__ partials_in, int n_in, double* __restrict__ partials_out) {
+    const double* __restrict__ partials_in, int n_in, double* __restrict__ partials_out,
+    const int32_t* __restrict__ hot_cols, int32_t hot_n, V* __restrict__ x_hot) {
   constexpr int ILP = 4;
   const double delta = sum_partials_first(partials_in, n_in);
   const V teleport = (V)((alpha * delta + 1.0 - alpha) / (double)n);
@@ -138,13 +142,16 @@ __global__ __launch_bounds__(kReduceThreads) void pr_update_kernel(
     for (int u = 0; u < ILP; ++u) {
       const int64_t i = base + (int64_t)u * kReduceThreads;
       if (i < n) {
-        const V xn = a * yv[u] + teleport;
+        const V xn = fma(a, yv[u], teleport);
         x_new[i] = xn;
         rsum += fabs((double)xn - (double)xo[u]);
         if ((mw[u] >> (i & 31)) & 1u) dsum += (double)xn;
       }
     }
   }
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < hot_n;
+       h += (int64_t)gridDim.x * blockDim.x)
+    x_hot[h] = fma(a, y[hot_cols[h]], teleport);
   block_sum2(dsum, rsum);
   if (threadIdx.x == 0) {
     partials_out[2 * blockIdx.x] = dsum;
@@ -155,17 +162,18 @@ __global__ __launch_bounds__(kReduceThreads) void pr_update_kernel(
 hipError_t launch_pr_update(int dtype, const void* y, const void* x_old, void* x_new,
                             const uint32_t* dmask, int64_t n, double alpha,
                             const double* partials_in, int n_in, double* partials_out, int grid,
-                            hipStream_t st) {
+                            hipStream_t st, const int32_t* hot_cols, int32_t hot_n,
+                            void* x_hot) {
   if (dtype == 0)
     hipLaunchKernelGGL(pr_update_kernel<float>, dim3(grid), dim3(kReduceThreads), 0, st,
                        static_cast<const float*>(y), static_cast<const float*>(x_old),
                        static_cast<float*>(x_new), dmask, n, alpha, partials_in, n_in,
-                       partials_out);
+                       partials_out, hot_cols, hot_n, static_cast<float*>(x_hot));
   else
     hipLaunchKernelGGL(pr_update_kernel<double>, dim3(grid), dim3(kReduceThreads), 0, st,
                        static_cast<const double*>(y), static_cast<const double*>(x_old),
                        static_cast<double*>(x_new), dmask, n, alpha, partials_in, n_in,
-                       partials_out);
+                       partials_out, hot_cols, hot_n, static_cast<double*>(x_hot));
   return hipGetLastError();
 }
 

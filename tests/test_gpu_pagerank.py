@@ -24,12 +24,13 @@ def _x0(n, dtype, dev):
     return x0.astype(np.float64), torch.from_numpy(x0).to(dev)
 
 
+@pytest.mark.parametrize("hot", [-1, 37], ids=["all_hot", "partial_hot"])
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
-def test_chung_lu_20_iterations_iterate_by_iterate(dtype):
+def test_chung_lu_20_iterations_iterate_by_iterate(dtype, hot):
     dev = require_gpu()
     w = workload("chung_lu_10k")
     n = w["n_rows"]
-    plan, keep = _plan(w, dtype, dev)
+    plan, keep = _plan(w, dtype, dev, hot_columns=hot)
     x0_64, x0 = _x0(n, dtype, dev)
     vals = host_values(w["values"], dtype)
     _, resid_ref, hist = oracle.pagerank(w["row_ptr"], w["col"], vals, ALPHA, 20, x0_64,
@@ -150,17 +151,22 @@ def test_rmat22_pagerank_iterates(dtype):
     plan.close()
 
 
+@pytest.mark.parametrize("hot", [-1, 37], ids=["all_hot", "partial_hot"])
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
-def test_graph_replays_match_eager(dtype):
+def test_graph_replays_match_eager(dtype, hot):
     """Iteration chunks recorded in HIP graphs: the first call captures the
-    chunk, later calls replay it.  Five calls with eager work (a plain SpMV,
-    an eager-mode plan) and synchronisations between them; every replay is
-    checked against the oracle and against the eager plan."""
+    chunks, later calls replay them.  Five calls with eager work (a plain
+    SpMV, an eager-mode plan) and synchronisations between them; every replay
+    is checked against the oracle and against the eager plan.  With a partial
+    hot-column cache the update writes the next iterate's hot values and only
+    each call's first chunk gathers them."""
     dev = require_gpu()
     w = workload("chung_lu_10k")
     n = w["n_rows"]
-    plan, keep = _plan(w, dtype, dev)
-    eager, keep2 = _plan(w, dtype, dev, eager_loops=True)
+    plan, keep = _plan(w, dtype, dev, hot_columns=hot)
+    eager, keep2 = _plan(w, dtype, dev, eager_loops=True, hot_columns=hot)
+    if hot > 0:
+        assert 0 < plan.info()["hot_columns"] <= hot
     x0_64, x0 = _x0(n, dtype, dev)
     vals = host_values(w["values"], dtype)
     ref, _, _ = oracle.pagerank(w["row_ptr"], w["col"], vals, ALPHA, 12, x0_64)
