@@ -316,6 +316,63 @@ def measured_copy_gbs(mib: int = 1024, reps: int = 5) -> float:
     return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
+def run_adjoint(scale: int, iters: int, alpha: float):
+    """Differentiable PageRank on R-MAT (scale 20 by default), FP32: weights in
+    (0.5, 1.5] column-normalised, loss ||pr(w) - t||^2.  Times the forward
+    power method and the backward pass (adjoint fixed point on the transposed
+    plan + per-nonzero value gradient + column-normalisation backward), both
+    with `iters` iterations, and the transposed SpMV against the forward one."""
+    import numpy as np
+    import torch
+
+    import graphgen
+    import paper_2605_07391_amd.autograd as ag
+    dev = torch.device("cuda:0")
+    w = graphgen.workload(f"rmat{scale}")
+    n, m = w["n_rows"], w["nnz"]
+    r = torch.from_numpy(w["row_ptr"]).to(dev)
+    c = torch.from_numpy(w["col"]).to(dev)
+    op = ag.DiffPageRank(r, c, n, dtype=torch.float32, alpha=alpha, tol=0.0, max_iter=iters)
+    w0 = torch.from_numpy(graphgen.uniform(5, 83, m, 0.5, 1.5, closed_high=True)).float().to(dev)
+    t0 = graphgen.uniform(6, 84, n, 0.0, 1.0)
+    tgt = torch.from_numpy(t0 / t0.sum()).float().to(dev)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+
+    def step():
+        wt = w0.clone().requires_grad_(True)
+        ev[0].record()
+        x = op(wt)
+        loss = ((x - tgt) ** 2).sum()
+        ev[1].record()
+        ev[2].record()
+        loss.backward()
+        ev[3].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]), ev[2].elapsed_time(ev[3]), wt.grad
+
+    step()
+    fwd, bwd, grad = step()
+    # kernel time of the forward and the transposed SpMV over one more step
+    op.plan.profile_enable(True)
+    op.plan_t.profile_enable(True)
+    step()
+    nf, tf = op.plan.profile_read()
+    nt, tt = op.plan_t.profile_read()
+    op.plan.profile_enable(False)
+    op.plan_t.profile_enable(False)
+    op.close()
+    spmv_f = tf / max(nf, 1)
+    spmv_t = tt / max(nt, 1)
+    return {"workload": f"rmat{scale}_diff_pagerank", "dtype": "f32", "n": n, "nnz": int(m),
+            "iterations": iters, "forward_ms": round(fwd, 3), "backward_ms": round(bwd, 3),
+            "backward_vs_forward": round(bwd / fwd, 3),
+            "forward_spmv_us": round(spmv_f * 1e3, 1),
+            "transposed_spmv_us": round(spmv_t * 1e3, 1),
+            "transposed_vs_forward_spmv": round(spmv_t / spmv_f, 3),
+            "grad_finite": bool(torch.isfinite(grad).all().item()),
+            "seeds": {"graph": scale, "w": 5, "target": 6}}
+
+
 def cpu_baseline(w, iters: int, alpha: float, dtype_name: str = "f32"):
     import numpy as np
 
@@ -362,6 +419,9 @@ def main():
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched runs (64-source PPR, 256 graphs)")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--no-adjoint", action="store_true",
+                    help="skip the differentiable-PageRank run (R-MAT scale 20)")
+    ap.add_argument("--adjoint-scale", type=int, default=20)
     ap.add_argument("--no-bicgstab", action="store_true",
                     help="skip the BiCGSTAB run on the symmetric 0/1 R-MAT system")
     ap.add_argument("--bicgstab-scale", type=int, default=21)
@@ -428,6 +488,11 @@ def main():
         print(f"[bench] multi256: step {multi['ms_per_step']:.3f} ms", file=sys.stderr,
               flush=True)
         batched = {"ppr64_" + args.workload + "_f32": ppr, "chung_lu_multi256_f32": multi}
+    adj = None
+    if not args.no_adjoint and w["meta"]["generator"] == "rmat":
+        adj = run_adjoint(args.adjoint_scale, 50, args.alpha)
+        print(f"[bench] adjoint: forward {adj['forward_ms']:.2f} ms, backward "
+              f"{adj['backward_ms']:.2f} ms", file=sys.stderr, flush=True)
     bicg = None
     if not args.no_bicgstab and w["meta"]["generator"] == "rmat":
         bicg = run_bicgstab(args.bicgstab_scale, args.batched_steps * 10)
@@ -481,6 +546,7 @@ def main():
         "f64": extra,
         "batched": batched,
         "bicgstab": bicg,
+        "adjoint": adj,
     }
     print(json.dumps(out), flush=True)
 
