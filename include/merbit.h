@@ -62,8 +62,9 @@ typedef enum {
 typedef struct {
     int32_t sigma;         /* steps per lane; 0 = 12 (F32) / 7 (F64).  Must satisfy
                               2 ceil(log2(64 sigma)) + sigma <= 32: 1..12 are built     */
-    int32_t block_lanes;   /* threads per block; 0 = 512 (WAVE) / 256 (BLOCK).  Built:
-                              BLOCK 128, 256, 512, 1024; WAVE 256, 512, 1024           */
+    int32_t block_lanes;   /* threads per block; 0 = WAVE: 1024 (FP32, 32-bit
+                              descriptors) or 512, BLOCK: 256.  Built: BLOCK 128, 256,
+                              512, 1024; WAVE 256, 512, 1024 (64-bit: 256, 512)        */
     int32_t commit;        /* merbit_commit                                            */
     int32_t hot_columns;   /* LDS x cache for the most frequent columns -- an addition
                               to the paper's method: on gfx950 scattered x gathers are

@@ -350,7 +350,11 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   if (nnz > 0 && (!col_ind || !values)) return fail(MERBIT_EINVAL, "col_ind/values NULL");
   if (nnz > 0 && n_rows == 0) return fail(MERBIT_EINVAL, "nonzeros without rows");
   if (sigma == 0) sigma = dtype == MERBIT_F32 ? 12 : 7;
-  if (block_lanes == 0) block_lanes = commit == MERBIT_COMMIT_WAVE ? 512 : 256;
+  // defaults: the best block size measured for each family (R-MAT 22)
+  if (block_lanes == 0)
+    block_lanes = commit != MERBIT_COMMIT_WAVE                   ? 256
+                  : (dtype == MERBIT_F32 && opts.desc_bits != 64) ? 1024
+                                                                  : 512;
   const int desc_bits = opts.desc_bits == 0 ? 32 : opts.desc_bits;
   if (desc_bits != 32 && desc_bits != 64) return fail(MERBIT_EINVAL, "desc_bits must be 32 or 64");
   if (desc_bits == 64 && commit != MERBIT_COMMIT_WAVE)
