@@ -2,11 +2,13 @@
 MI355X, R-MAT scale 22 (4,194,304 rows, ~65.2M nonzeros after merging).
 
 A step is one PageRank iteration: the fused SpMV kernel (y = P x) plus the
-update kernel (x' = alpha y + teleport, dangling mass and l1 change).  The
-plan is built once and timed separately.  `value` is nonzeros processed per
-second over the timed steps (GNZ/s).  The roofline block reports the fused
-SpMV kernel: algorithmic bytes per launch / mean launch time from HIP events,
-against the MI355X HBM peak.  The CPU baseline is the oracle (single thread)
+update kernel (x' = alpha y + teleport, dangling mass and l1 change); with a
+column-stripe plan the SpMV is the fused kernel on the stacked matrix plus the
+kernel that adds each row's stripes.  The plan is built once and timed
+separately.  `value` is nonzeros processed per second over the timed steps
+(GNZ/s).  The roofline block reports the SpMV: algorithmic bytes per SpMV /
+mean SpMV time from HIP events around its launches, against the MI355X HBM
+peak.  The CPU baseline is the oracle (single thread)
 timed on a bounded number of iterations of the same workload.
 
 Prints one JSON line.
@@ -29,11 +31,21 @@ CSRC = os.path.join(ROOT, "paper_2605_07391_amd", "csrc")
 # fused SpMV kernel of each commit family: (kernel name, source file)
 KERNELS = {1: ("merbit::spmv_kernel", "merbit_spmv.hip"),
            2: ("merbit::spmv_wave_kernel", "merbit_spmv_wave.hip")}
+# a striped plan's SpMV is the wave kernel on the stacked matrix plus the
+# kernel that sums each row's stripes
+COMBINE = ("merbit::stripe_combine_kernel", "merbit_stripes.hip")
 
 
-def spmv_source_hash(commit: int) -> str:
-    with open(os.path.join(CSRC, KERNELS[commit][1]), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def spmv_kernels(commit: int, stripes: int):
+    return [KERNELS[commit]] + ([COMBINE] if stripes > 1 else [])
+
+
+def spmv_source_hash(commit: int, stripes: int = 1) -> str:
+    h = hashlib.sha256()
+    for _, src in spmv_kernels(commit, stripes):
+        with open(os.path.join(CSRC, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def algorithmic_bytes(info: dict, value_size: int) -> float:
@@ -47,23 +59,24 @@ def algorithmic_bytes(info: dict, value_size: int) -> float:
             + 4 * lanes * (1.0 - r_f))
 
 
-def load_traffic(workload: str, dtype: str, commit: int):
-    """Measured HBM bytes per launch from the committed rocprofv3 counter
-    summary, if it was taken on the current source of the same kernel."""
+def load_traffic(workload: str, dtype: str, commit: int, stripes: int = 1):
+    """Measured HBM bytes per SpMV from the committed rocprofv3 counter
+    summary, if it was taken on the current source of the same kernels."""
     path = os.path.join(ROOT, "profiles", f"spmv_traffic_{workload}_{dtype}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
     if (not rec.get("kernel", "").startswith(KERNELS[commit][0] + "<")
-            or rec.get("spmv_source_sha256_16") != spmv_source_hash(commit)):
+            or rec.get("stripes", 1) != stripes
+            or rec.get("spmv_source_sha256_16") != spmv_source_hash(commit, stripes)):
         return None
     return rec.get("hbm_bytes_per_launch")
 
 
 def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes: int,
             alpha: float, hot_columns: int = -1, commit: str = "auto", blocks_per_cu: int = 0,
-            tune: bool = False):
+            tune: bool = False, stripes: int = 0):
     import numpy as np
     import torch
 
@@ -85,39 +98,52 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
         table_block = None
         cands = [(t, a, b, "wave" if commit == "auto" else commit)
                  for (a, b), t in table.items() if t > 0]
+        cands = [(t, a, b, cm, 0) for t, a, b, cm in cands]
+        table_block = table_striped = None
         if commit == "auto":
             # the paper's block-commit layout, b = 128 .. 1024 lanes, swept as well
             _, table_block = pkg.tune(r, c, v, n, reps=10, commit="block",
                                       hot_columns=hot_columns, block_lanes=[128, 256, 512, 1024])
-            cands += [(t, a, b, "block") for (a, b), t in table_block.items() if t > 0]
-        # the library default (sigma 12 / 7, 1024 / 512 lanes, wave commit)
-        # unless a candidate is more than 2 % faster: near-ties do not flip
-        # the configuration from run to run
+            cands += [(t, a, b, "block", 0) for (a, b), t in table_block.items() if t > 0]
+        if commit in ("auto", "wave") and stripes < 0:
+            # the column-stripe plan (8 stripes, one tile range per XCD); its
+            # time includes the launch that adds each row's stripes
+            _, table_striped = pkg.tune(r, c, v, n, reps=10, commit="wave",
+                                        hot_columns=hot_columns, stripes=8)
+            cands += [(t, a, b, "wave", 8) for (a, b), t in table_striped.items() if t > 0]
+        # the library default (sigma 12 / 7, 1024 / 512 lanes, wave commit, no
+        # stripes) unless a candidate is more than 2 % faster: near-ties do
+        # not flip the configuration from run to run
         d_sigma, d_lanes = (12, 1024) if dtype == torch.float32 else (7, 512)
-        t_best, b_sigma, b_lanes, b_commit = min(cands)
+        t_best, b_sigma, b_lanes, b_commit, b_stripes = min(cands)
         t_def = table.get((d_sigma, d_lanes), -1.0)
         if t_def > 0 and t_best >= 0.98 * t_def:
-            sigma, block_lanes, commit = d_sigma, d_lanes, "wave"
+            sigma, block_lanes, commit, stripes = d_sigma, d_lanes, "wave", 0
         else:
-            sigma, block_lanes, commit = b_sigma, b_lanes, b_commit
+            sigma, block_lanes, commit, stripes = b_sigma, b_lanes, b_commit, b_stripes
         best64, table64 = pkg.tune(r, c, v, n, reps=10, hot_columns=hot_columns, desc_bits=64,
                                    block_lanes=[256, 512])
-        tuning = {"chosen": {"sigma": sigma, "block_lanes": block_lanes, "commit": commit},
+        tuning = {"chosen": {"sigma": sigma, "block_lanes": block_lanes, "commit": commit,
+                             "stripes": stripes},
                   "rule": "fastest candidate if more than 2 % faster than the default "
                           "(sigma, lanes) of the wave kernel, else the default",
                   "us_per_spmv": {f"s{a}_b{b}": round(t, 1) for (a, b), t in table.items()},
                   "block_commit_us_per_spmv": None if table_block is None else {
                       f"s{a}_b{b}": round(t, 1) for (a, b), t in table_block.items()},
+                  "striped8_us_per_spmv": None if table_striped is None else {
+                      f"s{a}_b{b}": round(t, 1) for (a, b), t in table_striped.items()},
                   "desc64": {"best": best64,
                              "us_per_spmv": {f"s{a}_b{b}": round(t, 1)
                                              for (a, b), t in table64.items()},
                              "vs_32bit": round(min(t for t in table.values() if t > 0)
                                                / min(t for t in table64.values() if t > 0), 3)}}
+    stripes = max(stripes, 0)
     # plan build, timed on its own (kernel + allocation of TILE)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     plan = pkg.Plan(r, c, v, n, sigma=sigma, block_lanes=block_lanes, hot_columns=hot_columns,
-                    commit=commit, blocks_per_cu=blocks_per_cu, validate=False)
+                    commit=commit, blocks_per_cu=blocks_per_cu, validate=False,
+                    stripes=max(stripes, 0))
     e1.record()
     torch.cuda.synchronize()
     plan_ms = e0.elapsed_time(e1)
@@ -420,6 +446,8 @@ def main():
     ap.add_argument("--hot-columns", type=int, default=-1,
                     help="LDS x cache size in columns: -1 automatic, 0 off")
     ap.add_argument("--commit", default="auto", choices=["auto", "block", "wave"])
+    ap.add_argument("--stripes", type=int, default=-1,
+                    help="column stripes: -1 = the autotuner also tries 8, 0 = none, S = S")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--alpha", type=float, default=0.85)
     ap.add_argument("--cpu-iters", type=int, default=15)
@@ -464,14 +492,15 @@ def main():
 
     tune = not args.no_tune and args.sigma == 0 and args.block_lanes == 0
     main_run = run_gpu(w, args.dtype, args.steps, args.warmup, args.sigma, args.block_lanes,
-                       args.alpha, args.hot_columns, args.commit, args.blocks_per_cu, tune)
+                       args.alpha, args.hot_columns, args.commit, args.blocks_per_cu, tune,
+                       args.stripes)
     info = main_run["info"]
     print(f"[bench] {args.dtype}: step {main_run['step_ms'] * 1e3:.1f} us, spmv "
           f"{main_run['spmv_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
     extra = None
     if not args.no_f64 and args.dtype == "f32" and w["meta"]["generator"] != "stress":
         r64 = run_gpu(w, "f64", args.steps, args.warmup, 0, args.block_lanes, args.alpha,
-                      args.hot_columns, args.commit, args.blocks_per_cu, tune)
+                      args.hot_columns, args.commit, args.blocks_per_cu, tune, args.stripes)
         extra = {
             "value": round(r64["value_gnzs"], 3), "ms_per_step": round(r64["step_ms"], 5),
             "spmv_us": round(r64["spmv_ms"] * 1e3, 2), "spmv_gnzs": round(r64["spmv_gnzs"], 3),
@@ -480,7 +509,9 @@ def main():
             "plan_ms": round(r64["plan_ms"], 3), "sigma": r64["info"]["sigma"],
             "hot_columns": r64["info"]["hot_columns"],
             "hot_coverage": round(r64["info"]["hot_coverage"], 4),
-            "traffic": load_traffic(args.workload, "f64", r64["info"]["commit"]),
+            "traffic": load_traffic(args.workload, "f64", r64["info"]["commit"],
+                                    r64["info"]["stripes"]),
+            "stripes": r64["info"]["stripes"],
             "block_lanes": r64["info"]["block_lanes"],
             "commit": {1: "block", 2: "wave"}[r64["info"]["commit"]], "tuning": r64["tuning"],
         }
@@ -535,12 +566,16 @@ def main():
                    "commit": {1: "block", 2: "wave"}[info["commit"]],
                    "hot_columns": info["hot_columns"],
                    "hot_coverage": round(info["hot_coverage"], 4), "grid": info["grid"],
+                   "stripes": info["stripes"], "ranges": info["ranges"],
+                   "plan_rows": info["plan_rows"],
                    "alpha": args.alpha,
                    "seed": w["meta"].get("seed"), "x0": "1/n"},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": load_traffic(args.workload, args.dtype, info["commit"]),
-                     "kernel": KERNELS[info["commit"]][0],
+                     "traffic": load_traffic(args.workload, args.dtype, info["commit"],
+                                             info["stripes"]),
+                     "kernel": " + ".join(k for k, _ in spmv_kernels(info["commit"],
+                                                                     info["stripes"])),
                      "alg_bytes_per_launch": int(main_run["alg_bytes"]),
                      "mean_launch_us": round(main_run["spmv_ms"] * 1e3, 2),
                      "measured_copy_gbs": round(copy_gbs, 1),

@@ -90,6 +90,24 @@ typedef struct {
                               commit only; built: FP32 sigma 16, 20, 24, FP64 14, 16,
                               block_lanes 256 or 512).  SpMM and the adjoint pieces
                               need 32-bit plans.                                        */
+    int32_t stripes;       /* column stripes -- an addition to the paper's method for
+                              gfx950's per-XCD caches: 0 or 1 = off; S = 2, 4, 8, 16 or
+                              32 (wave commit only) cuts the columns into S stripes of
+                              equal width and plans the stacked matrix A' whose rows
+                              are the non-empty (stripe, row) pairs, stripe-major
+                              (A x = sum of each row's pairs in A' x).  The tiles are
+                              split into one contiguous range per XCD (8 on MI355X),
+                              so an XCD gathers from about one stripe of x at a time
+                              (L2-resident) and keeps the most frequent columns of its
+                              own range in LDS (hot_columns then applies per range).
+                              A second launch adds the stripes of each row in stripe
+                              order.  The plan then owns copies of col_ind and values
+                              in stacked order (values: re-copied by
+                              merbit_plan_set_values, so in-place changes of the
+                              array need that call) and two y' buffers [rows of A'].
+                              Needs nnz < 2^30.  SpMM, personalised / multi-graph
+                              PageRank, transpose, SDDMM and the adjoint return
+                              MERBIT_EUNSUPPORTED on such a plan.                       */
 } merbit_opts_t;
 
 typedef struct merbit_plan merbit_plan;
@@ -116,7 +134,12 @@ typedef struct {
                               a 1-in-s sample of the column stream, s <= 8, when the
                               cache holds only part of the columns)                     */
     int32_t desc_bits;     /* lane descriptor width: 32 or 64                           */
+    int32_t stripes;       /* column stripes (1 = none)                                 */
+    int32_t ranges;        /* contiguous tile ranges of the fused launch (1 = none)     */
     int32_t reserved;
+    int64_t plan_rows;     /* rows of the planned matrix: n_rows, or the (stripe, row)
+                              pairs of a striped plan; TILE and the exported arrays
+                              are those of that matrix                                 */
 } merbit_plan_info_t;
 
 /* Fill *opts (host pointer) with the defaults. */
@@ -142,7 +165,9 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz,
                        int dtype, const merbit_opts_t* opts, void* stream, merbit_plan** out);
 
 /* Replace the borrowed values pointer (same sparsity pattern, same dtype).
- * The TILE arrays depend only on row_ptr, so nothing is rebuilt. */
+ * The TILE arrays depend only on row_ptr, so nothing is rebuilt.  A striped
+ * plan copies the values into its stacked order (one gather on the plan's
+ * last stream). */
 int merbit_plan_set_values(merbit_plan* plan, const void* values);
 
 /* Fill *info (host pointer).  Counts the long-row tiles on the device and
@@ -170,6 +195,8 @@ int merbit_spmv(merbit_plan* plan, const void* x, void* y, void* stream);
  * y <- A x and zeroes z at the same rows, so z can be the next call's y.  y and
  * z: device [n_rows], distinct, not aliased with x. */
 int merbit_spmv_dual(merbit_plan* plan, const void* x, void* y, void* z, void* stream);
+/* (A striped plan keeps its own dual buffers of A' x: there y is written
+ * whole, z is not touched and merbit_zero_boundary does nothing.) */
 
 /* Zero v (device [n_rows]) at the first row of every commit unit. */
 int merbit_zero_boundary(merbit_plan* plan, void* v, void* stream);

@@ -38,7 +38,8 @@ void plan_free_all(merbit_plan* p) {
                   p->multi_chunk_ptr, p->multi_gsize, p->multi_part, p->multi_gsum[0],
                   p->multi_gsum[1], p->bvec[0], p->bvec[1], p->bvec[2], p->bvec[3], p->bvec[4],
                   p->bvec[5], p->bvec[6], p->bpart[0], p->bpart[1], p->bpart[2], p->bpart[3],
-                  p->bpart[4], p->bpart[5], p->bpart[6]};
+                  p->bpart[4], p->bpart[5], p->bpart[6], p->sperm, p->scol, p->svals, p->swords,
+                  p->yv[0], p->yv[1], p->range_tile, p->hot_off};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& ev : p->events) {
@@ -54,27 +55,41 @@ static SpmvArgs spmv_args(const merbit_plan* p, const void* x, void* y, void* z)
   a.tile_y = p->tile_y;
   a.lane_desc = p->lane_desc;
   a.lane_desc64 = p->lane_desc64;
-  a.col = p->hot_n > 0 ? p->colx : p->col;
-  a.val = p->values;
+  a.col = p->hot_n > 0 ? p->colx : (p->stripes > 1 ? p->scol : p->col);
+  a.val = p->stripes > 1 ? p->svals : p->values;
   a.x = x;
   a.x_hot = p->hot_n > 0 ? (p->hot_all ? x : p->x_hot) : nullptr;
   a.y = y;
   a.z = z;
   a.tile_num = (int32_t)p->tile_num;
   a.lane_num = (int32_t)p->lane_num;
-  a.path_len = (int32_t)(p->nnz + p->n_rows);
-  a.n_rows = (int32_t)p->n_rows;
+  a.path_len = (int32_t)(p->nnz + p->plan_rows);
+  a.n_rows = (int32_t)p->plan_rows;
   a.chunk_num = (int32_t)p->chunk_num;  // commit units of the block kernel
   a.chunks_per_block = p->chunks_per_block;
   a.grid = p->grid;
   a.hot_n = p->hot_n;
+  a.ranges = p->ranges;
+  a.range_tile = p->range_tile;
+  a.hot_off = p->hot_off;
   return a;
 }
 
+int zero_boundary(merbit_plan* p, void* v, hipStream_t st) {
+  if (p->stripes > 1 || p->chunk_num == 0) return MERBIT_OK;
+  HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->chunk_num, p->unit_tiles, v, st));
+  return MERBIT_OK;
+}
+
 // Launch the fused kernel (after the hot gather), bracketed by events when
-// profiling is on.
+// profiling is on.  A striped plan runs the kernel on its own dual buffers of
+// A' x and then sums each row's stripes into y (inside the same events).
 int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st, bool hot_ready) {
-  if (p->chunk_num == 0) return MERBIT_OK;
+  if (p->chunk_num == 0) {
+    // no tiles: the planned matrix has no rows (a striped plan always has
+    // nonzeros, so it never gets here)
+    return MERBIT_OK;
+  }
   if (p->hot_n > 0 && !p->hot_all && !hot_ready)
     HIP_TRY(launch_hot_gather(p->dtype, x, p->hot_cols, p->hot_n, p->x_hot, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -90,7 +105,14 @@ int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st, b
     ++p->events_used;
     HIP_TRY(hipEventRecord(e0, st));
   }
-  if (p->commit == MERBIT_COMMIT_WAVE)
+  if (p->stripes > 1) {
+    const int c = p->yv_cur;
+    HIP_TRY(launch_spmv_wave(p->dtype, p->sigma, p->waves, p->hot_n > 0, p->hot_lds_bytes,
+                             spmv_args(p, x, p->yv[c], p->yv[c ^ 1]), st, p->desc_bits == 64));
+    HIP_TRY(launch_stripe_combine(p->dtype, p->stripes, p->yv[c], p->plan_rows, p->swords,
+                                  p->words, p->n_rows, y, st));
+    p->yv_cur = c ^ 1;
+  } else if (p->commit == MERBIT_COMMIT_WAVE)
     HIP_TRY(launch_spmv_wave(p->dtype, p->sigma, p->waves, p->hot_n > 0, p->hot_lds_bytes,
                              spmv_args(p, x, y, z), st, p->desc_bits == 64));
   else
@@ -143,15 +165,6 @@ int ensure_pagerank_state(merbit_plan* p, hipStream_t st) {
   return MERBIT_OK;
 }
 
-}  // namespace merbit
-
-using namespace merbit;
-
-extern "C" {
-
-const char* merbit_last_error(void) { return g_last_error.c_str(); }
-
-const char* merbit_version(void) { return "merbit-mi355x 0.1 (gfx950, wave64)"; }
 
 // Static LDS of the fused kernel: block kernel = products + row slots of b
 // lanes plus head/tail partials; wave kernel = 64 sigma values per wavefront.
@@ -170,8 +183,10 @@ static bool kernel_supported(const merbit_plan* p, bool hot) {
 // Choose the grid.  Block kernel: one commit unit (b lanes) per block, or with
 // the hot cache as many blocks as fit at once, each taking a run of units.
 // Wave kernel: as many resident blocks as LDS and wavefront slots allow (or
-// blocks_per_cu), every wavefront striding over the tiles.
-static int size_grid(merbit_plan* p) {
+// blocks_per_cu), every wavefront striding over the tiles; a striped plan
+// rounds the grid down to a multiple of the XCD count and gives each XCD's
+// blocks (block b runs on XCD b mod 8) one contiguous range of tiles.
+int size_grid(merbit_plan* p) {
   p->unit_tiles = p->commit == MERBIT_COMMIT_WAVE ? 1 : p->waves;
   p->chunk_num = (p->tile_num + p->unit_tiles - 1) / p->unit_tiles;
   p->chunks_per_block = 1;
@@ -193,6 +208,12 @@ static int size_grid(merbit_plan* p) {
   if (p->commit == MERBIT_COMMIT_WAVE) {
     const int64_t need = (p->tile_num + p->waves - 1) / p->waves;  // one tile per wavefront
     p->grid = (int)(grid < need ? grid : need);
+    if (p->stripes > 1 && p->grid >= kXcds) {
+      p->grid -= p->grid % kXcds;
+      p->ranges = kXcds;
+    } else {
+      p->ranges = 1;
+    }
     return MERBIT_OK;
   }
   if (grid > p->chunk_num) grid = p->chunk_num;
@@ -205,6 +226,15 @@ static int size_grid(merbit_plan* p) {
 // when they all fit) and recode the column stream.  `cap` < 0 picks the
 // largest cap that leaves one block per CU room for its LDS, and keeps the
 // cache only if the hot columns hold at least 20 % of the nonzeros.
+int64_t hot_cap_lds(const merbit_plan* p) {
+  int lds_block = 0;
+  if (hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) !=
+      hipSuccess)
+    return 0;
+  int64_t cap = ((int64_t)lds_block - (int64_t)static_lds_bytes(p)) / (int64_t)vsize(p->dtype);
+  return (cap / 256) * 256;
+}
+
 static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
   p->hot_n = 0;
   if (cap_req == 0 || p->nnz == 0 || p->n_cols == 0) return MERBIT_OK;
@@ -216,12 +246,8 @@ static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
   if (!kernel_supported(p, true))
     return cap_req > 0 ? fail(MERBIT_EUNSUPPORTED, "hot cache not built for this block size")
                        : MERBIT_OK;
-  int lds_block = 0;
-  HIP_TRY(hipDeviceGetAttribute(&lds_block, hipDeviceAttributeMaxSharedMemoryPerBlock,
-                                p->device));
   const size_t vs = vsize(p->dtype);
-  int64_t cap_lds = ((int64_t)lds_block - (int64_t)static_lds_bytes(p)) / (int64_t)vs;
-  cap_lds = (cap_lds / 256) * 256;
+  const int64_t cap_lds = hot_cap_lds(p);
   int64_t cap = cap_req > 0 ? cap_req : cap_lds;
   if (cap > cap_lds) return fail(MERBIT_EUNSUPPORTED, "hot_columns exceeds the LDS budget");
   if (cap <= 0) return MERBIT_OK;
@@ -320,6 +346,48 @@ static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
   return MERBIT_OK;
 }
 
+int build_tile(merbit_plan* p, const int32_t* row_ptr, hipStream_t st) {
+  const int64_t L = p->nnz + p->plan_rows;
+  const int sigma = p->sigma;
+  p->tile_num = (L + (int64_t)kOmega * sigma - 1) / ((int64_t)kOmega * sigma);
+  p->lane_num = (L + sigma - 1) / sigma;
+  HIP_TRY(hipMalloc(&p->tile_x, sizeof(int32_t) * (size_t)(p->tile_num + 1)));
+  HIP_TRY(hipMalloc(&p->tile_y, sizeof(uint32_t) * (size_t)(p->tile_num + 1)));
+  const size_t lanes = (size_t)(p->lane_num > 0 ? p->lane_num : 1);
+  if (p->desc_bits == 64) HIP_TRY(hipMalloc(&p->lane_desc64, sizeof(uint64_t) * lanes));
+  else HIP_TRY(hipMalloc(&p->lane_desc, sizeof(uint32_t) * lanes));
+  if (p->plan_rows == 0) {
+    // empty path: TILE = {[0], [0]}
+    HIP_TRY(hipMemsetAsync(p->tile_x, 0, sizeof(int32_t), st));
+    HIP_TRY(hipMemsetAsync(p->tile_y, 0, sizeof(uint32_t), st));
+    return MERBIT_OK;
+  }
+  PlanArgs pa;
+  pa.row_ptr = row_ptr;
+  pa.n_rows = (int32_t)p->plan_rows;
+  pa.nnz = (int32_t)p->nnz;
+  pa.sigma = sigma;
+  pa.bits = p->bits;
+  pa.lane_num = p->lane_num;
+  pa.tile_num = p->tile_num;
+  pa.tile_x = p->tile_x;
+  pa.tile_y = p->tile_y;
+  pa.lane_desc = p->lane_desc;
+  pa.lane_desc64 = p->lane_desc64;
+  HIP_TRY(launch_plan(pa, st));
+  return MERBIT_OK;
+}
+
+}  // namespace merbit
+
+using namespace merbit;
+
+extern "C" {
+
+const char* merbit_last_error(void) { return g_last_error.c_str(); }
+
+const char* merbit_version(void) { return "merbit-mi355x 0.1 (gfx950, wave64)"; }
+
 void merbit_opts_init(merbit_opts_t* o) {
   if (!o) return;
   memset(o, 0, sizeof *o);
@@ -377,6 +445,13 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
                 : commit == MERBIT_COMMIT_WAVE ? "block_lanes must be 256, 512 or 1024"
                                                : "block_lanes must be 128, 256, 512 or 1024");
   if (opts.blocks_per_cu < 0) return fail(MERBIT_EINVAL, "blocks_per_cu < 0");
+  const int stripes = opts.stripes <= 1 ? 1 : opts.stripes;
+  if (opts.stripes < 0 || (stripes & (stripes - 1)) != 0 || stripes > 32)
+    return fail(MERBIT_EINVAL, "stripes must be 0, 1, 2, 4, 8, 16 or 32");
+  if (stripes > 1 && commit != MERBIT_COMMIT_WAVE)
+    return fail(MERBIT_EUNSUPPORTED, "column stripes need the wave commit kernel");
+  if (stripes > 1 && nnz >= ((int64_t)1 << 30))
+    return fail(MERBIT_EUNSUPPORTED, "column stripes need nnz < 2^30");
 
   hipStream_t st = static_cast<hipStream_t>(stream);
   merbit_plan* p = new merbit_plan();
@@ -396,9 +471,6 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   p->values = values;
   p->last_stream = st;
   (void)hipGetDevice(&p->device);
-  const int64_t L = nnz + n_rows;
-  p->tile_num = (L + (int64_t)kOmega * sigma - 1) / ((int64_t)kOmega * sigma);
-  p->lane_num = (L + sigma - 1) / sigma;
 
   hipError_t e;
 #define CREATE_TRY(expr)                       \
@@ -412,15 +484,6 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   } while (0)
 
   CREATE_TRY(hipMalloc(&p->scratch, 64));
-  CREATE_TRY(hipMalloc(&p->tile_x, sizeof(int32_t) * (size_t)(p->tile_num + 1)));
-  CREATE_TRY(hipMalloc(&p->tile_y, sizeof(uint32_t) * (size_t)(p->tile_num + 1)));
-  if (desc_bits == 64)
-    CREATE_TRY(hipMalloc(&p->lane_desc64,
-                         sizeof(uint64_t) * (size_t)(p->lane_num > 0 ? p->lane_num : 1)));
-  else
-    CREATE_TRY(hipMalloc(&p->lane_desc,
-                         sizeof(uint32_t) * (size_t)(p->lane_num > 0 ? p->lane_num : 1)));
-
   if (validate && (n_rows > 0 || nnz > 0)) {
     CREATE_TRY(hipMemsetAsync(p->scratch, 0, 64, st));
     CREATE_TRY(launch_validate(row_ptr, col_ind, n_rows, n_cols, nnz,
@@ -437,28 +500,18 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
       return fail(MERBIT_EINVAL, buf);
     }
   }
-  if (n_rows == 0) {
-    // empty path: TILE = {[0], [0]}
-    CREATE_TRY(hipMemsetAsync(p->tile_x, 0, sizeof(int32_t), st));
-    CREATE_TRY(hipMemsetAsync(p->tile_y, 0, sizeof(uint32_t), st));
-  } else {
-    PlanArgs pa;
-    pa.row_ptr = row_ptr;
-    pa.n_rows = (int32_t)n_rows;
-    pa.nnz = (int32_t)nnz;
-    pa.sigma = sigma;
-    pa.bits = bits;
-    pa.lane_num = p->lane_num;
-    pa.tile_num = p->tile_num;
-    pa.tile_x = p->tile_x;
-    pa.tile_y = p->tile_y;
-    pa.lane_desc = p->lane_desc;
-    pa.lane_desc64 = p->lane_desc64;
-    CREATE_TRY(launch_plan(pa, st));
-  }
 #undef CREATE_TRY
-  int rc = build_hot_cache(p, hot_columns, st);
-  if (rc == MERBIT_OK) rc = size_grid(p);
+  int rc;
+  if (stripes > 1 && nnz > 0) {
+    p->stripes = stripes;
+    rc = build_stripes(p, row_ptr, st);
+    if (rc == MERBIT_OK) rc = build_range_hot(p, hot_columns, st);
+  } else {
+    p->plan_rows = n_rows;
+    rc = build_tile(p, row_ptr, st);
+    if (rc == MERBIT_OK) rc = build_hot_cache(p, hot_columns, st);
+    if (rc == MERBIT_OK) rc = size_grid(p);
+  }
   if (rc != MERBIT_OK) {
     std::string msg = g_last_error;
     plan_free_all(p);
@@ -471,6 +524,11 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
 int merbit_plan_set_values(merbit_plan* p, const void* values) {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (p->nnz > 0 && !values) return fail(MERBIT_EINVAL, "values is NULL");
+  if (p->stripes > 1) {
+    // the stacked copy is rewritten in place: graphs keep valid pointers
+    p->values = values;
+    return stripes_copy_values(p, values, p->last_stream);
+  }
   if (values != p->values) invalidate_graphs(p);
   p->values = values;
   return MERBIT_OK;
@@ -497,6 +555,9 @@ int merbit_plan_info(merbit_plan* p, merbit_plan_info_t* info) {
   info->dtype = p->dtype;
   info->lds_bytes = (int32_t)(static_lds_bytes(p) + p->hot_lds_bytes);
   info->desc_bits = p->desc_bits;
+  info->stripes = p->stripes;
+  info->ranges = p->ranges;
+  info->plan_rows = p->plan_rows;
   if (p->tile_num > 0) {
     hipStream_t st = p->last_stream;
     unsigned long long cnt = 0;
@@ -535,7 +596,8 @@ int merbit_zero_boundary(merbit_plan* p, void* v, void* stream) {
   if (p->chunk_num == 0) return MERBIT_OK;
   if (!v) return fail(MERBIT_EINVAL, "vector is NULL");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->chunk_num, p->unit_tiles, v, st));
+  const int rc = zero_boundary(p, v, st);
+  if (rc != MERBIT_OK) return rc;
   p->last_stream = st;
   return MERBIT_OK;
 }
@@ -546,7 +608,8 @@ int merbit_spmv(merbit_plan* p, const void* x, void* y, void* stream) {
   if (!y || (p->nnz > 0 && !x)) return fail(MERBIT_EINVAL, "x or y is NULL");
   if (x == y) return fail(MERBIT_EINVAL, "x and y alias");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->chunk_num, p->unit_tiles, y, st));
+  const int rc = zero_boundary(p, y, st);
+  if (rc != MERBIT_OK) return rc;
   return run_fused(p, x, y, nullptr, st);
 }
 

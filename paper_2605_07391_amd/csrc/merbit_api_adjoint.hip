@@ -27,6 +27,7 @@ static TileRowsArgs tile_rows_args(const merbit_plan* p) {
 int merbit_transpose(merbit_plan* p, int32_t* rowT_ptr, int32_t* colT, int32_t* perm,
                      void* stream) {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->stripes > 1) return fail(MERBIT_EUNSUPPORTED, "not available on a striped plan");
   if (p->desc_bits != 32)
     return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
   if (!rowT_ptr || (p->nnz > 0 && (!colT || !perm)))
@@ -70,6 +71,7 @@ int merbit_transpose(merbit_plan* p, int32_t* rowT_ptr, int32_t* colT, int32_t* 
 int merbit_sddmm(merbit_plan* p, const void* g, const void* x, double scale, void* out,
                  void* stream) {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->stripes > 1) return fail(MERBIT_EUNSUPPORTED, "not available on a striped plan");
   if (p->desc_bits != 32)
     return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
   if (p->nnz == 0) return MERBIT_OK;

@@ -65,6 +65,7 @@ static int run_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t
 int merbit_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy, int k,
                 void* stream) {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->stripes > 1) return fail(MERBIT_EUNSUPPORTED, "not available on a striped plan");
   if (p->desc_bits != 32)
     return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
   if (k < 1) return fail(MERBIT_EINVAL, "k < 1");
@@ -85,6 +86,7 @@ int merbit_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy
 int merbit_spmm_dual(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy, void* Z,
                      int64_t ldz, int k, void* stream) {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->stripes > 1) return fail(MERBIT_EUNSUPPORTED, "not available on a striped plan");
   if (p->desc_bits != 32)
     return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
   if (k < 1) return fail(MERBIT_EINVAL, "k < 1");
@@ -97,6 +99,7 @@ int merbit_spmm_dual(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_
 
 int merbit_spmm_zero_boundary(merbit_plan* p, void* Y, int64_t ldy, int k, void* stream) {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->stripes > 1) return fail(MERBIT_EUNSUPPORTED, "not available on a striped plan");
   if (k < 1 || ldy < k) return fail(MERBIT_EINVAL, "bad k / leading dimension");
   if (p->tile_num == 0) return MERBIT_OK;
   if (!Y) return fail(MERBIT_EINVAL, "Y is NULL");
@@ -140,6 +143,7 @@ int merbit_pagerank_personalized(merbit_plan* p, double alpha, double tol, int m
                                  int* iters_out, double* resid_out, void* stream) {
   if (iters_out) *iters_out = 0;
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
+  if (p->stripes > 1) return fail(MERBIT_EUNSUPPORTED, "not available on a striped plan");
   if (p->desc_bits != 32)
     return fail(MERBIT_EUNSUPPORTED, "this call needs a plan with 32-bit descriptors");
   if (p->n_rows != p->n_cols) return fail(MERBIT_EINVAL, "PageRank needs a square matrix");

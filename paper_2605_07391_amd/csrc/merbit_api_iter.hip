@@ -34,8 +34,8 @@ int merbit_pagerank(merbit_plan* p, double alpha, double tol, int max_iter, int 
   int yb = p->zeroed_buf;
   if (yb < 0) {
     yb = 0;
-    HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->chunk_num, p->unit_tiles,
-                                 p->ybuf[0], st));
+    rc = zero_boundary(p, p->ybuf[0], st);
+    if (rc != MERBIT_OK) return rc;
   }
   void* xs[2] = {x_inout, p->xwork};
   std::vector<double> host_pairs(2 * (size_t)p->reduce_grid);
@@ -177,8 +177,8 @@ int merbit_pagerank_multi(merbit_plan* p, const int64_t* graph_ptr, int n_graphs
   int yb = p->zeroed_buf;
   if (yb < 0) {
     yb = 0;
-    HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->chunk_num, p->unit_tiles,
-                                 p->ybuf[0], st));
+    rc = zero_boundary(p, p->ybuf[0], st);
+    if (rc != MERBIT_OK) return rc;
   }
   void* xs[2] = {x_inout, p->xwork};
   std::vector<double> host_sums(2 * (size_t)n_graphs);
@@ -255,8 +255,8 @@ int merbit_pagerank_adjoint(merbit_plan* p, merbit_plan* pt, double alpha, doubl
   int yb = pt->zeroed_buf;
   if (yb < 0) {
     yb = 0;
-    HIP_TRY(launch_zero_boundary(pt->dtype, pt->tile_y, (int32_t)pt->chunk_num, pt->unit_tiles,
-                                 pt->ybuf[0], st));
+    const int rz = zero_boundary(pt, pt->ybuf[0], st);
+    if (rz != MERBIT_OK) return rz;
   }
   void* ls[2] = {lam_inout, pt->xwork};
   std::vector<double> host_pairs(2 * (size_t)pt->reduce_grid);
@@ -342,9 +342,9 @@ int merbit_bicgstab(merbit_plan* p, const void* b, void* x_inout, double tol, in
   a.t = p->bvec[6];
   // r_0 = b - A x_0 (t holds A x_0; the launch leaves v_even zero at the
   // boundary rows for iteration 0)
-  HIP_TRY(launch_zero_boundary(p->dtype, p->tile_y, (int32_t)p->chunk_num, p->unit_tiles, a.t,
-                               st));
-  int rc = run_fused(p, x_inout, a.t, p->bvec[3], st);
+  int rc = zero_boundary(p, a.t, st);
+  if (rc != MERBIT_OK) return rc;
+  rc = run_fused(p, x_inout, a.t, p->bvec[3], st);
   if (rc != MERBIT_OK) return rc;
   a.pa_next = p->bpart[0];
   a.pb_norm = p->bpart[6];

@@ -1,0 +1,248 @@
+// C ABI of libmerbit, column stripes (plan side): the stacked matrix A' of
+// the non-empty (stripe, row) pairs, its MERBIT plan, and one hot-column set
+// per tile range.  The kernels are in merbit_stripes.hip; the SpMV entry
+// points reach them through run_fused.
+#include <algorithm>
+#include <functional>
+#include <vector>
+
+#include "merbit_host.hpp"
+
+namespace merbit {
+
+namespace {
+// device buffers freed when the build leaves
+struct Scratch {
+  std::vector<void*> bufs;
+  ~Scratch() {
+    for (void* b : bufs)
+      if (b) (void)hipFree(b);
+  }
+  template <typename T>
+  hipError_t get(T** out, size_t count) {
+    void* b = nullptr;
+    hipError_t e = hipMalloc(&b, count > 0 ? count * sizeof(T) : 1);
+    if (e == hipSuccess) bufs.push_back(b);
+    *out = static_cast<T*>(b);
+    return e;
+  }
+};
+}  // namespace
+
+int stripes_copy_values(merbit_plan* p, const void* values, hipStream_t st) {
+  HIP_TRY(launch_gather_values(p->dtype, p->sperm, values, nullptr, p->svals, p->nnz, st));
+  return MERBIT_OK;
+}
+
+int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st) {
+  const int64_t m = p->nnz, n = p->n_rows;
+  const int sbits = ceil_log2(p->stripes);
+  int cbits = 0;  // columns are < 2^cbits
+  while (((int64_t)1 << cbits) < p->n_cols) ++cbits;
+  StripeSplitArgs a;
+  a.row_ptr = row_ptr;
+  a.col = p->col;
+  a.n_rows = n;
+  a.m = m;
+  a.shift = cbits > sbits ? cbits - sbits : 0;
+  a.key_bits = sbits;  // stripe indices are < 2^sbits
+  a.stripes = p->stripes;
+  a.words = (n + kOmega - 1) / kOmega;
+  p->words = a.words;
+  const int64_t nw = a.stripes * a.words;
+  Scratch tmp;
+  HIP_TRY(stripe_temp_bytes(m, nw, a.key_bits, &a.temp_bytes));
+  HIP_TRY(tmp.get(reinterpret_cast<unsigned char**>(&a.temp), a.temp_bytes));
+  HIP_TRY(tmp.get(&a.rows, (size_t)m));
+  HIP_TRY(tmp.get(&a.key, (size_t)m));
+  HIP_TRY(tmp.get(&a.pos, (size_t)m));
+  HIP_TRY(tmp.get(&a.skey, (size_t)m));
+  HIP_TRY(tmp.get(&a.row_s, (size_t)m));
+  HIP_TRY(tmp.get(&a.flag, (size_t)m));
+  HIP_TRY(tmp.get(&a.vidx, (size_t)m));
+  HIP_TRY(hipMalloc(&p->sperm, sizeof(int32_t) * (size_t)m));
+  HIP_TRY(hipMalloc(&p->scol, sizeof(int32_t) * (size_t)m));
+  a.perm = p->sperm;
+  a.col_s = p->scol;
+  HIP_TRY(launch_stripe_split(a, st));
+  // number of pairs V = vidx[m - 1] + flag[m - 1]
+  int32_t last[2] = {0, 0};
+  HIP_TRY(hipMemcpyAsync(&last[0], a.vidx + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&last[1], a.flag + (m - 1), sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const int64_t nv = (int64_t)last[0] + last[1];
+  if (nv < 1 || nv > m) return fail(MERBIT_EHIP, "column stripes: bad pair count");
+  p->plan_rows = nv;
+  HIP_TRY(tmp.get(&a.vrow_ptr, (size_t)nv + 1));
+  HIP_TRY(tmp.get(&a.vrow_row, (size_t)nv));
+  HIP_TRY(tmp.get(&a.vrow_stripe, (size_t)nv));
+  HIP_TRY(tmp.get(&a.wcnt, (size_t)nw));
+  HIP_TRY(tmp.get(&a.rank, (size_t)nw));
+  HIP_TRY(hipMalloc(&p->swords, sizeof(StripeWord) * (size_t)nw));
+  a.sw = p->swords;
+  HIP_TRY(launch_stripe_rows(a, nv, st));
+  // values in stacked order, the plan of A', and its two result buffers
+  HIP_TRY(hipMalloc(&p->svals, vsize(p->dtype) * (size_t)m));
+  int rc = stripes_copy_values(p, p->values, st);
+  if (rc != MERBIT_OK) return rc;
+  rc = build_tile(p, a.vrow_ptr, st);
+  if (rc != MERBIT_OK) return rc;
+  const size_t yb = vsize(p->dtype) * (size_t)nv;
+  HIP_TRY(hipMalloc(&p->yv[0], yb));
+  HIP_TRY(hipMalloc(&p->yv[1], yb));
+  // zero everywhere: in particular at every tile's first row (dual buffers)
+  HIP_TRY(hipMemsetAsync(p->yv[0], 0, yb, st));
+  HIP_TRY(hipMemsetAsync(p->yv[1], 0, yb, st));
+  p->yv_cur = 0;
+  // the temporaries are freed on return: finish the work that reads them
+  HIP_TRY(hipStreamSynchronize(st));
+  return MERBIT_OK;
+}
+
+// Tile ranges and their hot sets.  The grid is sized for one block per CU
+// with the largest cache (cap_req > 0: that many values), rounded to a
+// multiple of the XCD count, and the tiles are cut into that many contiguous
+// ranges; each range takes the (at most cap) most frequent columns of its own
+// nonzeros, ties by increasing column.  The ranges first get equal tile
+// counts; with a cache they are then re-cut so that every range carries the
+// same estimated cost, tiles plus the gathers its cache does not serve
+// (kColdWeight tiles per gather: a range whose columns are less concentrated
+// gets fewer tiles), and the hot sets are chosen again for the new ranges.
+// The cache is dropped when cap_req < 0 and the hot columns hold under 20 %
+// of the nonzeros.
+constexpr double kColdWeight = 1.0 / 384.0;
+
+int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
+  const size_t vs = vsize(p->dtype);
+  const int64_t cap_lds = hot_cap_lds(p);
+  int64_t cap = cap_req > 0 ? cap_req : (cap_req < 0 ? cap_lds : 0);
+  if (cap > cap_lds) return fail(MERBIT_EUNSUPPORTED, "hot_columns exceeds the LDS budget");
+  if (cap > p->n_cols) cap = p->n_cols;
+  if (cap > 0 && !spmv_wave_supported(p->dtype, p->sigma, p->waves, true, p->desc_bits == 64)) {
+    if (cap_req > 0) return fail(MERBIT_EUNSUPPORTED, "hot cache not built for this block size");
+    cap = 0;
+  }
+  p->hot_lds_bytes = (size_t)cap * vs;  // for the grid size
+  int rc = size_grid(p);
+  if (rc != MERBIT_OK) return rc;
+  const int R = p->ranges;
+  std::vector<int32_t> rt(R + 1), spans(R + 1), hoff(R + 1, 0);
+  std::vector<double> cov(R, 0.0);
+  for (int k = 0; k <= R; ++k) rt[k] = (int32_t)(p->tile_num * k / R);
+  auto read_spans = [&]() -> int {
+    for (int k = 0; k <= R; ++k)
+      HIP_TRY(hipMemcpyAsync(&spans[k], p->tile_x + rt[k], sizeof(int32_t),
+                             hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return MERBIT_OK;
+  };
+  rc = read_spans();
+  if (rc != MERBIT_OK) return rc;
+  int64_t taken_max = 0;
+  if (cap > 0) {
+    const int64_t nc = p->n_cols;
+    Scratch tmp;
+    int32_t *counts = nullptr, *hist = nullptr, *iota = nullptr, *csorted = nullptr,
+            *cols = nullptr, *slot_of = nullptr;
+    unsigned char* sort_tmp = nullptr;
+    size_t sort_bytes = 0;
+    HIP_TRY(stripe_rank_bytes(nc, &sort_bytes));
+    HIP_TRY(tmp.get(&sort_tmp, sort_bytes));
+    HIP_TRY(tmp.get(&counts, (size_t)nc));
+    HIP_TRY(tmp.get(&hist, (size_t)kHotHistBins));
+    HIP_TRY(tmp.get(&iota, (size_t)nc));
+    HIP_TRY(tmp.get(&csorted, (size_t)nc));
+    HIP_TRY(tmp.get(&cols, (size_t)nc));
+    HIP_TRY(tmp.get(&slot_of, (size_t)nc));
+    HIP_TRY(hipMalloc(&p->hot_cols, sizeof(int32_t) * (size_t)(cap * R)));
+    HIP_TRY(hipMalloc(&p->colx, sizeof(int32_t) * (size_t)p->nnz));
+    std::vector<int32_t> top((size_t)cap);
+    // hot sets of the current ranges: hoff, cov (hot nonzeros per range)
+    auto select = [&]() -> int {
+      taken_max = 0;
+      for (int k = 0; k < R; ++k) {
+        const int64_t lo = spans[k], len = (int64_t)spans[k + 1] - spans[k];
+        HIP_TRY(hot_count_columns(p->scol + lo, len, nc, 1, counts, hist, st));
+        HIP_TRY(launch_stripe_rank_columns(counts, nc, sort_tmp, sort_bytes, iota, csorted, cols,
+                                           st));
+        HIP_TRY(hipMemcpyAsync(top.data(), csorted, sizeof(int32_t) * (size_t)cap,
+                               hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        // counts are in decreasing order: keep the columns that occur
+        const int64_t taken =
+            std::lower_bound(top.begin(), top.end(), 0, std::greater<int32_t>()) - top.begin();
+        cov[k] = 0.0;
+        for (int64_t i = 0; i < taken; ++i) cov[k] += top[(size_t)i];
+        HIP_TRY(hipMemsetAsync(slot_of, 0xFF, sizeof(int32_t) * (size_t)nc, st));
+        HIP_TRY(launch_stripe_hot(cols, (int32_t)taken, slot_of, p->hot_cols + hoff[k], st));
+        HIP_TRY(hot_recode(p->scol + lo, len, slot_of, p->colx + lo, st));
+        hoff[k + 1] = hoff[k] + (int32_t)taken;
+        taken_max = std::max(taken_max, taken);
+      }
+      HIP_TRY(hipStreamSynchronize(st));
+      return MERBIT_OK;
+    };
+    rc = select();
+    if (rc != MERBIT_OK) return rc;
+    if (R > 1) {
+      // equal estimated cost per range: the cost is spread evenly over the
+      // tiles of each old range, and the new cuts invert its running sum
+      std::vector<double> acc(R + 1, 0.0);
+      for (int k = 0; k < R; ++k) {
+        const double cold = (double)(spans[k + 1] - spans[k]) - cov[k];
+        acc[k + 1] = acc[k] + (double)(rt[k + 1] - rt[k]) + kColdWeight * cold;
+      }
+      std::vector<int32_t> cut(R + 1);
+      cut[0] = 0;
+      cut[R] = (int32_t)p->tile_num;
+      int k = 0;
+      for (int q = 1; q < R; ++q) {
+        const double target = acc[R] * q / R;
+        while (k < R - 1 && acc[k + 1] < target) ++k;
+        const double span = acc[k + 1] - acc[k];
+        const double f = span > 0.0 ? (target - acc[k]) / span : 0.0;
+        int32_t c = rt[k] + (int32_t)(f * (double)(rt[k + 1] - rt[k]) + 0.5);
+        cut[q] = std::max(cut[q - 1], std::min(c, (int32_t)p->tile_num));
+      }
+      rt = cut;
+      rc = read_spans();
+      if (rc == MERBIT_OK) rc = select();
+      if (rc != MERBIT_OK) return rc;
+    }
+    double covered = 0.0;
+    for (int k = 0; k < R; ++k) covered += cov[k];
+    p->hot_coverage = p->nnz > 0 ? covered / (double)p->nnz : 0.0;
+    if (cap_req < 0 && p->hot_coverage < 0.2) {
+      (void)hipFree(p->hot_cols);
+      (void)hipFree(p->colx);
+      p->hot_cols = nullptr;
+      p->colx = nullptr;
+      std::fill(hoff.begin(), hoff.end(), 0);
+      taken_max = 0;
+    }
+  }
+  HIP_TRY(hipMalloc(&p->range_tile, sizeof(int32_t) * (size_t)(R + 1)));
+  HIP_TRY(hipMemcpyAsync(p->range_tile, rt.data(), sizeof(int32_t) * (size_t)(R + 1),
+                         hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMalloc(&p->hot_off, sizeof(int32_t) * (size_t)(R + 1)));
+  HIP_TRY(hipMemcpyAsync(p->hot_off, hoff.data(), sizeof(int32_t) * (size_t)(R + 1),
+                         hipMemcpyHostToDevice, st));
+  p->hot_n = hoff[R];
+  p->hot_lds_bytes = (size_t)taken_max * vs;
+  if (p->hot_n > 0) {
+    HIP_TRY(hipMalloc(&p->x_hot, vs * (size_t)p->hot_n));
+    HIP_TRY(spmv_wave_set_hot_lds(p->dtype, p->sigma, p->waves, p->hot_lds_bytes,
+                                  p->desc_bits == 64));
+  } else {
+    p->hot_coverage = 0.0;
+  }
+  // the grid for the LDS actually used (it stays a multiple of the ranges)
+  const int ranges = p->ranges;
+  rc = size_grid(p);
+  if (rc != MERBIT_OK) return rc;
+  if (p->ranges != ranges) return fail(MERBIT_EHIP, "column stripes: range count changed");
+  HIP_TRY(hipStreamSynchronize(st));  // host vectors above are read by queued copies
+  return MERBIT_OK;
+}
+
+}  // namespace merbit

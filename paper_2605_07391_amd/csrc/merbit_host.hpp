@@ -42,6 +42,24 @@ struct merbit_plan {
   void* x_hot = nullptr;       // [hot_n] gathered hot x values (partial mode)
   size_t hot_lds_bytes = 0;
   double hot_coverage = 0.0;   // fraction of nonzeros whose column is hot
+  // column stripes (stripes > 1): TILE is the plan of the stacked matrix A'
+  // (rows = non-empty (stripe, row) pairs, plan_rows of them), whose column
+  // stream and values the plan keeps in stacked order; the fused kernel writes
+  // A' x into yv[yv_cur] (dual buffers) and a second launch sums each row's
+  // pairs into y.  ranges > 1: the fused launch's tiles are split into
+  // contiguous ranges (range_tile), each with its own hot set (hot_off).
+  int stripes = 1;
+  int64_t plan_rows = 0;
+  int64_t words = 0;                 // 64-row words per stripe
+  int32_t* sperm = nullptr;          // [nnz] stacked position -> matrix position
+  int32_t* scol = nullptr;           // [nnz] stacked column stream
+  void* svals = nullptr;             // [nnz] stacked values
+  merbit::StripeWord* swords = nullptr;  // [words][stripes] combine table
+  void* yv[2] = {nullptr, nullptr};  // [plan_rows] A' x, dual buffers
+  int yv_cur = 0;
+  int ranges = 1;
+  int32_t* range_tile = nullptr;     // [ranges + 1]
+  int32_t* hot_off = nullptr;        // [ranges + 1]
   // PageRank state
   uint32_t* dmask = nullptr;
   void* ybuf[2] = {nullptr, nullptr};
@@ -79,6 +97,7 @@ struct merbit_plan {
   uint64_t generation = 0;
   struct LoopGraph {
     int kind, parity, ybuf, len, k;
+    int sp_in, sp_out;  // stacked-buffer parity (yv_cur) before / after the chunk
     const void* x;
     const void* aux;  // a second captured operand (adjoint: g)
     double alpha;
@@ -115,6 +134,19 @@ int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st,
               bool hot_ready = false);
 // A buffer or value array that captured graphs use has changed: drop them.
 void invalidate_graphs(merbit_plan* p);
+// Zero v at the first row of every commit unit (nothing for a striped plan,
+// whose fused kernel writes only its own buffers).
+int zero_boundary(merbit_plan* p, void* v, hipStream_t st);
+// Striped plans: the stacked matrix, its plan, and the per-range hot sets.
+int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st);
+int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st);
+// copy values into the stacked order
+int stripes_copy_values(merbit_plan* p, const void* values, hipStream_t st);
+// allocate TILE for plan_rows rows and build it from row_ptr
+int build_tile(merbit_plan* p, const int32_t* row_ptr, hipStream_t st);
+// largest number of hot values that fit next to the kernel's static LDS
+int64_t hot_cap_lds(const merbit_plan* p);
+int size_grid(merbit_plan* p);
 // Dangling mask and the PageRank iteration buffers (allocated on first use).
 int ensure_dmask(merbit_plan* p, hipStream_t st);
 int ensure_pagerank_state(merbit_plan* p, hipStream_t st);
@@ -134,10 +166,13 @@ int run_chunk(merbit_plan* p, int kind, int parity, int ybuf, int len, int k,
   if (p->eager_loops || p->profiling) return enqueue(st);
   for (auto& g : p->loop_graphs)
     if (g.kind == kind && g.parity == parity && g.ybuf == ybuf && g.len == len && g.k == k &&
-        g.x == x && g.aux == aux && g.alpha == alpha && g.gen == p->generation) {
+        g.x == x && g.aux == aux && g.alpha == alpha && g.gen == p->generation &&
+        g.sp_in == p->yv_cur) {
       HIP_TRY(hipGraphLaunch(g.exec, st));
+      p->yv_cur = g.sp_out;  // the replay used the buffers the capture did
       return MERBIT_OK;
     }
+  const int sp_in = p->yv_cur;
   if (!p->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
   HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeRelaxed));
   const int rc = enqueue(p->cap_stream);
@@ -157,7 +192,8 @@ int run_chunk(merbit_plan* p, int kind, int parity, int ybuf, int len, int k,
     (void)hipGraphExecDestroy(p->loop_graphs.front().exec);
     p->loop_graphs.erase(p->loop_graphs.begin());
   }
-  p->loop_graphs.push_back({kind, parity, ybuf, len, k, x, aux, alpha, p->generation, exec});
+  p->loop_graphs.push_back(
+      {kind, parity, ybuf, len, k, sp_in, p->yv_cur, x, aux, alpha, p->generation, exec});
   HIP_TRY(hipGraphLaunch(exec, st));
   return MERBIT_OK;
 }

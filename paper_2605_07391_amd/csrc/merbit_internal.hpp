@@ -13,6 +13,7 @@ constexpr uint32_t kFastBit = 0x80000000u; // tile_y: long-row (single-row) tile
 constexpr int kMaxSigma = 12;              // 2 ceil(log2(64 sigma)) + sigma <= 32
 constexpr int kMaxSigma64 = 40;            // 2 ceil(log2(64 sigma)) + sigma <= 64
 constexpr int kHotHistBins = 65536;        // column-count histogram of the hot cache
+constexpr int kXcds = 8;                   // MI355X: accelerator dies, one L2 each
 
 // ceil(log2(v)) for v >= 1: width of the x_offset / y_offset fields.
 __host__ __device__ constexpr int ceil_log2(int v) {
@@ -193,6 +194,13 @@ struct SpmvArgs {
   int32_t chunks_per_block;
   int32_t grid;
   int32_t hot_n;
+  // wave kernel: tiles split into `ranges` contiguous parts (1: one part);
+  // block b works on part b % ranges, whose tiles are
+  // [range_tile[k], range_tile[k + 1]) and whose hot x values are
+  // x_hot[hot_off[k] .. hot_off[k + 1]).  grid is a multiple of ranges.
+  int32_t ranges;
+  const int32_t* range_tile;
+  const int32_t* hot_off;
 };
 
 struct SpmmArgs {
@@ -306,6 +314,56 @@ struct BicgArgs {
 };
 int bicg_grid(int64_t n);
 hipError_t launch_bicg(int dtype, const BicgArgs& a, int stage, hipStream_t st);
+
+// Column stripes (a matrix stacked by column stripe, rows = the non-empty
+// (stripe, row) pairs) and the per-row sum of the stripes' results.
+// Entry [w][s] of the combine table: which of rows 64 w .. 64 w + 63 have
+// nonzeros in stripe s, and the stacked row of the first of them.
+struct alignas(16) StripeWord {
+  unsigned long long bits;
+  int32_t rank;
+  int32_t pad;
+};
+struct StripeSplitArgs {
+  const int32_t* row_ptr;  // [n_rows + 1] of the matrix
+  const int32_t* col;      // [m]
+  int64_t n_rows, m;
+  int shift;               // stripe of column c = c >> shift
+  int key_bits;            // bits of the stripe index (radix sort)
+  int64_t stripes, words;  // words = ceil(n_rows / 64) per stripe
+  void* temp;
+  size_t temp_bytes;
+  int32_t* rows;           // [m] row of each nonzero
+  uint32_t* key;           // [m] stripe of each nonzero
+  int32_t* pos;            // [m]
+  uint32_t* skey;          // [m] sorted stripes
+  int32_t* perm;           // [m] position in the matrix of the i-th stacked nonzero
+  int32_t* col_s;          // [m] stacked column stream
+  int32_t* row_s;          // [m] row of each stacked nonzero
+  int32_t* flag;           // [m] 1 where a (stripe, row) pair begins
+  int32_t* vidx;           // [m] exclusive scan of flag
+  int32_t* vrow_ptr;       // [V + 1] row pointer of the stacked matrix
+  int32_t* vrow_row;       // [V] row of each stacked row
+  uint32_t* vrow_stripe;   // [V] stripe of each stacked row
+  StripeWord* sw;          // [words][stripes] combine table
+  int32_t* wcnt;           // [stripes * words] popcounts, stripe-major
+  int32_t* rank;           // [stripes * words] their exclusive scan
+};
+hipError_t stripe_temp_bytes(int64_t m, int64_t n_words, int key_bits, size_t* bytes);
+// rows, the stable sort by stripe, the stacked column stream and pair flags
+hipError_t launch_stripe_split(const StripeSplitArgs& a, hipStream_t st);
+// with V = number of pairs known: vrow_* , the bitmap and the ranks
+hipError_t launch_stripe_rows(const StripeSplitArgs& a, int64_t nv, hipStream_t st);
+hipError_t stripe_rank_bytes(int64_t n, size_t* bytes);
+// columns by decreasing count (ties: increasing column)
+hipError_t launch_stripe_rank_columns(const int32_t* counts, int64_t n, void* temp,
+                                      size_t temp_bytes, int32_t* iota, int32_t* counts_sorted,
+                                      int32_t* cols_sorted, hipStream_t st);
+hipError_t launch_stripe_hot(const int32_t* sorted_cols, int32_t taken, int32_t* slot_of,
+                             int32_t* hot_cols, hipStream_t st);
+hipError_t launch_stripe_combine(int dtype, int stripes, const void* yv, int64_t nv,
+                                 const StripeWord* sw, int64_t words, int64_t n_rows, void* y,
+                                 hipStream_t st);
 
 // Batched forms.
 struct MultiTables {  // device row-chunk tables of a block-diagonal matrix

@@ -14,7 +14,9 @@
 //     the launch (dual buffer: each tile zeroes z at its first row, Sec. 4.2
 //     opt. (3)).
 // A block of WAVES wavefronts is resident for the whole launch; wavefront g
-// of the grid takes tiles g, g + W_total, g + 2 W_total, ...  The loads of the
+// of the grid takes tiles g, g + W_total, g + 2 W_total, ...  (with the tiles
+// split into ranges, the same within the block's range, over the blocks of
+// that range).  The loads of the
 // next tile (bounds, descriptor, col_ind, values) are issued before the
 // current tile's gathers are consumed, so memory stays busy while a tile is
 // walked and committed.
@@ -97,20 +99,36 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
   const int wid = __builtin_amdgcn_readfirstlane(tid / kOmega);
   V* s_w = s_stage + wid * WLDS;
 
+  // this block's part of the tiles and of the hot values (one part unless
+  // the plan splits the tiles into ranges)
+  int t_begin = 0, t_end = a.tile_num, slot = blockIdx.x, slots = a.grid;
+  int h_begin = 0, h_num = a.hot_n;
+  if (a.ranges > 1) {
+    const int k = blockIdx.x % a.ranges;
+    t_begin = a.range_tile[k];
+    t_end = a.range_tile[k + 1];
+    slot = blockIdx.x / a.ranges;
+    slots = a.grid / a.ranges;
+    if (HOT) {
+      h_begin = a.hot_off[k];
+      h_num = a.hot_off[k + 1] - h_begin;
+    }
+  }
+
   extern __shared__ __align__(16) unsigned char s_dyn[];
   const V* s_hot = reinterpret_cast<const V*>(s_dyn);
   if (HOT) {
     V* dst = reinterpret_cast<V*>(s_dyn);
-    const V* __restrict__ xh = static_cast<const V*>(a.x_hot);
-    for (int s = tid; s < a.hot_n; s += WAVES * kOmega) dst[s] = xh[s];
+    const V* __restrict__ xh = static_cast<const V*>(a.x_hot) + h_begin;
+    for (int s = tid; s < h_num; s += WAVES * kOmega) dst[s] = xh[s];
     __syncthreads();
   }
 
-  const int stride = a.grid * WAVES;
-  int t = blockIdx.x * WAVES + wid;
+  const int stride = slots * WAVES;
+  int t = t_begin + slot * WAVES + wid;
   WaveTile<V, SIGMA, D> cur;
-  if (t < a.tile_num) wave_load_tile<V, SIGMA, D>(a, col, val, t, lid, cur);
-  while (t < a.tile_num) {
+  if (t < t_end) wave_load_tile<V, SIGMA, D>(a, col, val, t, lid, cur);
+  while (t < t_end) {
     // gathers of the current tile (none for a tile without nonzeros: x may be
     // empty then)
     V g[SIGMA];
@@ -129,7 +147,7 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
     // loads of the next tile go out before the gathers are consumed
     const int tn = t + stride;
     WaveTile<V, SIGMA, D> nxt;
-    if (tn < a.tile_num) wave_load_tile<V, SIGMA, D>(a, col, val, tn, lid, nxt);
+    if (tn < t_end) wave_load_tile<V, SIGMA, D>(a, col, val, tn, lid, nxt);
 
     const int x_se = cur.x_se;
     const int y_ws = (int)(cur.tyw & kRowMask);
@@ -197,7 +215,7 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
       for (int r = lid; r < y_we - y_ws - 1; r += kOmega) y[y_ws + 1 + r] = s_w[x_se + r];
     }
     if (z != nullptr && lid == 0) z[y_ws] = V(0);
-    if (tn >= a.tile_num) break;
+    if (tn >= t_end) break;
     cur = nxt;
     t = tn;
   }

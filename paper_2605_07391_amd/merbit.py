@@ -43,14 +43,16 @@ class PlanInfo(ctypes.Structure):
                 ("offset_bits", ctypes.c_int32), ("dtype", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("commit", ctypes.c_int32),
                 ("hot_coverage", ctypes.c_double), ("desc_bits", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("stripes", ctypes.c_int32), ("ranges", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("plan_rows", ctypes.c_int64)]
 
 
 class Opts(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_int32), ("block_lanes", ctypes.c_int32),
                 ("commit", ctypes.c_int32), ("hot_columns", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("eager_loops", ctypes.c_int32), ("desc_bits", ctypes.c_int32)]
+                ("eager_loops", ctypes.c_int32), ("desc_bits", ctypes.c_int32),
+                ("stripes", ctypes.c_int32)]
 
 
 COMMIT_AUTO, COMMIT_BLOCK, COMMIT_WAVE = 0, 1, 2
@@ -149,12 +151,15 @@ def _vdtype(values: torch.Tensor):
 
 class Plan:
     """A reusable MERBIT plan: TILE built once on the GPU from row_ptr, then
-    repeated y = A x.  col_ind and values are borrowed (kept referenced)."""
+    repeated y = A x.  col_ind and values are borrowed (kept referenced).
+    stripes = S > 1 plans the column-stripe stack of the matrix (the plan then
+    copies col_ind and values; set_values re-copies the values)."""
 
     def __init__(self, row_ptr: torch.Tensor, col_ind: torch.Tensor, values: torch.Tensor,
                  n_cols: int, *, sigma: int = 0, block_lanes: int = 0, hot_columns: int = -1,
                  commit: str = "auto", blocks_per_cu: int = 0, validate: bool = True,
-                 eager_loops: bool = False, desc_bits: int = 32, stream=None):
+                 eager_loops: bool = False, desc_bits: int = 32, stripes: int = 0,
+                 stream=None):
         lib = load()
         self.dtype = values.dtype
         self._code = _vdtype(values)
@@ -177,6 +182,7 @@ class Plan:
         opts.blocks_per_cu = blocks_per_cu
         opts.eager_loops = 1 if eager_loops else 0
         opts.desc_bits = desc_bits
+        opts.stripes = stripes
         h = ctypes.c_void_p()
         _check(lib.merbit_plan_create(self.n_rows, self.n_cols, self.nnz, rp, ci, va, self._code,
                                       ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
@@ -472,7 +478,7 @@ def column_scale(col: torch.Tensor, a: torch.Tensor, s: torch.Tensor,
 
 def tune(row_ptr: torch.Tensor, col_ind: torch.Tensor, values: torch.Tensor, n_cols: int, *,
          sigmas=None, block_lanes=None, reps: int = 20, commit: str = "auto",
-         hot_columns: int = -1, desc_bits: int = 32, stream=None):
+         hot_columns: int = -1, desc_bits: int = 32, stripes: int = 0, stream=None):
     """Time the fused SpMV for every (sigma, block_lanes) candidate on this
     matrix.  Returns ({"sigma": s, "block_lanes": b}, {(s, b): mean us})."""
     import numpy as np
@@ -493,6 +499,7 @@ def tune(row_ptr: torch.Tensor, col_ind: torch.Tensor, values: torch.Tensor, n_c
     opts.commit = _COMMIT[commit]
     opts.hot_columns = hot_columns
     opts.desc_bits = desc_bits
+    opts.stripes = stripes
     _check(lib.merbit_tune(n_rows, int(n_cols), col_ind.numel(),
                            _dev(row_ptr, torch.int32, "row_ptr"),
                            _dev(col_ind, torch.int32, "col_ind"),

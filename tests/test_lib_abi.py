@@ -47,7 +47,7 @@ def test_argument_errors_without_gpu():
     d = mb.Opts()
     lib.merbit_opts_init(ctypes.byref(d))
     assert (d.sigma, d.block_lanes, d.commit, d.hot_columns, d.validate,
-            d.eager_loops, d.desc_bits) == (0, 0, 0, -1, 1, 0, 0)
+            d.eager_loops, d.desc_bits, d.stripes) == (0, 0, 0, -1, 1, 0, 0, 0)
     # NULL out pointer
     assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, None, None, None) == mb.EINVAL
     # unsupported dtype
@@ -84,6 +84,15 @@ def test_argument_errors_without_gpu():
     assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0,
                                   opts(desc_bits=64, sigma=24, block_lanes=1024), None,
                                   ctypes.byref(out)) == mb.EUNSUPPORTED
+    # column stripes: a power of two up to 32, wave commit only, nnz < 2^30
+    for bad in (3, 6, 64, -1):
+        assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, opts(stripes=bad), None,
+                                      ctypes.byref(out)) == mb.EINVAL
+    assert b"stripes" in lib.merbit_last_error()
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, opts(stripes=8, commit=1),
+                                  None, ctypes.byref(out)) == mb.EUNSUPPORTED
+    assert lib.merbit_plan_create(1, 1 << 20, 1 << 30, vp(8), vp(8), vp(8), 0,
+                                  opts(stripes=8), None, ctypes.byref(out)) == mb.EUNSUPPORTED
     assert not out.value
     # calls on a NULL plan
     assert lib.merbit_spmv(None, None, None, None) == mb.EINVAL
