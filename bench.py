@@ -223,7 +223,9 @@ def run_ppr(w, k: int, steps: int, warmup: int, alpha: float):
     v = torch.from_numpy(w["values"]).float().to(dev)
     plan = pkg.Plan(r, c, v, n, validate=False)
     src = graphgen.ppr_sources(n, k, seed=4)
-    X, _, _, _ = plan.pagerank_personalized(src, alpha=alpha, max_iter=max(warmup, 1))
+    # untimed: warm-up iterations in the timed run's chunk shape, so its HIP
+    # graph is recorded before the clock starts
+    X, _, _, _ = plan.pagerank_personalized(src, alpha=alpha, max_iter=max(warmup, steps))
     torch.cuda.synchronize()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     X0 = torch.zeros_like(X)
@@ -249,7 +251,7 @@ def run_ppr(w, k: int, steps: int, warmup: int, alpha: float):
             "max_mass_error": mass_err, "sources_seed": 4}
 
 
-def run_multi(steps: int, warmup: int, alpha: float):
+def run_multi(steps: int, warmup: int, alpha: float, stripes: int = 0):
     """PageRank of the 256 Chung-Lu graphs stored on one diagonal, FP32, one
     plan: a step is one fused SpMV over all graphs plus the per-graph update."""
     import numpy as np
@@ -263,11 +265,11 @@ def run_multi(steps: int, warmup: int, alpha: float):
     r = torch.from_numpy(w["row_ptr"]).to(dev)
     c = torch.from_numpy(w["col"]).to(dev)
     v = torch.from_numpy(w["values"]).float().to(dev)
-    plan = pkg.Plan(r, c, v, n, validate=False)
+    plan = pkg.Plan(r, c, v, n, validate=False, stripes=stripes)
     sizes = np.diff(gp)
     x0 = torch.from_numpy(np.repeat(1.0 / sizes, sizes)).float().to(dev)
     x = x0.clone()
-    plan.pagerank_multi(gp, x, alpha=alpha, max_iter=max(warmup, 1))
+    plan.pagerank_multi(gp, x, alpha=alpha, max_iter=max(warmup, steps))  # records the graphs
     x.copy_(x0)
     torch.cuda.synchronize()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -287,13 +289,13 @@ def run_multi(steps: int, warmup: int, alpha: float):
             "ms_per_step": round(step_ms, 4), "spmv_us": round(spmv_ms * 1e3, 1),
             "gnzs": round(nnz / (step_ms * 1e-3) / 1e9, 3),
             "spmv_gnzs": round(nnz / (spmv_ms * 1e-3) / 1e9, 3),
-            "seed": w["meta"]["seed"]}
+            "stripes": stripes, "seed": w["meta"]["seed"]}
 
 
-def run_bicgstab(scale: int, steps: int):
+def run_bicgstab(scale: int, steps: int, stripes: int = 0):
     """BiCGSTAB (Sec. 5.5.2) on the symmetric 0/1 R-MAT system of the given
     scale, FP64, b = A x_true: `steps` iterations (two fused SpMVs and five
-    vector kernels each) after 5 warm-up iterations.  Returns per-iteration
+    vector kernels each) after 20 warm-up iterations.  Returns per-iteration
     time, the SpMV share and the residual reached."""
     import torch
 
@@ -305,10 +307,11 @@ def run_bicgstab(scale: int, steps: int):
     r = torch.from_numpy(w["row_ptr"]).to(dev)
     c = torch.from_numpy(w["col"]).to(dev)
     v = torch.from_numpy(w["values"]).to(dev)
-    plan = pkg.Plan(r, c, v, n, validate=False)
+    plan = pkg.Plan(r, c, v, n, validate=False, stripes=stripes)
     b = plan.spmv(torch.from_numpy(w["x"]).to(dev))
     x = torch.zeros(n, dtype=torch.float64, device=dev)
-    plan.bicgstab(b, x, tol=0.0, max_iter=5)
+    # two chunks of the timed run's shape: both of its HIP graphs are recorded
+    plan.bicgstab(b, x, tol=0.0, max_iter=20, check_every=10)
     x.zero_()
     torch.cuda.synchronize()
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -329,7 +332,7 @@ def run_bicgstab(scale: int, steps: int):
             "spmv_us": round(spmv_ms * 1e3, 1),
             "spmv_share": round(2 * spmv_ms / it_ms, 3),
             "gnzs": round(2 * nnz / (it_ms * 1e-3) / 1e9, 3),
-            "rel_residual": res, "seed": scale}
+            "rel_residual": res, "stripes": stripes, "seed": scale}
 
 
 def measured_copy_gbs(mib: int = 1024, reps: int = 5) -> float:
@@ -437,7 +440,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=20,
+                    help="untimed PageRank iterations first (20 = two chunks between "
+                         "convergence checks, so both HIP graphs of the loop are recorded)")
     ap.add_argument("--workload", default="rmat22")
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
     ap.add_argument("--sigma", type=int, default=0,
@@ -523,7 +528,10 @@ def main():
         ppr["vs_plain_spmv"] = round(ppr["gnz_rhs_per_s"] / main_run["spmv_gnzs"], 3)
         print(f"[bench] ppr64: step {ppr['ms_per_step']:.3f} ms, spmm {ppr['spmm_us']:.1f} us",
               file=sys.stderr, flush=True)
-        multi = run_multi(args.batched_steps, 2, args.alpha)
+        multi = run_multi(args.batched_steps, 2, args.alpha, stripes=8)
+        multi_plain = run_multi(args.batched_steps, 2, args.alpha)
+        multi["one_plan_without_stripes"] = {k: multi_plain[k] for k in
+                                             ("ms_per_step", "spmv_us", "gnzs", "spmv_gnzs")}
         multi["vs_plain"] = round(multi["gnzs"] / main_run["value_gnzs"], 3)
         print(f"[bench] multi256: step {multi['ms_per_step']:.3f} ms", file=sys.stderr,
               flush=True)
@@ -535,7 +543,10 @@ def main():
               f"{adj['backward_ms']:.2f} ms", file=sys.stderr, flush=True)
     bicg = None
     if not args.no_bicgstab and w["meta"]["generator"] == "rmat":
-        bicg = run_bicgstab(args.bicgstab_scale, args.batched_steps * 10)
+        bicg = run_bicgstab(args.bicgstab_scale, args.batched_steps * 10, stripes=8)
+        bicg_plain = run_bicgstab(args.bicgstab_scale, args.batched_steps * 10)
+        bicg["one_plan_without_stripes"] = {k: bicg_plain[k] for k in
+                                            ("ms_per_iteration", "spmv_us", "spmv_share", "gnzs")}
         print(f"[bench] bicgstab: {bicg['ms_per_iteration']:.3f} ms / iteration", file=sys.stderr,
               flush=True)
     cpu = None

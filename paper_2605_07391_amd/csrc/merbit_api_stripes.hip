@@ -103,14 +103,17 @@ int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st) {
 // with the largest cache (cap_req > 0: that many values), rounded to a
 // multiple of the XCD count, and the tiles are cut into that many contiguous
 // ranges; each range takes the (at most cap) most frequent columns of its own
-// nonzeros, ties by increasing column.  The ranges first get equal tile
+// nonzeros (counted on every 4th nonzero of a long range), ties by
+// increasing column.  The ranges first get equal tile
 // counts; with a cache they are then re-cut so that every range carries the
 // same estimated cost, tiles plus the gathers its cache does not serve
 // (kColdWeight tiles per gather: a range whose columns are less concentrated
 // gets fewer tiles), and the hot sets are chosen again for the new ranges.
-// The cache is dropped when cap_req < 0 and the hot columns hold under 20 %
-// of the nonzeros.
-constexpr double kColdWeight = 1.0 / 384.0;
+// The weight was measured on R-MAT 22 (1/96 .. 1/768 swept): 1/384 in FP32;
+// FP64 tiles stream 12 instead of 8 bytes per nonzero, so a gather weighs
+// less against a tile there, 1/768.  The cache is dropped when cap_req < 0
+// and the hot columns hold under 20 % of the nonzeros.
+constexpr double kColdWeightF32 = 1.0 / 384.0, kColdWeightF64 = 1.0 / 768.0;
 
 int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
   const size_t vs = vsize(p->dtype);
@@ -162,7 +165,10 @@ int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
       taken_max = 0;
       for (int k = 0; k < R; ++k) {
         const int64_t lo = spans[k], len = (int64_t)spans[k + 1] - spans[k];
-        HIP_TRY(hot_count_columns(p->scol + lo, len, nc, 1, counts, hist, st));
+        // a 1-in-4 sample of a long range: the hot columns' counts are in the
+        // hundreds, and the hottest columns' global atomics serialise
+        HIP_TRY(hot_count_columns(p->scol + lo, len, nc, len > 64 * cap ? 4 : 1, counts, hist,
+                                  st));
         HIP_TRY(launch_stripe_rank_columns(counts, nc, sort_tmp, sort_bytes, iota, csorted, cols,
                                            st));
         HIP_TRY(hipMemcpyAsync(top.data(), csorted, sizeof(int32_t) * (size_t)cap,
@@ -173,6 +179,7 @@ int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
             std::lower_bound(top.begin(), top.end(), 0, std::greater<int32_t>()) - top.begin();
         cov[k] = 0.0;
         for (int64_t i = 0; i < taken; ++i) cov[k] += top[(size_t)i];
+        if (len > 64 * cap) cov[k] = std::min(4.0 * cov[k], (double)len);  // sampled counts
         HIP_TRY(hipMemsetAsync(slot_of, 0xFF, sizeof(int32_t) * (size_t)nc, st));
         HIP_TRY(launch_stripe_hot(cols, (int32_t)taken, slot_of, p->hot_cols + hoff[k], st));
         HIP_TRY(hot_recode(p->scol + lo, len, slot_of, p->colx + lo, st));
@@ -188,6 +195,7 @@ int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
       // equal estimated cost per range: the cost is spread evenly over the
       // tiles of each old range, and the new cuts invert its running sum
       std::vector<double> acc(R + 1, 0.0);
+      const double kColdWeight = p->dtype == MERBIT_F64 ? kColdWeightF64 : kColdWeightF32;
       for (int k = 0; k < R; ++k) {
         const double cold = (double)(spans[k + 1] - spans[k]) - cov[k];
         acc[k + 1] = acc[k] + (double)(rt[k + 1] - rt[k]) + kColdWeight * cold;

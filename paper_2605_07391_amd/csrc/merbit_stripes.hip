@@ -122,11 +122,12 @@ __global__ void iota32_kernel(int32_t* __restrict__ v, int64_t n) {
 }
 
 // One wavefront per 64-row word: lane b sums row 64 w + b over the stripes.
-// The word index is uniform across the wavefront, so the bitmap words and
-// ranks are scalar loads.  Every lane loads every stripe's entry (a lane
-// whose row is absent from a stripe reads a valid entry nearby and drops it),
-// so the S loads go out together instead of one branch at a time; the
-// stripes are added in stripe order (a fixed order).
+// The S table entries of the word are read by every lane (the same address
+// across the wavefront: one request each), all before any is used, and every
+// lane loads every stripe's value (a lane whose row is absent from a stripe
+// reads a valid entry nearby and drops it), so the S loads go out together
+// instead of one branch at a time; the stripes are added in stripe order (a
+// fixed order).
 template <typename V, int S>
 __global__ __launch_bounds__(256) void stripe_combine_kernel(const V* __restrict__ yv,
                                                              int64_t nv,
@@ -138,13 +139,18 @@ __global__ __launch_bounds__(256) void stripe_combine_kernel(const V* __restrict
                     __builtin_amdgcn_readfirstlane(threadIdx.x / kOmega);
   if (w >= words) return;
   const unsigned long long below = (1ull << lid) - 1ull;
-  const StripeWord* __restrict__ e = sw + w * S;
+  // the entries as 16-byte vector loads (bits low / high, rank, pad)
+  typedef int32_t i4v __attribute__((ext_vector_type(4)));
+  const i4v* __restrict__ e = reinterpret_cast<const i4v*>(sw + w * S) + (lid & 0);
+  i4v ent[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) ent[s] = e[s];
   unsigned long long word[S];
   int32_t base[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
-    word[s] = e[s].bits;
-    base[s] = e[s].rank;
+    word[s] = ((unsigned long long)(uint32_t)ent[s].y << 32) | (uint32_t)ent[s].x;
+    base[s] = ent[s].z;
   }
   V part[S];
 #pragma unroll
