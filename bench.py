@@ -1,14 +1,14 @@
 """Benchmark: repeated merge-path SpMV inside PageRank power iterations on one
 MI355X, R-MAT scale 22 (4,194,304 rows, ~65.2M nonzeros after merging).
 
-A step is one PageRank iteration: the fused SpMV kernel (y = P x) plus the
-update kernel (x' = alpha y + teleport, dangling mass and l1 change); with a
-column-stripe plan the SpMV is the fused kernel on the stacked matrix plus the
-kernel that adds each row's stripes.  The plan is built once and timed
-separately.  `value` is nonzeros processed per second over the timed steps
-(GNZ/s).  The roofline block reports the SpMV: algorithmic bytes per SpMV /
-mean SpMV time from HIP events around its launches, against the MI355X HBM
-peak.  The CPU baseline is the oracle (single thread)
+A step is one PageRank iteration: the SpMV (y = P x) plus the update kernel
+(x' = alpha y + teleport, dangling mass and l1 change); with a column-stripe
+plan the SpMV is the fused kernel on the stacked matrix plus the kernel that
+adds each row's stripes.  The plan is built once and timed separately.
+`value` is nonzeros processed per second over the timed steps (GNZ/s).  The
+roofline block reports the SpMV: algorithmic bytes per SpMV / mean SpMV time
+from HIP events around its launches (a separate pass of standalone SpMVs),
+against the MI355X HBM peak.  The CPU baseline is the oracle (single thread)
 timed on a bounded number of iterations of the same workload.
 
 Prints one JSON line.
@@ -165,10 +165,15 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
         mass = float(x.double().sum().item())
-        # roofline pass: same steps, fused SpMV launches bracketed by HIP events
-        x.fill_(1.0 / n)
+        # roofline pass: `steps` standalone SpMVs y = A x on the ranks just
+        # computed (the same launches as in a PageRank step), each bracketed
+        # by HIP events
+        ys = [torch.empty(n, dtype=dtype, device=dev) for _ in range(2)]
+        plan.zero_boundary(ys[0])
+        plan.spmv_dual(x, ys[0], ys[1])
         plan.profile_enable(True)
-        plan.pagerank(x, alpha, tol=0.0, max_iter=steps)
+        for k in range(steps):
+            plan.spmv_dual(x, ys[(k + 1) % 2], ys[k % 2])
     else:
         # a step is one y = A x with the workload's x (dual output buffers)
         x = torch.from_numpy(w["x"]).to(dtype).to(dev)
