@@ -98,3 +98,20 @@ def case_matrix(cases, name, seed=0):
     # columns need not be sorted within a row
     vals = rng.uniform(-1, 1, m)
     return rp, col, vals, nc
+
+
+def stacked_row_ptr(row_ptr, col, n_cols, stripes):
+    """Row pointer of the stacked matrix, written from its definition: the
+    stripe of column c is c >> max(0, ceil(log2 n_cols) - log2 S); the
+    nonzeros are ordered by (stripe, row, position in the row) and every
+    distinct (stripe, row) pair is a row."""
+    n = len(row_ptr) - 1
+    m = int(row_ptr[-1])
+    cbits = int(np.ceil(np.log2(n_cols))) if n_cols > 1 else 0
+    shift = max(0, cbits - int(np.log2(stripes)))
+    stripe = np.asarray(col, np.int64) >> shift
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
+    order = np.lexsort((np.arange(m), rows, stripe))
+    key = stripe[order] * (n + 1) + rows[order]
+    starts = np.flatnonzero(np.r_[True, key[1:] != key[:-1]]) if m else np.zeros(0, np.int64)
+    return np.r_[starts, m].astype(np.int32), order

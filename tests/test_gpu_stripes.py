@@ -11,29 +11,12 @@ import torch
 import graphgen
 import oracle
 from helpers import (workload, OMEGA, PR_TOL, case_matrix, check_spmv, host_values,
-                     require_gpu, seeded_x, spmv_cases, to_device)
+                     require_gpu, seeded_x, spmv_cases, stacked_row_ptr, to_device)
 
 pytestmark = pytest.mark.gpu
 DTYPES = [torch.float32, torch.float64]
 CASES = spmv_cases()
 ALPHA = 0.85
-
-
-def stacked_row_ptr(row_ptr, col, n_cols, stripes):
-    """Row pointer of the stacked matrix, written from its definition: the
-    stripe of column c is c >> max(0, ceil(log2 n_cols) - log2 S); the
-    nonzeros are ordered by (stripe, row, position in the row) and every
-    distinct (stripe, row) pair is a row."""
-    n = len(row_ptr) - 1
-    m = int(row_ptr[-1])
-    cbits = int(np.ceil(np.log2(n_cols))) if n_cols > 1 else 0
-    shift = max(0, cbits - int(np.log2(stripes)))
-    stripe = np.asarray(col, np.int64) >> shift
-    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(row_ptr))
-    order = np.lexsort((np.arange(m), rows, stripe))
-    key = stripe[order] * (n + 1) + rows[order]
-    starts = np.flatnonzero(np.r_[True, key[1:] != key[:-1]]) if m else np.zeros(0, np.int64)
-    return np.r_[starts, m].astype(np.int32), order
 
 
 def _plan(rp, col, vals, nc, dtype, dev, **kw):
