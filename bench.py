@@ -359,7 +359,7 @@ def measured_copy_gbs(mib: int = 1024, reps: int = 5) -> float:
     return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
-def run_adjoint(scale: int, iters: int, alpha: float):
+def run_adjoint(scale: int, iters: int, alpha: float, stripes: int = 0):
     """Differentiable PageRank on R-MAT (scale 20 by default), FP32: weights in
     (0.5, 1.5] column-normalised, loss ||pr(w) - t||^2.  Times the forward
     power method and the backward pass (adjoint fixed point on the transposed
@@ -375,7 +375,8 @@ def run_adjoint(scale: int, iters: int, alpha: float):
     n, m = w["n_rows"], w["nnz"]
     r = torch.from_numpy(w["row_ptr"]).to(dev)
     c = torch.from_numpy(w["col"]).to(dev)
-    op = ag.DiffPageRank(r, c, n, dtype=torch.float32, alpha=alpha, tol=0.0, max_iter=iters)
+    op = ag.DiffPageRank(r, c, n, dtype=torch.float32, alpha=alpha, tol=0.0, max_iter=iters,
+                         stripes=stripes)
     w0 = torch.from_numpy(graphgen.uniform(5, 83, m, 0.5, 1.5, closed_high=True)).float().to(dev)
     t0 = graphgen.uniform(6, 84, n, 0.0, 1.0)
     tgt = torch.from_numpy(t0 / t0.sum()).float().to(dev)
@@ -396,12 +397,12 @@ def run_adjoint(scale: int, iters: int, alpha: float):
     step()
     fwd, bwd, grad = step()
     # kernel time of the forward and the transposed SpMV over one more step
-    op.plan.profile_enable(True)
+    op.plan_fwd.profile_enable(True)
     op.plan_t.profile_enable(True)
     step()
-    nf, tf = op.plan.profile_read()
+    nf, tf = op.plan_fwd.profile_read()
     nt, tt = op.plan_t.profile_read()
-    op.plan.profile_enable(False)
+    op.plan_fwd.profile_enable(False)
     op.plan_t.profile_enable(False)
     op.close()
     spmv_f = tf / max(nf, 1)
@@ -413,7 +414,7 @@ def run_adjoint(scale: int, iters: int, alpha: float):
             "transposed_spmv_us": round(spmv_t * 1e3, 1),
             "transposed_vs_forward_spmv": round(spmv_t / spmv_f, 3),
             "grad_finite": bool(torch.isfinite(grad).all().item()),
-            "seeds": {"graph": scale, "w": 5, "target": 6}}
+            "stripes": stripes, "seeds": {"graph": scale, "w": 5, "target": 6}}
 
 
 def cpu_baseline(w, iters: int, alpha: float, dtype_name: str = "f32"):
@@ -543,7 +544,11 @@ def main():
         batched = {"ppr64_" + args.workload + "_f32": ppr, "chung_lu_multi256_f32": multi}
     adj = None
     if not args.no_adjoint and w["meta"]["generator"] == "rmat":
-        adj = run_adjoint(args.adjoint_scale, 50, args.alpha)
+        adj = run_adjoint(args.adjoint_scale, 50, args.alpha, stripes=8)
+        adj_plain = run_adjoint(args.adjoint_scale, 50, args.alpha)
+        adj["one_plan_without_stripes"] = {k: adj_plain[k] for k in
+                                           ("forward_ms", "backward_ms", "forward_spmv_us",
+                                            "transposed_spmv_us")}
         print(f"[bench] adjoint: forward {adj['forward_ms']:.2f} ms, backward "
               f"{adj['backward_ms']:.2f} ms", file=sys.stderr, flush=True)
     bicg = None

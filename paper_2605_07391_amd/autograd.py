@@ -26,12 +26,16 @@ class DiffPageRank:
 
     alpha, tol, max_iter, check_every apply to the forward power method;
     adj_tol / adj_max_iter to the adjoint fixed point (defaults: the same).
+    stripes = S > 1 runs the forward power method and the adjoint fixed point
+    on column-stripe plans (a second plan of P, and P^T's plan); the plain
+    plan of P keeps the transpose and the per-nonzero products.
     """
 
     def __init__(self, row_ptr: torch.Tensor, col_ind: torch.Tensor, n: int, *,
                  dtype=torch.float32, alpha: float = 0.85, tol: float = 0.0,
                  max_iter: int = 100, check_every: int = 10, adj_tol: float | None = None,
-                 adj_max_iter: int | None = None, sigma: int = 0, stream=None):
+                 adj_max_iter: int | None = None, sigma: int = 0, stripes: int = 0,
+                 stream=None):
         dev = col_ind.device
         self.n = int(n)
         self.nnz = col_ind.numel()
@@ -42,19 +46,32 @@ class DiffPageRank:
         self.stream = stream
         self.col = col_ind
         self.values = torch.zeros(self.nnz, dtype=dtype, device=dev)  # P, persistent
+        self.stripes = stripes if stripes > 1 else 0
         self.plan = Plan(row_ptr, col_ind, self.values, n, sigma=sigma, stream=stream)
+        # the forward power method's plan: a column-stripe plan keeps its own
+        # copy of the values (refreshed after every write to self.values)
+        self.plan_fwd = (Plan(row_ptr, col_ind, self.values, n, sigma=sigma,
+                              stripes=self.stripes, stream=stream)
+                         if self.stripes else self.plan)
         self.row_t, self.col_t, self.perm = self.plan.transpose(stream=stream)
         self.values_t = torch.zeros(self.nnz, dtype=dtype, device=dev)  # P^T, persistent
-        self.plan_t = Plan(self.row_t, self.col_t, self.values_t, n, sigma=sigma, stream=stream)
+        self.plan_t = Plan(self.row_t, self.col_t, self.values_t, n, sigma=sigma,
+                           stripes=self.stripes, stream=stream)
         self.ones = torch.ones(n, dtype=dtype, device=dev)
         self.x0 = torch.full((n,), 1.0 / n, dtype=dtype, device=dev)
         self.last_forward = None   # (iterations, l1 change) of the last forward solve
         self.last_adjoint = None
 
+    def refresh_transpose_values(self):
+        """After a write to values_t: a column-stripe plan of P^T re-copies them."""
+        if self.stripes:
+            self.plan_t.set_values(self.values_t)
+
     # column sums over the pattern's columns of per-nonzero values a[e] (times
     # b[e]): the transpose's SpMV with a vector of ones
     def _column_sums(self, a: torch.Tensor, b: torch.Tensor | None = None) -> torch.Tensor:
         gather_values(self.perm, a, b, out=self.values_t, stream=self.stream)
+        self.refresh_transpose_values()
         return self.plan_t.spmv(self.ones, stream=self.stream)
 
     def colnorm(self, w: torch.Tensor) -> torch.Tensor:
@@ -68,6 +85,8 @@ class DiffPageRank:
         return self.pagerank(self.colnorm(w))
 
     def close(self):
+        if self.plan_fwd is not self.plan:
+            self.plan_fwd.close()
         self.plan.close()
         self.plan_t.close()
 
@@ -100,9 +119,11 @@ class _PageRank(torch.autograd.Function):
     def forward(ctx, P, op: DiffPageRank):
         P = P.detach().contiguous()
         op.values.copy_(P)
+        if op.plan_fwd is not op.plan:
+            op.plan_fwd.set_values(op.values)
         x = op.x0.clone()
-        it, res, _ = op.plan.pagerank(x, op.alpha, op.tol, op.max_iter, op.check_every,
-                                      stream=op.stream)
+        it, res, _ = op.plan_fwd.pagerank(x, op.alpha, op.tol, op.max_iter, op.check_every,
+                                          stream=op.stream)
         op.last_forward = (it, res)
         ctx.op = op
         ctx.save_for_backward(P, x)
@@ -114,6 +135,7 @@ class _PageRank(torch.autograd.Function):
         P, x = ctx.saved_tensors
         gx = gx.contiguous().to(op.dtype)
         gather_values(op.perm, P, out=op.values_t, stream=op.stream)   # P^T's values
+        op.refresh_transpose_values()
         lam = gx.clone()
         it, res, _ = op.plan.pagerank_adjoint(op.plan_t, gx, lam, op.alpha, op.adj_tol,
                                               op.adj_max_iter, op.check_every,

@@ -98,17 +98,21 @@ def _diff_setup(w, dtype, dev, **kw):
     return ag.DiffPageRank(r, c, n, dtype=dtype, **kw)
 
 
+@pytest.mark.parametrize("stripes", [0, 8])
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
-def test_adjoint_fixed_point_chung_lu(dtype):
-    """20 adjoint iterations against the oracle's, normwise."""
+def test_adjoint_fixed_point_chung_lu(dtype, stripes):
+    """20 adjoint iterations against the oracle's, normwise (P^T on a plain
+    and on a column-stripe plan)."""
     dev = require_gpu()
     w = workload("chung_lu_10k")
     rp, col, vals, n = w["row_ptr"], w["col"], w["values"], w["n_rows"]
-    op = _diff_setup(w, dtype, dev)
+    op = _diff_setup(w, dtype, dev, stripes=stripes)
+    assert op.plan_t.info()["stripes"] == max(stripes, 1)
     vh = host_values(vals, dtype)
     P = torch.from_numpy(vh).to(dtype).to(dev)
     import paper_2605_07391_amd as pkg
     pkg.gather_values(op.perm, P, out=op.values_t)
+    op.refresh_transpose_values()
     g64 = graphgen.uniform(8, 82, n, -1.0, 1.0).astype(_np(dtype)).astype(np.float64)
     g = torch.from_numpy(g64).to(dtype).to(dev)
     for iters in (1, 7, 20):
@@ -151,15 +155,17 @@ def test_gradcheck_fp64(seed):
     op.close()
 
 
+@pytest.mark.parametrize("stripes", [0, 4])
 @pytest.mark.parametrize("seed", [3, 4])
-def test_loss_gradient_vs_oracle_small(seed):
-    """FP64 gradient of ||x* - t||^2 equals the oracle's adjoint gradient."""
+def test_loss_gradient_vs_oracle_small(seed, stripes):
+    """FP64 gradient of ||x* - t||^2 equals the oracle's adjoint gradient
+    (also with the forward and adjoint iterations on column-stripe plans)."""
     dev = require_gpu()
     g = _tiny_graph(40, seed)
     rng = np.random.default_rng(seed)
     w0 = 1.5 - rng.random(len(g["col"]))
     tgt = rng.dirichlet(np.ones(40))
-    op = _diff_setup(g, torch.float64, dev, max_iter=300, check_every=20)
+    op = _diff_setup(g, torch.float64, dev, max_iter=300, check_every=20, stripes=stripes)
     w = torch.tensor(w0, dtype=torch.float64, device=dev, requires_grad=True)
     x = op(w)
     loss = ((x - torch.from_numpy(tgt).to(dev)) ** 2).sum()
@@ -195,6 +201,15 @@ def test_rmat20_fp32_gradient_vs_fp64_oracle_and_finite_differences():
     g32 = grads[torch.float32][1]
     err = np.linalg.norm(g32 - grad_ref) / np.linalg.norm(grad_ref)
     assert err <= 1e-3, err
+    # the same FP32 gradient with the forward and adjoint iterations on
+    # column-stripe plans (8 stripes)
+    ops = _diff_setup(w, torch.float32, dev, tol=1e-7, max_iter=400, check_every=10, stripes=8)
+    wt = torch.from_numpy(w0).float().to(dev).requires_grad_(True)
+    x = ops(wt)
+    ((x.double() - tg.to(dev)) ** 2).sum().backward()
+    gs = wt.grad.double().cpu().numpy()
+    assert np.linalg.norm(gs - grad_ref) / np.linalg.norm(grad_ref) <= 1e-3
+    ops.close()
     op64, g64 = grads[torch.float64]
     assert np.linalg.norm(g64 - grad_ref) / np.linalg.norm(grad_ref) <= 1e-6
     edges = np.random.default_rng(7).choice(m, 100, replace=False)
