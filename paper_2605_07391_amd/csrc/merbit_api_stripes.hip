@@ -104,7 +104,8 @@ int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st) {
 // multiple of the XCD count, and the tiles are cut into that many contiguous
 // ranges; each range takes the (at most cap) most frequent columns of its own
 // nonzeros (counted on every 4th nonzero of a long range), ties by
-// increasing column.  The ranges first get equal tile
+// increasing column, in slots of increasing column.  The ranges first get
+// equal tile
 // counts; with a cache they are then re-cut so that every range carries the
 // same estimated cost, tiles plus the gathers its cache does not serve
 // (kColdWeight tiles per gather: a range whose columns are less concentrated
@@ -181,7 +182,8 @@ int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
         for (int64_t i = 0; i < taken; ++i) cov[k] += top[(size_t)i];
         if (len > 64 * cap) cov[k] = std::min(4.0 * cov[k], (double)len);  // sampled counts
         HIP_TRY(hipMemsetAsync(slot_of, 0xFF, sizeof(int32_t) * (size_t)nc, st));
-        HIP_TRY(launch_stripe_hot(cols, (int32_t)taken, slot_of, p->hot_cols + hoff[k], st));
+        HIP_TRY(launch_stripe_hot(cols, (int32_t)taken, sort_tmp, sort_bytes, csorted, slot_of,
+                                  p->hot_cols + hoff[k], st));
         HIP_TRY(hot_recode(p->scol + lo, len, slot_of, p->colx + lo, st));
         hoff[k + 1] = hoff[k] + (int32_t)taken;
         taken_max = std::max(taken_max, taken);

@@ -359,7 +359,9 @@ hipError_t stripe_rank_bytes(int64_t n, size_t* bytes);
 hipError_t launch_stripe_rank_columns(const int32_t* counts, int64_t n, void* temp,
                                       size_t temp_bytes, int32_t* iota, int32_t* counts_sorted,
                                       int32_t* cols_sorted, hipStream_t st);
-hipError_t launch_stripe_hot(const int32_t* sorted_cols, int32_t taken, int32_t* slot_of,
+// the taken most frequent columns (top_cols) get slots in column order
+hipError_t launch_stripe_hot(const int32_t* top_cols, int32_t taken, void* temp,
+                             size_t temp_bytes, int32_t* cols_sorted, int32_t* slot_of,
                              int32_t* hot_cols, hipStream_t st);
 hipError_t launch_stripe_combine(int dtype, int stripes, const void* yv, int64_t nv,
                                  const StripeWord* sw, int64_t words, int64_t n_rows, void* y,

@@ -243,18 +243,29 @@ hipError_t launch_stripe_rows(const StripeSplitArgs& a, int64_t nv, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_stripe_hot(const int32_t* sorted_cols, int32_t taken, int32_t* slot_of,
+hipError_t launch_stripe_hot(const int32_t* top_cols, int32_t taken, void* temp,
+                             size_t temp_bytes, int32_t* cols_sorted, int32_t* slot_of,
                              int32_t* hot_cols, hipStream_t st) {
   if (taken <= 0) return hipSuccess;
-  hipLaunchKernelGGL(slot_assign_kernel, dim3(blocks_of(taken)), dim3(256), 0, st, sorted_cols,
+  // slots in column order: the hot-value gathers then walk x in order
+  hipError_t e = hipcub::DeviceRadixSort::SortKeys(temp, temp_bytes, top_cols, cols_sorted,
+                                                   (int)taken, 0, 32, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(slot_assign_kernel, dim3(blocks_of(taken)), dim3(256), 0, st, cols_sorted,
                      taken, slot_of, hot_cols);
   return hipGetLastError();
 }
 
 hipError_t stripe_rank_bytes(int64_t n, size_t* bytes) {
-  return hipcub::DeviceRadixSort::SortPairsDescending(
-      nullptr, *bytes, (const int32_t*)nullptr, (int32_t*)nullptr, (const int32_t*)nullptr,
+  size_t a = 0, b = 0;
+  hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(
+      nullptr, a, (const int32_t*)nullptr, (int32_t*)nullptr, (const int32_t*)nullptr,
       (int32_t*)nullptr, (int)n);
+  if (e != hipSuccess) return e;
+  e = hipcub::DeviceRadixSort::SortKeys(nullptr, b, (const int32_t*)nullptr, (int32_t*)nullptr,
+                                        (int)n, 0, 32);
+  *bytes = a > b ? a : b;
+  return e;
 }
 
 hipError_t launch_stripe_rank_columns(const int32_t* counts, int64_t n, void* temp,
