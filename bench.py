@@ -76,7 +76,7 @@ def load_traffic(workload: str, dtype: str, commit: int, stripes: int = 1):
 
 def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes: int,
             alpha: float, hot_columns: int = -1, commit: str = "auto", blocks_per_cu: int = 0,
-            tune: bool = False, stripes: int = 0):
+            tune: bool = False, stripes: int = 0, desc_bits: int = 32):
     import numpy as np
     import torch
 
@@ -92,49 +92,58 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
     torch.cuda.synchronize()
     tuning = None
     if tune:
-        # sigma and block size by measurement on this matrix (untimed); the
-        # 64-bit-descriptor kernels are swept too and reported beside it
+        # sigma, block size, commit family, column stripes and descriptor
+        # width by measurement on this matrix (untimed); every table is kept
+        # in the output
+        def cands_of(table, commit_name, stripes_, bits):
+            return [(t, a, b, commit_name, stripes_, bits) for (a, b), t in table.items() if t > 0]
+
         best, table = pkg.tune(r, c, v, n, reps=10, commit=commit, hot_columns=hot_columns)
-        table_block = None
-        cands = [(t, a, b, "wave" if commit == "auto" else commit)
-                 for (a, b), t in table.items() if t > 0]
-        cands = [(t, a, b, cm, 0) for t, a, b, cm in cands]
-        table_block = table_striped = None
+        cands = cands_of(table, "wave" if commit == "auto" else commit, 0, 32)
+        table_block = table_striped = table64s = None
         if commit == "auto":
             # the paper's block-commit layout, b = 128 .. 1024 lanes, swept as well
             _, table_block = pkg.tune(r, c, v, n, reps=10, commit="block",
                                       hot_columns=hot_columns, block_lanes=[128, 256, 512, 1024])
-            cands += [(t, a, b, "block", 0) for (a, b), t in table_block.items() if t > 0]
-        if commit in ("auto", "wave") and stripes < 0:
-            # the column-stripe plan (8 stripes, one tile range per XCD); its
-            # time includes the launch that adds each row's stripes
-            _, table_striped = pkg.tune(r, c, v, n, reps=10, commit="wave",
-                                        hot_columns=hot_columns, stripes=8)
-            cands += [(t, a, b, "wave", 8) for (a, b), t in table_striped.items() if t > 0]
-        # the library default (sigma 12 / 7, 1024 / 512 lanes, wave commit, no
-        # stripes) unless a candidate is more than 2 % faster: near-ties do
-        # not flip the configuration from run to run
-        d_sigma, d_lanes = (12, 1024) if dtype == torch.float32 else (7, 512)
-        t_best, b_sigma, b_lanes, b_commit, b_stripes = min(cands)
-        t_def = table.get((d_sigma, d_lanes), -1.0)
-        if t_def > 0 and t_best >= 0.98 * t_def:
-            sigma, block_lanes, commit, stripes = d_sigma, d_lanes, "wave", 0
-        else:
-            sigma, block_lanes, commit, stripes = b_sigma, b_lanes, b_commit, b_stripes
+            cands += cands_of(table_block, "block", 0, 32)
         best64, table64 = pkg.tune(r, c, v, n, reps=10, hot_columns=hot_columns, desc_bits=64,
                                    block_lanes=[256, 512])
+        if commit in ("auto", "wave"):
+            cands += cands_of(table64, "wave", 0, 64)
+        if commit in ("auto", "wave") and stripes < 0:
+            # the column-stripe plan (8 stripes, one tile range per XCD), with
+            # 32- and 64-bit descriptors; its time includes the launch that
+            # adds each row's stripes
+            _, table_striped = pkg.tune(r, c, v, n, reps=10, commit="wave",
+                                        hot_columns=hot_columns, stripes=8)
+            cands += cands_of(table_striped, "wave", 8, 32)
+            _, table64s = pkg.tune(r, c, v, n, reps=10, hot_columns=hot_columns, desc_bits=64,
+                                   block_lanes=[256, 512], stripes=8)
+            cands += cands_of(table64s, "wave", 8, 64)
+        # the library default (sigma 12 / 7, 1024 / 512 lanes, wave commit, no
+        # stripes, 32-bit descriptors) unless a candidate is more than 2 %
+        # faster: near-ties do not flip the configuration from run to run
+        d_sigma, d_lanes = (12, 1024) if dtype == torch.float32 else (7, 512)
+        t_best, b_sigma, b_lanes, b_commit, b_stripes, b_bits = min(cands)
+        t_def = table.get((d_sigma, d_lanes), -1.0)
+        if t_def > 0 and t_best >= 0.98 * t_def:
+            sigma, block_lanes, commit, stripes, desc_bits = d_sigma, d_lanes, "wave", 0, 32
+        else:
+            sigma, block_lanes, commit, stripes, desc_bits = (b_sigma, b_lanes, b_commit,
+                                                              b_stripes, b_bits)
+
+        def fmt(t):
+            return None if t is None else {f"s{a}_b{b}": round(x, 1) for (a, b), x in t.items()}
+
         tuning = {"chosen": {"sigma": sigma, "block_lanes": block_lanes, "commit": commit,
-                             "stripes": stripes},
+                             "stripes": stripes, "desc_bits": desc_bits},
                   "rule": "fastest candidate if more than 2 % faster than the default "
                           "(sigma, lanes) of the wave kernel, else the default",
-                  "us_per_spmv": {f"s{a}_b{b}": round(t, 1) for (a, b), t in table.items()},
-                  "block_commit_us_per_spmv": None if table_block is None else {
-                      f"s{a}_b{b}": round(t, 1) for (a, b), t in table_block.items()},
-                  "striped8_us_per_spmv": None if table_striped is None else {
-                      f"s{a}_b{b}": round(t, 1) for (a, b), t in table_striped.items()},
-                  "desc64": {"best": best64,
-                             "us_per_spmv": {f"s{a}_b{b}": round(t, 1)
-                                             for (a, b), t in table64.items()},
+                  "us_per_spmv": fmt(table),
+                  "block_commit_us_per_spmv": fmt(table_block),
+                  "striped8_us_per_spmv": fmt(table_striped),
+                  "desc64": {"best": best64, "us_per_spmv": fmt(table64),
+                             "striped8_us_per_spmv": fmt(table64s),
                              "vs_32bit": round(min(t for t in table.values() if t > 0)
                                                / min(t for t in table64.values() if t > 0), 3)}}
     stripes = max(stripes, 0)
@@ -143,7 +152,7 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
     e0.record()
     plan = pkg.Plan(r, c, v, n, sigma=sigma, block_lanes=block_lanes, hot_columns=hot_columns,
                     commit=commit, blocks_per_cu=blocks_per_cu, validate=False,
-                    stripes=max(stripes, 0))
+                    stripes=max(stripes, 0), desc_bits=desc_bits)
     e1.record()
     torch.cuda.synchronize()
     plan_ms = e0.elapsed_time(e1)
@@ -457,6 +466,7 @@ def main():
     ap.add_argument("--hot-columns", type=int, default=-1,
                     help="LDS x cache size in columns: -1 automatic, 0 off")
     ap.add_argument("--commit", default="auto", choices=["auto", "block", "wave"])
+    ap.add_argument("--desc-bits", type=int, default=32, choices=[32, 64])
     ap.add_argument("--stripes", type=int, default=-1,
                     help="column stripes: -1 = the autotuner also tries 8, 0 = none, S = S")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
@@ -504,14 +514,15 @@ def main():
     tune = not args.no_tune and args.sigma == 0 and args.block_lanes == 0
     main_run = run_gpu(w, args.dtype, args.steps, args.warmup, args.sigma, args.block_lanes,
                        args.alpha, args.hot_columns, args.commit, args.blocks_per_cu, tune,
-                       args.stripes)
+                       args.stripes, args.desc_bits)
     info = main_run["info"]
     print(f"[bench] {args.dtype}: step {main_run['step_ms'] * 1e3:.1f} us, spmv "
           f"{main_run['spmv_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
     extra = None
     if not args.no_f64 and args.dtype == "f32" and w["meta"]["generator"] != "stress":
         r64 = run_gpu(w, "f64", args.steps, args.warmup, 0, args.block_lanes, args.alpha,
-                      args.hot_columns, args.commit, args.blocks_per_cu, tune, args.stripes)
+                      args.hot_columns, args.commit, args.blocks_per_cu, tune, args.stripes,
+                      args.desc_bits)
         extra = {
             "value": round(r64["value_gnzs"], 3), "ms_per_step": round(r64["step_ms"], 5),
             "spmv_us": round(r64["spmv_ms"] * 1e3, 2), "spmv_gnzs": round(r64["spmv_gnzs"], 3),
@@ -522,7 +533,7 @@ def main():
             "hot_coverage": round(r64["info"]["hot_coverage"], 4),
             "traffic": load_traffic(args.workload, "f64", r64["info"]["commit"],
                                     r64["info"]["stripes"]),
-            "stripes": r64["info"]["stripes"],
+            "stripes": r64["info"]["stripes"], "desc_bits": r64["info"]["desc_bits"],
             "block_lanes": r64["info"]["block_lanes"],
             "commit": {1: "block", 2: "wave"}[r64["info"]["commit"]], "tuning": r64["tuning"],
         }
@@ -588,6 +599,7 @@ def main():
                    "hot_columns": info["hot_columns"],
                    "hot_coverage": round(info["hot_coverage"], 4), "grid": info["grid"],
                    "stripes": info["stripes"], "ranges": info["ranges"],
+                   "desc_bits": info["desc_bits"],
                    "plan_rows": info["plan_rows"],
                    "alpha": args.alpha,
                    "seed": w["meta"].get("seed"), "x0": "1/n"},
