@@ -271,3 +271,54 @@ def test_striped_stress24_fp64_full_size():
     torch.cuda.synchronize()
     check_spmv(y, rp, col, np.asarray(vals, np.float64), x64, torch.float64, "stress24 S8")
     plan.close()
+
+
+DESC64 = [(torch.float32, 24, 512), (torch.float32, 16, 256), (torch.float64, 16, 512),
+          (torch.float64, 14, 256)]
+
+
+@pytest.mark.parametrize("dtype,sigma,block_lanes", DESC64,
+                         ids=[f"{'f32' if d == torch.float32 else 'f64'}s{s}b{b}"
+                              for d, s, b in DESC64])
+@pytest.mark.parametrize("name", ["random1_700x300", "single_long_row", "long_then_empty",
+                                  "chung_lu_10k", "one_column", "fuzz1_3634x3198"])
+def test_striped_desc64(name, dtype, sigma, block_lanes):
+    """64-bit descriptors on a column-stripe plan: the stacked plan bit exact
+    against the oracle's 64-bit TILE, y within tolerance."""
+    dev = require_gpu()
+    rp, col, vals, nc = case_matrix(CASES, name, seed=sigma)
+    plan, keep = _plan(rp, col, vals, nc, dtype, dev, sigma=sigma, block_lanes=block_lanes,
+                       desc_bits=64, stripes=8)
+    info = plan.info()
+    assert info["desc_bits"] == 64 and info["stripes"] == 8
+    vrp, _ = stacked_row_ptr(rp, col, nc, 8)
+    tx, ty, ld = plan.export()
+    ox, oy, od = oracle.plan64(vrp, OMEGA, sigma)
+    assert np.array_equal(tx, ox) and np.array_equal(ty, oy) and np.array_equal(ld, od)
+    x64 = seeded_x(nc, sigma, dtype)
+    for rep in range(2):
+        y = torch.full((len(rp) - 1,), float("nan"), dtype=dtype, device=dev)
+        plan.spmv(torch.from_numpy(x64).to(dtype).to(dev), out=y)
+        torch.cuda.synchronize()
+        check_spmv(y, rp, col, host_values(vals, dtype), x64, dtype, f"{name} desc64 S8")
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype,sigma", [(torch.float32, 24), (torch.float64, 16)],
+                         ids=["f32s24", "f64s16"])
+def test_striped_desc64_rmat22_pagerank(dtype, sigma):
+    """The 64-bit-descriptor column-stripe configuration at full size:
+    20 PageRank iterations against the oracle."""
+    dev = require_gpu()
+    w = workload("rmat22")
+    n = w["n_rows"]
+    plan, keep = _plan(w["row_ptr"], w["col"], w["values"], n, dtype, dev, sigma=sigma,
+                       block_lanes=512, desc_bits=64, stripes=8)
+    x0 = np.full(n, 1.0 / n).astype(np.float32 if dtype == torch.float32 else np.float64)
+    x = torch.from_numpy(x0).to(dev)
+    iters, resid, conv = plan.pagerank(x, ALPHA, tol=0.0, max_iter=20)
+    ref, _, _ = oracle.pagerank(w["row_ptr"], w["col"], host_values(w["values"], dtype), ALPHA,
+                                20, x0.astype(np.float64))
+    rel = np.abs(x.double().cpu().numpy() - ref) / ref
+    assert iters == 20 and rel.max() <= PR_TOL[dtype], rel.max()
+    plan.close()
