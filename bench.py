@@ -59,15 +59,28 @@ def algorithmic_bytes(info: dict, value_size: int) -> float:
             + 4 * lanes * (1.0 - r_f))
 
 
-def load_traffic(workload: str, dtype: str, commit: int, stripes: int = 1):
+def kernel_instance(info: dict) -> str:
+    """Name of the fused kernel's template instance a plan launches."""
+    v = "float" if info["dtype"] == 0 else "double"
+    hot = "true" if info["hot_columns"] else "false"
+    waves = info["block_lanes"] // 64
+    if info["commit"] == 1:
+        return f"merbit::spmv_kernel<{v}, {info['sigma']}, {waves}, {hot}>"
+    word = "unsigned long" if info["desc_bits"] == 64 else "unsigned int"
+    return f"merbit::spmv_wave_kernel<{v}, {info['sigma']}, {waves}, {hot}, {word}>"
+
+
+def load_traffic(workload: str, dtype: str, info: dict):
     """Measured HBM bytes per SpMV from the committed rocprofv3 counter
-    summary, if it was taken on the current source of the same kernels."""
+    summary, if it was taken on the same kernel instance, stripe count and
+    kernel sources."""
     path = os.path.join(ROOT, "profiles", f"spmv_traffic_{workload}_{dtype}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    if (not rec.get("kernel", "").startswith(KERNELS[commit][0] + "<")
+    commit, stripes = info["commit"], info["stripes"]
+    if (rec.get("kernel") != kernel_instance(info)
             or rec.get("stripes", 1) != stripes
             or rec.get("spmv_source_sha256_16") != spmv_source_hash(commit, stripes)):
         return None
@@ -531,8 +544,7 @@ def main():
             "plan_ms": round(r64["plan_ms"], 3), "sigma": r64["info"]["sigma"],
             "hot_columns": r64["info"]["hot_columns"],
             "hot_coverage": round(r64["info"]["hot_coverage"], 4),
-            "traffic": load_traffic(args.workload, "f64", r64["info"]["commit"],
-                                    r64["info"]["stripes"]),
+            "traffic": load_traffic(args.workload, "f64", r64["info"]),
             "stripes": r64["info"]["stripes"], "desc_bits": r64["info"]["desc_bits"],
             "block_lanes": r64["info"]["block_lanes"],
             "commit": {1: "block", 2: "wave"}[r64["info"]["commit"]], "tuning": r64["tuning"],
@@ -605,10 +617,10 @@ def main():
                    "seed": w["meta"].get("seed"), "x0": "1/n"},
         "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                     "traffic": load_traffic(args.workload, args.dtype, info["commit"],
-                                             info["stripes"]),
-                     "kernel": " + ".join(k for k, _ in spmv_kernels(info["commit"],
-                                                                     info["stripes"])),
+                     "traffic": load_traffic(args.workload, args.dtype, info),
+                     "kernel": kernel_instance(info) + (
+                         f" + merbit::stripe_combine_kernel<{'float' if info['dtype'] == 0 else 'double'}, "
+                         f"{info['stripes']}>" if info["stripes"] > 1 else ""),
                      "alg_bytes_per_launch": int(main_run["alg_bytes"]),
                      "mean_launch_us": round(main_run["spmv_ms"] * 1e3, 2),
                      "measured_copy_gbs": round(copy_gbs, 1),
