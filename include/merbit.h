@@ -87,9 +87,9 @@ typedef struct {
                               use and replay it; nonzero: launch every kernel directly  */
     int32_t desc_bits;     /* lane descriptor width: 0 or 32 (sigma <= 12), or 64
                               (2 ceil(log2(64 sigma)) + sigma <= 64, sigma <= 40; wave
-                              commit only; built: FP32 sigma 16, 20, 24, FP64 14, 16,
-                              block_lanes 256 or 512).  SpMM and the adjoint pieces
-                              need 32-bit plans.                                        */
+                              commit only; built: FP32 sigma 16, 20, 24, 28, 32, FP64
+                              14, 16, 20, 24, block_lanes 256 or 512).  SpMM and the
+                              adjoint pieces need 32-bit plans.                         */
     int32_t stripes;       /* column stripes -- an addition to the paper's method for
                               gfx950's per-XCD caches: 0 or 1 = off; S = 2, 4, 8, 16 or
                               32 (wave commit only) cuts the columns into S stripes of

@@ -254,17 +254,20 @@ static WaveEntry wave_pick_sigma(int sigma) {
 }
 
 // 64-bit descriptors: longer lanes than 32 bits allow.  FP32: sigma 16, 20,
-// 24; FP64 (twice the registers per value): sigma 14, 16.  256 or 512 lanes.
+// 24, 28, 32; FP64 (twice the registers per value): sigma 14, 16, 20, 24.  256 or
+// 512 lanes.
 template <typename V, int W, bool H>
 static WaveEntry wave_pick_sigma64(int sigma) {
   if (sizeof(V) == 4) {
     switch (sigma) {
       MERBIT_WCASE(16, uint64_t) MERBIT_WCASE(20, uint64_t) MERBIT_WCASE(24, uint64_t)
+      MERBIT_WCASE(28, uint64_t) MERBIT_WCASE(32, uint64_t)
       default: return WaveEntry{nullptr, nullptr};
     }
   }
   switch (sigma) {
-    MERBIT_WCASE(14, uint64_t) MERBIT_WCASE(16, uint64_t)
+    MERBIT_WCASE(14, uint64_t) MERBIT_WCASE(16, uint64_t) MERBIT_WCASE(20, uint64_t)
+    MERBIT_WCASE(24, uint64_t)
     default: return WaveEntry{nullptr, nullptr};
   }
 }

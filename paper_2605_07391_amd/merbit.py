@@ -486,7 +486,7 @@ def tune(row_ptr: torch.Tensor, col_ind: torch.Tensor, values: torch.Tensor, n_c
     code = _vdtype(values)
     n_rows = row_ptr.numel() - 1
     if sigmas is None and desc_bits == 64:
-        sigmas = [16, 20, 24] if code == F32 else [14, 16]
+        sigmas = [16, 20, 24, 28, 32] if code == F32 else [14, 16, 20, 24]
     elif sigmas is None:
         sigmas = list(range(7, 13)) if code == F32 else list(range(4, 11))
     if block_lanes is None:

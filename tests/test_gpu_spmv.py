@@ -313,8 +313,9 @@ def test_autotuner_picks_a_measured_candidate(dtype):
 
 
 # 64-bit lane descriptors: (dtype, sigma) pairs the wave kernel builds
-DESC64 = [(torch.float32, 16), (torch.float32, 20), (torch.float32, 24), (torch.float64, 14),
-          (torch.float64, 16)]
+DESC64 = [(torch.float32, 16), (torch.float32, 20), (torch.float32, 24), (torch.float32, 28),
+          (torch.float32, 32), (torch.float64, 14), (torch.float64, 16), (torch.float64, 20),
+          (torch.float64, 24)]
 
 
 @pytest.mark.parametrize("block_lanes,hot", [(256, 0), (512, -1), (512, 37)])

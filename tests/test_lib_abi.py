@@ -79,7 +79,7 @@ def test_argument_errors_without_gpu():
                                   None, ctypes.byref(out)) == mb.EUNSUPPORTED
     assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0, opts(desc_bits=64, sigma=18),
                                   None, ctypes.byref(out)) == mb.EUNSUPPORTED
-    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 1, opts(desc_bits=64, sigma=24),
+    assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 1, opts(desc_bits=64, sigma=28),
                                   None, ctypes.byref(out)) == mb.EUNSUPPORTED
     assert lib.merbit_plan_create(1, 1, 0, vp(8), None, None, 0,
                                   opts(desc_bits=64, sigma=24, block_lanes=1024), None,
