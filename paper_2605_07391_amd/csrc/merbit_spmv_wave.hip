@@ -51,6 +51,16 @@ __device__ __forceinline__ uint64_t load_desc<uint64_t>(const SpmvArgs& a, int j
   return a.lane_desc64[j];
 }
 
+// Buffer-resource loads of the tile stream: faster for FP32 (both descriptor
+// widths) and for FP64 with 64-bit descriptors (3.7-5 % per SpMV on R-MAT 22),
+// slower by 2 % for FP64 with 32-bit descriptors, which keeps plain loads.
+template <typename V, typename D>
+constexpr bool kBufferStream = sizeof(V) == 4 || sizeof(D) == 8;
+// word 3 of a raw (unformatted, stride 0) buffer resource on gfx950
+constexpr int kBufferWord3 = 0x00020000;
+// cache policy bits of a gfx950 buffer load: nt (streaming, evicted first)
+constexpr int kPolicyStream = 2;
+
 template <typename V, int SIGMA, typename D>
 __device__ __forceinline__ void wave_load_tile(const SpmvArgs& a, const int32_t* __restrict__ col,
                                                const V* __restrict__ val, int t, int lid,
@@ -65,11 +75,36 @@ __device__ __forceinline__ void wave_load_tile(const SpmvArgs& a, const int32_t*
   // A tile without nonzeros reads nothing: col / val may be empty (nnz = 0).
   // The branch is uniform across the wavefront.
   if (s.x_se > 0) {
+    if constexpr (kBufferStream<V, D>) {
+      // buffer loads over the tile's own range (streaming policy): one 32-bit
+      // offset per lane instead of a 64-bit address per load, and reads past
+      // the tile's end return 0 without a clamp.  A zero column gathers x[0]
+      // (x is not empty when the tile has nonzeros) and its product is never
+      // staged.
+      const int xws = __builtin_amdgcn_readfirstlane(s.x_ws);
+      const int xse = __builtin_amdgcn_readfirstlane(s.x_se);
+      const __amdgpu_buffer_rsrc_t rc = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(col + xws), (short)0, xse * 4, kBufferWord3);
+      const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(val + xws), (short)0, xse * (int)sizeof(V), kBufferWord3);
 #pragma unroll
-    for (int it = 0; it < SIGMA; ++it) {
-      const int k = min(lid + it * kOmega, s.x_se - 1);
-      s.cc[it] = __builtin_nontemporal_load(col + s.x_ws + k);
-      s.vv[it] = __builtin_nontemporal_load(val + s.x_ws + k);
+      for (int it = 0; it < SIGMA; ++it) {
+        const int k = lid + it * kOmega;
+        s.cc[it] = (int)__builtin_amdgcn_raw_buffer_load_b32(rc, k * 4, 0, kPolicyStream);
+        if constexpr (sizeof(V) == 4)
+          s.vv[it] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(rv, k * 4, 0,
+                                                                                kPolicyStream));
+        else
+          s.vv[it] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rv, k * 8, 0,
+                                                                                kPolicyStream));
+      }
+    } else {
+#pragma unroll
+      for (int it = 0; it < SIGMA; ++it) {
+        const int k = min(lid + it * kOmega, s.x_se - 1);
+        s.cc[it] = __builtin_nontemporal_load(col + s.x_ws + k);
+        s.vv[it] = __builtin_nontemporal_load(val + s.x_ws + k);
+      }
     }
   } else {
 #pragma unroll
@@ -258,17 +293,18 @@ static WaveEntry wave_pick_sigma(int sigma) {
 // 512 lanes.
 template <typename V, int W, bool H>
 static WaveEntry wave_pick_sigma64(int sigma) {
-  if (sizeof(V) == 4) {
+  if constexpr (sizeof(V) == 4) {
     switch (sigma) {
       MERBIT_WCASE(16, uint64_t) MERBIT_WCASE(20, uint64_t) MERBIT_WCASE(24, uint64_t)
       MERBIT_WCASE(28, uint64_t) MERBIT_WCASE(32, uint64_t)
       default: return WaveEntry{nullptr, nullptr};
     }
-  }
-  switch (sigma) {
-    MERBIT_WCASE(14, uint64_t) MERBIT_WCASE(16, uint64_t) MERBIT_WCASE(20, uint64_t)
-    MERBIT_WCASE(24, uint64_t)
-    default: return WaveEntry{nullptr, nullptr};
+  } else {
+    switch (sigma) {
+      MERBIT_WCASE(14, uint64_t) MERBIT_WCASE(16, uint64_t) MERBIT_WCASE(20, uint64_t)
+      MERBIT_WCASE(24, uint64_t)
+      default: return WaveEntry{nullptr, nullptr};
+    }
   }
 }
 #undef MERBIT_WCASE
