@@ -278,7 +278,7 @@ def run_ppr(w, k: int, steps: int, warmup: int, alpha: float):
             "max_mass_error": mass_err, "sources_seed": 4}
 
 
-def run_multi(steps: int, warmup: int, alpha: float, stripes: int = 0):
+def run_multi(steps: int, warmup: int, alpha: float, stripes: int = 0, plan_kw=None):
     """PageRank of the 256 Chung-Lu graphs stored on one diagonal, FP32, one
     plan: a step is one fused SpMV over all graphs plus the per-graph update."""
     import numpy as np
@@ -292,7 +292,7 @@ def run_multi(steps: int, warmup: int, alpha: float, stripes: int = 0):
     r = torch.from_numpy(w["row_ptr"]).to(dev)
     c = torch.from_numpy(w["col"]).to(dev)
     v = torch.from_numpy(w["values"]).float().to(dev)
-    plan = pkg.Plan(r, c, v, n, validate=False, stripes=stripes)
+    plan = pkg.Plan(r, c, v, n, validate=False, stripes=stripes, **(plan_kw or {}))
     sizes = np.diff(gp)
     x0 = torch.from_numpy(np.repeat(1.0 / sizes, sizes)).float().to(dev)
     x = x0.clone()
@@ -316,10 +316,18 @@ def run_multi(steps: int, warmup: int, alpha: float, stripes: int = 0):
             "ms_per_step": round(step_ms, 4), "spmv_us": round(spmv_ms * 1e3, 1),
             "gnzs": round(nnz / (step_ms * 1e-3) / 1e9, 3),
             "spmv_gnzs": round(nnz / (spmv_ms * 1e-3) / 1e9, 3),
-            "stripes": stripes, "seed": w["meta"]["seed"]}
+            "stripes": stripes, "plan": plan_kw or "default", "seed": w["meta"]["seed"]}
 
 
-def run_bicgstab(scale: int, steps: int, stripes: int = 0):
+def tuned_kw(info) -> dict:
+    """Plan options of a tuned striped run, for the other striped workloads."""
+    if info["stripes"] <= 1 or {1: "block", 2: "wave"}[info["commit"]] != "wave":
+        return {}
+    return {"sigma": info["sigma"], "block_lanes": info["block_lanes"],
+            "desc_bits": info["desc_bits"], "commit": "wave"}
+
+
+def run_bicgstab(scale: int, steps: int, stripes: int = 0, plan_kw=None):
     """BiCGSTAB (Sec. 5.5.2) on the symmetric 0/1 R-MAT system of the given
     scale, FP64, b = A x_true: `steps` iterations (two fused SpMVs and five
     vector kernels each) after 20 warm-up iterations.  Returns per-iteration
@@ -334,7 +342,7 @@ def run_bicgstab(scale: int, steps: int, stripes: int = 0):
     r = torch.from_numpy(w["row_ptr"]).to(dev)
     c = torch.from_numpy(w["col"]).to(dev)
     v = torch.from_numpy(w["values"]).to(dev)
-    plan = pkg.Plan(r, c, v, n, validate=False, stripes=stripes)
+    plan = pkg.Plan(r, c, v, n, validate=False, stripes=stripes, **(plan_kw or {}))
     b = plan.spmv(torch.from_numpy(w["x"]).to(dev))
     x = torch.zeros(n, dtype=torch.float64, device=dev)
     # two chunks of the timed run's shape: both of its HIP graphs are recorded
@@ -359,7 +367,7 @@ def run_bicgstab(scale: int, steps: int, stripes: int = 0):
             "spmv_us": round(spmv_ms * 1e3, 1),
             "spmv_share": round(2 * spmv_ms / it_ms, 3),
             "gnzs": round(2 * nnz / (it_ms * 1e-3) / 1e9, 3),
-            "rel_residual": res, "stripes": stripes, "seed": scale}
+            "rel_residual": res, "stripes": stripes, "plan": plan_kw or "default", "seed": scale}
 
 
 def measured_copy_gbs(mib: int = 1024, reps: int = 5) -> float:
@@ -557,7 +565,10 @@ def main():
         ppr["vs_plain_spmv"] = round(ppr["gnz_rhs_per_s"] / main_run["spmv_gnzs"], 3)
         print(f"[bench] ppr64: step {ppr['ms_per_step']:.3f} ms, spmm {ppr['spmm_us']:.1f} us",
               file=sys.stderr, flush=True)
-        multi = run_multi(args.batched_steps, 2, args.alpha, stripes=8)
+        # the striped runs take the (sigma, lanes, descriptor width) tuned on the
+        # R-MAT matrix of the same value type
+        multi = run_multi(args.batched_steps, 2, args.alpha, stripes=8,
+                          plan_kw=tuned_kw(main_run["info"]) if args.dtype == "f32" else None)
         multi_plain = run_multi(args.batched_steps, 2, args.alpha)
         multi["one_plan_without_stripes"] = {k: multi_plain[k] for k in
                                              ("ms_per_step", "spmv_us", "gnzs", "spmv_gnzs")}
@@ -576,7 +587,8 @@ def main():
               f"{adj['backward_ms']:.2f} ms", file=sys.stderr, flush=True)
     bicg = None
     if not args.no_bicgstab and w["meta"]["generator"] == "rmat":
-        bicg = run_bicgstab(args.bicgstab_scale, args.batched_steps * 10, stripes=8)
+        bicg = run_bicgstab(args.bicgstab_scale, args.batched_steps * 10, stripes=8,
+                            plan_kw=tuned_kw(r64["info"]) if extra is not None else None)
         bicg_plain = run_bicgstab(args.bicgstab_scale, args.batched_steps * 10)
         bicg["one_plan_without_stripes"] = {k: bicg_plain[k] for k in
                                             ("ms_per_iteration", "spmv_us", "spmv_share", "gnzs")}

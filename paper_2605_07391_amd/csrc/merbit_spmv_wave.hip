@@ -60,6 +60,8 @@ constexpr bool kBufferStream = sizeof(V) == 4 || sizeof(D) == 8;
 constexpr int kBufferWord3 = 0x00020000;
 // cache policy bits of a gfx950 buffer load: nt (streaming, evicted first)
 constexpr int kPolicyStream = 2;
+// hot x values loaded per lane before they are stored to LDS
+constexpr int kHotBatch = 16;
 
 template <typename V, int SIGMA, typename D>
 __device__ __forceinline__ void wave_load_tile(const SpmvArgs& a, const int32_t* __restrict__ col,
@@ -153,9 +155,31 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
   const V* s_hot = reinterpret_cast<const V*>(s_dyn);
   if (HOT) {
+    // kHotBatch loads per lane in flight before their LDS stores: the copy
+    // takes h_num / (kHotBatch * block lanes) memory round trips, not
+    // h_num / block lanes (one block per CU waits for it)
+    // (buffer loads over the block's hot slice: reads past its end return 0)
+    constexpr int NT = WAVES * kOmega;
     V* dst = reinterpret_cast<V*>(s_dyn);
-    const V* __restrict__ xh = static_cast<const V*>(a.x_hot) + h_begin;
-    for (int s = tid; s < h_num; s += WAVES * kOmega) dst[s] = xh[s];
+    const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(static_cast<const V*>(a.x_hot) + h_begin), (short)0, h_num * (int)sizeof(V),
+        kBufferWord3);
+    for (int s0 = tid; s0 < h_num; s0 += kHotBatch * NT) {
+      V hv[kHotBatch];
+#pragma unroll
+      for (int u = 0; u < kHotBatch; ++u) {
+        const int off = (s0 + u * NT) * (int)sizeof(V);
+        if constexpr (sizeof(V) == 4)
+          hv[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(rh, off, 0, 0));
+        else
+          hv[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rh, off, 0, 0));
+      }
+#pragma unroll
+      for (int u = 0; u < kHotBatch; ++u) {
+        const int s = s0 + u * NT;
+        if (s < h_num) dst[s] = hv[u];
+      }
+    }
     __syncthreads();
   }
 
