@@ -31,6 +31,13 @@ FLAGS = [
     f"-I{os.path.join(ROOT, 'include')}",
 ]
 
+# Per-file flags.  The wave kernel reads a tile-queue atomic's result one tile
+# after issuing it; the atomic optimizer would turn the single-lane atomic into
+# a wave reduction that reads the result (and waits for it) at once.
+FILE_FLAGS = {
+    "merbit_spmv_wave.hip": ["-mllvm", "-amdgpu-atomic-optimizer-strategy=None"],
+}
+
 
 def build(verbose: bool = False, jobs: int = 4) -> str:
     """Compile every source to an object file (in parallel) and link the
@@ -46,7 +53,8 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
             src = pending.pop(0)
             obj = os.path.join(objdir, src.replace(".hip", ".o"))
             objs.append(obj)
-            cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+            cmd = [HIPCC, *FLAGS, *FILE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src),
+                   "-o", obj]
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE,

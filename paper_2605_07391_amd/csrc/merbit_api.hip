@@ -39,7 +39,7 @@ void plan_free_all(merbit_plan* p) {
                   p->multi_gsum[1], p->bvec[0], p->bvec[1], p->bvec[2], p->bvec[3], p->bvec[4],
                   p->bvec[5], p->bvec[6], p->bpart[0], p->bpart[1], p->bpart[2], p->bpart[3],
                   p->bpart[4], p->bpart[5], p->bpart[6], p->sperm, p->scol, p->svals, p->swords,
-                  p->yv[0], p->yv[1], p->range_tile, p->hot_off};
+                  p->yv[0], p->yv[1], p->range_tile, p->hot_off, p->queue};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (auto& ev : p->events) {
@@ -72,6 +72,7 @@ static SpmvArgs spmv_args(const merbit_plan* p, const void* x, void* y, void* z)
   a.ranges = p->ranges;
   a.range_tile = p->range_tile;
   a.hot_off = p->hot_off;
+  a.queue = p->queue;
   return a;
 }
 
@@ -511,6 +512,15 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
     rc = build_tile(p, row_ptr, st);
     if (rc == MERBIT_OK) rc = build_hot_cache(p, hot_columns, st);
     if (rc == MERBIT_OK) rc = size_grid(p);
+  }
+  if (rc == MERBIT_OK && p->commit == MERBIT_COMMIT_WAVE && p->tile_num > 0 && p->ranges > 1) {
+    // tile queues of the wave kernel, zero before the first launch.  Only with
+    // ranges: one counter for a whole grid (4,096 wavefronts on R-MAT 22) is
+    // served one atomic at a time and made a plain plan's SpMV 4x slower.
+    const size_t qb = sizeof(unsigned long long) * kQueueStride * (size_t)p->ranges;
+    hipError_t qe = hipMalloc(&p->queue, qb);
+    if (qe == hipSuccess) qe = hipMemsetAsync(p->queue, 0, qb, st);
+    if (qe != hipSuccess) rc = fail_hip("tile queue", qe);
   }
   if (rc != MERBIT_OK) {
     std::string msg = g_last_error;

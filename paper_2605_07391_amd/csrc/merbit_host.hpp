@@ -60,6 +60,7 @@ struct merbit_plan {
   int ranges = 1;
   int32_t* range_tile = nullptr;     // [ranges + 1]
   int32_t* hot_off = nullptr;        // [ranges + 1]
+  unsigned long long* queue = nullptr;  // wave kernel tile queues: [ranges][kQueueStride]
   // PageRank state
   uint32_t* dmask = nullptr;
   void* ybuf[2] = {nullptr, nullptr};

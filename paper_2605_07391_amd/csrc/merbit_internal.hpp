@@ -201,7 +201,18 @@ struct SpmvArgs {
   int32_t ranges;
   const int32_t* range_tile;
   const int32_t* hot_off;
+  // wave kernel: per range, two counters kQueueStride words apart from the
+  // next range's: [0] tiles taken beyond the first one of each wavefront, [1]
+  // wavefronts finished.  Zero before a launch; the launch's last wavefront of
+  // the range sets them back to zero.  nullptr: every wavefront takes a fixed
+  // arithmetic sequence of tiles.  (64-bit words: no other array the kernel
+  // reads has this type, so the compiler can still keep the tile bounds in
+  // scalar loads.)
+  unsigned long long* queue;
 };
+
+// words between two ranges' tile-queue counters (one 256-byte line each)
+constexpr int kQueueStride = 32;
 
 struct SpmmArgs {
   const int32_t* tile_x;

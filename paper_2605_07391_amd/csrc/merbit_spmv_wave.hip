@@ -63,14 +63,24 @@ constexpr int kPolicyStream = 2;
 // hot x values loaded per lane before they are stored to LDS
 constexpr int kHotBatch = 16;
 
+// A load through the constant address space: the tile bounds are never
+// written during a launch, and with the tile-queue atomics in the loop the
+// compiler could otherwise not prove that, and would load the (uniform) bounds
+// with vector loads that wait for every gather in flight.
+template <typename T>
+__device__ __forceinline__ T const_load(const T* p, int i) {
+  typedef const __attribute__((address_space(4))) T ConstT;
+  return ((ConstT*)p)[i];
+}
+
 template <typename V, int SIGMA, typename D>
 __device__ __forceinline__ void wave_load_tile(const SpmvArgs& a, const int32_t* __restrict__ col,
                                                const V* __restrict__ val, int t, int lid,
                                                WaveTile<V, SIGMA, D>& s) {
-  s.x_ws = a.tile_x[t];
-  s.x_se = a.tile_x[t + 1] - s.x_ws;
-  s.tyw = a.tile_y[t];
-  s.y_we = (int)(a.tile_y[t + 1] & kRowMask);
+  s.x_ws = const_load(a.tile_x, t);
+  s.x_se = const_load(a.tile_x, t + 1) - s.x_ws;
+  s.tyw = const_load(a.tile_y, t);
+  s.y_we = (int)(const_load(a.tile_y, t + 1) & kRowMask);
   const bool normal = s.x_se > 0 && !(s.tyw & kFastBit);
   s.desc = 0;
   if (normal) s.desc = load_desc<D>(a, min(t * kOmega + lid, a.lane_num - 1));
@@ -140,8 +150,10 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
   // the plan splits the tiles into ranges)
   int t_begin = 0, t_end = a.tile_num, slot = blockIdx.x, slots = a.grid;
   int h_begin = 0, h_num = a.hot_n;
+  unsigned long long* queue = a.queue;
   if (a.ranges > 1) {
     const int k = blockIdx.x % a.ranges;
+    if (queue) queue += kQueueStride * k;
     t_begin = a.range_tile[k];
     t_end = a.range_tile[k + 1];
     slot = blockIdx.x / a.ranges;
@@ -183,10 +195,31 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
     __syncthreads();
   }
 
+  // Every wavefront of the range first takes one tile of the range's first
+  // slots * WAVES; further tiles come from the range's queue counter, one at a
+  // time, so wavefronts that meet cheap tiles take more of them (without a
+  // queue: the fixed sequence t + stride, t + 2 stride, ...).  The number of
+  // the tile after next is requested while the current tile is worked on and
+  // read at the end of it: the atomic's latency hides behind a tile, and
+  // waiting for it (memory returns in issue order) never waits for loads the
+  // next iteration does not need first anyway.
   const int stride = slots * WAVES;
+  auto take = [&]() -> int {
+    int q = 0;
+    if (lid == 0) q = (int)atomicAdd(queue, 1ull);
+    return q;
+  };
+  auto tile_of = [&](int q) -> int {
+    q = __builtin_amdgcn_readfirstlane(q);
+    return q < t_end - t_begin - stride ? t_begin + stride + q : t_end;
+  };
   int t = t_begin + slot * WAVES + wid;
+  int tn = t_end;
   WaveTile<V, SIGMA, D> cur;
-  if (t < t_end) wave_load_tile<V, SIGMA, D>(a, col, val, t, lid, cur);
+  if (t < t_end) {
+    wave_load_tile<V, SIGMA, D>(a, col, val, t, lid, cur);
+    tn = queue ? tile_of(take()) : t + stride;
+  }
   while (t < t_end) {
     // gathers of the current tile (none for a tile without nonzeros: x may be
     // empty then)
@@ -203,8 +236,10 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
         }
       }
     }
-    // loads of the next tile go out before the gathers are consumed
-    const int tn = t + stride;
+    // the tile after next, then the loads of the next tile: both go out
+    // before the gathers are consumed
+    int qn = 0;
+    if (queue && tn < t_end) qn = take();
     WaveTile<V, SIGMA, D> nxt;
     if (tn < t_end) wave_load_tile<V, SIGMA, D>(a, col, val, tn, lid, nxt);
 
@@ -277,6 +312,16 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
     if (tn >= t_end) break;
     cur = nxt;
     t = tn;
+    tn = queue ? tile_of(qn) : tn + stride;
+  }
+  // The range's last wavefront to finish sets its counters back to zero for
+  // the next launch: every other wavefront of the range has taken its last
+  // tile number (and waited for it) before it counts itself finished.
+  if (queue && lid == 0) {
+    if (atomicAdd(queue + 1, 1ull) == (unsigned long long)(stride - 1)) {
+      atomicExch(queue, 0ull);
+      atomicExch(queue + 1, 0ull);
+    }
   }
 }
 

@@ -375,3 +375,45 @@ def test_desc64_rmat22_full_size(dtype, sigma):
     rel = np.abs(x.double().cpu().numpy() - ref) / ref
     assert rel.max() <= (1e-4 if dtype == torch.float32 else 1e-11)
     plan.close()
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+@pytest.mark.parametrize("stripes", [0, 8])
+def test_wave_tile_queue_across_launches(stripes, dtype):
+    """The wave kernel deals each wavefront one tile and hands out the rest
+    from a per-range counter that the launch's last wavefront resets: with
+    several tiles per wavefront (R-MAT scale 17, sigma 4, 256 lanes, one block
+    per CU), consecutive launches, dual-buffer launches and a PageRank chain
+    in between must each produce the oracle's y."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    rp, col = graphgen.rmat_pattern(17, 16, seed=17)
+    nc = len(rp) - 1
+    vals = np.random.default_rng(17).uniform(-1, 1, len(col))
+    r, c, v = to_device(rp, col, vals, dtype, dev)
+    plan = pkg.Plan(r, c, v, nc, sigma=4, block_lanes=256, blocks_per_cu=1, commit="wave",
+                    stripes=stripes)
+    info = plan.info()
+    waves = info["grid"] * 4
+    assert info["tile_num"] > 4 * waves  # most tiles come from the queue
+    vals64 = host_values(vals, dtype)
+    for rep in range(4):
+        x64 = seeded_x(nc, 40 + rep, dtype)
+        x = torch.from_numpy(x64).to(dtype).to(dev)
+        y = torch.full((nc,), float("nan"), dtype=dtype, device=dev)
+        plan.spmv(x, out=y)
+        torch.cuda.synchronize()
+        check_spmv(y, rp, col, vals64, x64, dtype, f"S={stripes} launch {rep}")
+        if rep == 1:
+            xp = torch.full((nc,), 1.0 / nc, dtype=dtype, device=dev)
+            plan.pagerank(xp, 0.85, tol=0.0, max_iter=7)
+    if stripes == 0:
+        bufs = [torch.full((nc,), float("nan"), dtype=dtype, device=dev) for _ in range(2)]
+        plan.zero_boundary(bufs[0])
+        for it in range(3):
+            x64 = seeded_x(nc, 60 + it, dtype)
+            x = torch.from_numpy(x64).to(dtype).to(dev)
+            plan.spmv_dual(x, bufs[it % 2], bufs[(it + 1) % 2])
+            torch.cuda.synchronize()
+            check_spmv(bufs[it % 2], rp, col, vals64, x64, dtype, f"dual {it}")
+    plan.close()
