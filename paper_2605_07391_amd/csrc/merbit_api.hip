@@ -513,10 +513,13 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
     if (rc == MERBIT_OK) rc = build_hot_cache(p, hot_columns, st);
     if (rc == MERBIT_OK) rc = size_grid(p);
   }
-  if (rc == MERBIT_OK && p->commit == MERBIT_COMMIT_WAVE && p->tile_num > 0 && p->ranges > 1) {
+  if (rc == MERBIT_OK && p->commit == MERBIT_COMMIT_WAVE && p->tile_num > 0 && p->ranges > 1 &&
+      p->tile_num >= (int64_t)kQueueMinTilesPerWave * p->grid * p->waves) {
     // tile queues of the wave kernel, zero before the first launch.  Only with
     // ranges: one counter for a whole grid (4,096 wavefronts on R-MAT 22) is
-    // served one atomic at a time and made a plain plan's SpMV 4x slower.
+    // served one atomic at a time and made a plain plan's SpMV 4x slower; and
+    // only with several tiles per wavefront: on R-MAT 20 (about 6) the
+    // atomics cost more than the balance gains (78 against 71 us).
     const size_t qb = sizeof(unsigned long long) * kQueueStride * (size_t)p->ranges;
     hipError_t qe = hipMalloc(&p->queue, qb);
     if (qe == hipSuccess) qe = hipMemsetAsync(p->queue, 0, qb, st);

@@ -213,6 +213,8 @@ struct SpmvArgs {
 
 // words between two ranges' tile-queue counters (one 256-byte line each)
 constexpr int kQueueStride = 32;
+// tiles per wavefront below which a striped plan keeps the fixed tile sequence
+constexpr int kQueueMinTilesPerWave = 12;
 
 struct SpmmArgs {
   const int32_t* tile_x;

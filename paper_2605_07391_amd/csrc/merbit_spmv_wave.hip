@@ -60,8 +60,11 @@ constexpr bool kBufferStream = sizeof(V) == 4 || sizeof(D) == 8;
 constexpr int kBufferWord3 = 0x00020000;
 // cache policy bits of a gfx950 buffer load: nt (streaming, evicted first)
 constexpr int kPolicyStream = 2;
-// hot x values loaded per lane before they are stored to LDS
-constexpr int kHotBatch = 16;
+// hot x values loaded per lane before they are stored to LDS (128 bytes:
+// 16 -> 32 took FP32 sigma 28 from 226 to 224 us per SpMV; 64 FP64 values
+// spill in the 1,024-lane kernels)
+template <typename V>
+constexpr int kHotBatch = 128 / (int)sizeof(V);
 
 // A load through the constant address space: the tile bounds are never
 // written during a launch, and with the tile-queue atomics in the loop the
@@ -176,10 +179,10 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
     const __amdgpu_buffer_rsrc_t rh = __builtin_amdgcn_make_buffer_rsrc(
         (void*)(static_cast<const V*>(a.x_hot) + h_begin), (short)0, h_num * (int)sizeof(V),
         kBufferWord3);
-    for (int s0 = tid; s0 < h_num; s0 += kHotBatch * NT) {
-      V hv[kHotBatch];
+    for (int s0 = tid; s0 < h_num; s0 += kHotBatch<V> * NT) {
+      V hv[kHotBatch<V>];
 #pragma unroll
-      for (int u = 0; u < kHotBatch; ++u) {
+      for (int u = 0; u < kHotBatch<V>; ++u) {
         const int off = (s0 + u * NT) * (int)sizeof(V);
         if constexpr (sizeof(V) == 4)
           hv[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(rh, off, 0, 0));
@@ -187,7 +190,7 @@ __global__ __launch_bounds__(WAVES * 64) void spmv_wave_kernel(SpmvArgs a) {
           hv[u] = __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rh, off, 0, 0));
       }
 #pragma unroll
-      for (int u = 0; u < kHotBatch; ++u) {
+      for (int u = 0; u < kHotBatch<V>; ++u) {
         const int s = s0 + u * NT;
         if (s < h_num) dst[s] = hv[u];
       }
