@@ -16,10 +16,11 @@
 // A block of WAVES wavefronts is resident for the whole launch; wavefront g
 // of the grid takes tiles g, g + W_total, g + 2 W_total, ...  (with the tiles
 // split into ranges, the same within the block's range, over the blocks of
-// that range).  The loads of the
-// next tile (bounds, descriptor, col_ind, values) are issued before the
-// current tile's gathers are consumed, so memory stays busy while a tile is
-// walked and committed.
+// that range; with a tile queue, only the first tile is fixed and the rest of
+// the range is handed out one tile at a time).  The loads of the next tile
+// (bounds, descriptor, col_ind, values) are issued before the current tile's
+// gathers are consumed, so memory stays busy while a tile is walked and
+// committed.
 //
 // HOT: the block first copies the hot x values into LDS (the plan's recoded
 // column stream marks hot columns as -1 - slot) and serves those gathers from
