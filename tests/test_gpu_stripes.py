@@ -304,11 +304,14 @@ def test_striped_desc64(name, dtype, sigma, block_lanes):
     plan.close()
 
 
-@pytest.mark.parametrize("dtype,sigma", [(torch.float32, 24), (torch.float64, 16)],
-                         ids=["f32s24", "f64s16"])
+@pytest.mark.parametrize("dtype,sigma", [(torch.float32, 24), (torch.float32, 28),
+                                         (torch.float32, 32), (torch.float64, 16),
+                                         (torch.float64, 20)],
+                         ids=["f32s24", "f32s28", "f32s32", "f64s16", "f64s20"])
 def test_striped_desc64_rmat22_pagerank(dtype, sigma):
-    """The 64-bit-descriptor column-stripe configuration at full size:
-    20 PageRank iterations against the oracle."""
+    """The 64-bit-descriptor column-stripe configurations at full size (the
+    benchmark's autotuner picks among them; their tile queues are in use):
+    20 PageRank iterations, replayed from HIP graphs, against the oracle."""
     dev = require_gpu()
     w = workload("rmat22")
     n = w["n_rows"]
