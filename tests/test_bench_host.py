@@ -1,0 +1,61 @@
+"""Host logic of bench.py (no GPU): the one-GPU refusal, kernel-instance
+names, and the choice of the committed HBM-traffic record."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+
+
+def _info(sigma=32, dtype=0, desc_bits=64, commit=2, stripes=8, lanes=512, hot=1):
+    return {"sigma": sigma, "dtype": dtype, "desc_bits": desc_bits, "commit": commit,
+            "stripes": stripes, "block_lanes": lanes, "hot_columns": hot}
+
+
+def test_kernel_instance_names():
+    assert bench.kernel_instance(_info()) == \
+        "merbit::spmv_wave_kernel<float, 32, 8, true, unsigned long>"
+    assert bench.kernel_instance(_info(sigma=7, dtype=1, desc_bits=32, hot=0)) == \
+        "merbit::spmv_wave_kernel<double, 7, 8, false, unsigned int>"
+    assert bench.kernel_instance(_info(sigma=12, commit=1, desc_bits=32, lanes=256)) == \
+        "merbit::spmv_kernel<float, 12, 4, true>"
+
+
+def test_traffic_record_must_match_instance_stripes_and_source(tmp_path, monkeypatch):
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    info = _info()
+    good = {"kernel": bench.kernel_instance(info), "stripes": 8,
+            "spmv_source_sha256_16": bench.spmv_source_hash(2, 8), "hbm_bytes_per_launch": 123}
+    near = dict(good, kernel=bench.kernel_instance(_info(sigma=28)), hbm_bytes_per_launch=456)
+    stale = dict(good, spmv_source_sha256_16="0" * 16, hbm_bytes_per_launch=789)
+    (prof / "spmv_traffic_w_f32.json").write_text(json.dumps(good))
+    (prof / "spmv_traffic_w_f32_sigma28.json").write_text(json.dumps(near))
+    (prof / "spmv_traffic_v_f32.json").write_text(json.dumps(stale))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.load_traffic("w", "f32", info) == 123
+    assert bench.load_traffic("w", "f32", _info(sigma=28)) == 456
+    assert bench.load_traffic("w", "f32", _info(sigma=24)) is None   # no record
+    assert bench.load_traffic("w", "f32", _info(stripes=4)) is None  # other stripe count
+    assert bench.load_traffic("v", "f32", info) is None              # taken on other sources
+    assert bench.load_traffic("w", "f64", info) is None
+
+
+@pytest.mark.parametrize("vs", [4, 8])
+def test_algorithmic_bytes_cover_the_csr_arrays_and_vectors(vs):
+    info = {"nnz": 1000, "n_rows": 300, "n_cols": 200, "tile_num": 10, "lane_num": 640,
+            "fast_tiles": 2, "sigma": 2, "desc_bits": 32, "stripes": 1, "plan_rows": 300}
+    floor = (4 + vs) * 1000 + vs * (300 + 200)
+    assert bench.algorithmic_bytes(info, vs) >= floor
