@@ -204,10 +204,9 @@ struct SpmvArgs {
   // wave kernel: per range, two counters kQueueStride words apart from the
   // next range's: [0] tiles taken beyond the first one of each wavefront, [1]
   // wavefronts finished.  Zero before a launch; the launch's last wavefront of
-  // the range sets them back to zero.  nullptr: every wavefront takes a fixed
-  // arithmetic sequence of tiles.  (64-bit words: no other array the kernel
-  // reads has this type, so the compiler can still keep the tile bounds in
-  // scalar loads.)
+  // the range sets them back to zero.  nullptr (plans without ranges, or with
+  // fewer than kQueueMinTilesPerWave tiles per wavefront): every wavefront
+  // takes a fixed arithmetic sequence of tiles.
   unsigned long long* queue;
 };
 
