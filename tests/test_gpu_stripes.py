@@ -273,8 +273,9 @@ def test_striped_stress24_fp64_full_size():
     plan.close()
 
 
-DESC64 = [(torch.float32, 24, 512), (torch.float32, 16, 256), (torch.float64, 16, 512),
-          (torch.float64, 14, 256)]
+DESC64 = [(torch.float32, 24, 512), (torch.float32, 16, 256), (torch.float32, 28, 512),
+          (torch.float32, 32, 512), (torch.float64, 16, 512), (torch.float64, 14, 256),
+          (torch.float64, 20, 512)]
 
 
 @pytest.mark.parametrize("dtype,sigma,block_lanes", DESC64,
