@@ -121,7 +121,7 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
                                       hot_columns=hot_columns, block_lanes=[128, 256, 512, 1024])
             cands += cands_of(table_block, "block", 0, 32)
         best64, table64 = pkg.tune(r, c, v, n, reps=10, hot_columns=hot_columns, desc_bits=64,
-                                   block_lanes=[256, 512, 768])
+                                   block_lanes=[256, 512])
         if commit in ("auto", "wave"):
             cands += cands_of(table64, "wave", 0, 64)
         if commit in ("auto", "wave") and stripes < 0:
@@ -132,7 +132,7 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
                                         hot_columns=hot_columns, stripes=8)
             cands += cands_of(table_striped, "wave", 8, 32)
             _, table64s = pkg.tune(r, c, v, n, reps=10, hot_columns=hot_columns, desc_bits=64,
-                                   block_lanes=[256, 512, 768], stripes=8)
+                                   block_lanes=[256, 512], stripes=8)
             cands += cands_of(table64s, "wave", 8, 64)
         # the library default (sigma 12 / 7, 1024 / 512 lanes, wave commit, no
         # stripes, 32-bit descriptors) unless a candidate is more than 2 %

@@ -64,7 +64,7 @@ typedef struct {
                               2 ceil(log2(64 sigma)) + sigma <= 32: 1..12 are built     */
     int32_t block_lanes;   /* threads per block; 0 = WAVE: 1024 (FP32, 32-bit
                               descriptors) or 512, BLOCK: 256.  Built: BLOCK 128, 256,
-                              512, 1024; WAVE 256, 512, 1024 (64-bit: 256, 512, 768)   */
+                              512, 1024; WAVE 256, 512, 1024 (64-bit: 256, 512)        */
     int32_t commit;        /* merbit_commit                                            */
     int32_t hot_columns;   /* LDS x cache for the most frequent columns -- an addition
                               to the paper's method: on gfx950 scattered x gathers are
@@ -88,8 +88,7 @@ typedef struct {
     int32_t desc_bits;     /* lane descriptor width: 0 or 32 (sigma <= 12), or 64
                               (2 ceil(log2(64 sigma)) + sigma <= 64, sigma <= 40; wave
                               commit only; built: FP32 sigma 16, 20, 24, 28, 32, FP64
-                              14, 16, 20, 24, block_lanes 256 or 512; 768 lanes for FP32
-                              sigma 16-28 and FP64 14, 16).  SpMM and the
+                              14, 16, 20, 24, block_lanes 256 or 512).  SpMM and the
                               adjoint pieces need 32-bit plans.                         */
     int32_t stripes;       /* column stripes -- an addition to the paper's method for
                               gfx950's per-XCD caches: 0 or 1 = off; S = 2, 4, 8, 16 or

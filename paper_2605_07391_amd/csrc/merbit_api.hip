@@ -441,8 +441,8 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
                                    : !spmv_supported(dtype, sigma, waves, false))
     return fail(MERBIT_EUNSUPPORTED,
                 desc_bits == 64 ? (dtype == MERBIT_F32
-                                       ? "64-bit descriptors: sigma 16, 20, 24, 28 or 32, 256 or 512 lanes (768: sigma 16-28)"
-                                       : "64-bit descriptors: sigma 14, 16, 20 or 24, 256 or 512 lanes (768: sigma 14, 16)")
+                                       ? "64-bit descriptors: sigma 16, 20, 24, 28 or 32, 256 or 512 lanes"
+                                       : "64-bit descriptors: sigma 14, 16, 20 or 24, 256 or 512 lanes")
                 : commit == MERBIT_COMMIT_WAVE ? "block_lanes must be 256, 512 or 1024"
                                                : "block_lanes must be 128, 256, 512 or 1024");
   if (opts.blocks_per_cu < 0) return fail(MERBIT_EINVAL, "blocks_per_cu < 0");

@@ -363,7 +363,7 @@ static WaveEntry wave_pick_sigma(int sigma) {
 
 // 64-bit descriptors: longer lanes than 32 bits allow.  FP32: sigma 16, 20,
 // 24, 28, 32; FP64 (twice the registers per value): sigma 14, 16, 20, 24.  256 or
-// 512 lanes (768: below).
+// 512 lanes.
 template <typename V, int W, bool H>
 static WaveEntry wave_pick_sigma64(int sigma) {
   if constexpr (sizeof(V) == 4) {
@@ -380,25 +380,6 @@ static WaveEntry wave_pick_sigma64(int sigma) {
     }
   }
 }
-// 768 lanes (12 wavefronts, three per SIMD) with 64-bit descriptors: the sigma
-// whose kernels fit in the 168 VGPRs that allows, without spilling (FP32 16,
-// 20, 24, 28; FP64 14, 16).
-template <typename V, bool H>
-static WaveEntry wave_pick_sigma64_w12(int sigma) {
-  constexpr int W = 12;
-  if constexpr (sizeof(V) == 4) {
-    switch (sigma) {
-      MERBIT_WCASE(16, uint64_t) MERBIT_WCASE(20, uint64_t) MERBIT_WCASE(24, uint64_t)
-      MERBIT_WCASE(28, uint64_t)
-      default: return WaveEntry{nullptr, nullptr};
-    }
-  } else {
-    switch (sigma) {
-      MERBIT_WCASE(14, uint64_t) MERBIT_WCASE(16, uint64_t)
-      default: return WaveEntry{nullptr, nullptr};
-    }
-  }
-}
 #undef MERBIT_WCASE
 
 template <typename V, bool H>
@@ -407,7 +388,6 @@ static WaveEntry wave_pick_waves(int sigma, int waves, bool desc64) {
     switch (waves) {
       case 4: return wave_pick_sigma64<V, 4, H>(sigma);
       case 8: return wave_pick_sigma64<V, 8, H>(sigma);
-      case 12: return wave_pick_sigma64_w12<V, H>(sigma);
       default: return WaveEntry{nullptr, nullptr};
     }
   }

@@ -350,45 +350,6 @@ def test_desc64_plan_and_spmv(name, dtype, sigma, block_lanes, hot):
     plan.close()
 
 
-# 768 lanes (three wavefronts per SIMD) are built for these
-DESC64_768 = [(torch.float32, 16), (torch.float32, 20), (torch.float32, 24), (torch.float32, 28),
-              (torch.float64, 14), (torch.float64, 16)]
-
-
-@pytest.mark.parametrize("hot", [0, -1, 37])
-@pytest.mark.parametrize("dtype,sigma", DESC64_768,
-                         ids=[f"{'f32' if d == torch.float32 else 'f64'}s{s}" for d, s in DESC64_768])
-@pytest.mark.parametrize("name", ["one_row", "all_rows_empty", "single_long_row", "long_then_empty",
-                                  "random1_700x300", "chung_lu_10k", "fuzz2_3471x315", "one_column"])
-def test_desc64_768_lanes(name, dtype, sigma, hot):
-    """12-wavefront blocks of the 64-bit kernel: y = A x within the SpMV
-    tolerance (the plan does not depend on the block size)."""
-    import paper_2605_07391_amd as pkg
-    dev = require_gpu()
-    rp, col, vals, nc = _matrix(name, seed=sigma + 1)
-    r, c, v = to_device(rp, col, vals, dtype, dev)
-    plan = pkg.Plan(r, c, v, nc, sigma=sigma, block_lanes=768, hot_columns=hot, desc_bits=64)
-    info = plan.info()
-    assert info["block_lanes"] == 768 and info["desc_bits"] == 64
-    x64 = seeded_x(nc, sigma + 1, dtype)
-    for rep in range(2):
-        y = torch.full((len(rp) - 1,), float("nan"), dtype=dtype, device=dev)
-        plan.spmv(torch.from_numpy(x64).to(dtype).to(dev), out=y)
-        torch.cuda.synchronize()
-        check_spmv(y, rp, col, host_values(vals, dtype), x64, dtype, f"{name} 768 s{sigma}")
-    plan.close()
-
-
-def test_desc64_768_lanes_only_where_built():
-    import paper_2605_07391_amd as pkg
-    dev = require_gpu()
-    rp, col, vals, nc = _matrix("random1_700x300")
-    for dtype, sigma in [(torch.float32, 32), (torch.float64, 20), (torch.float64, 24)]:
-        r, c, v = to_device(rp, col, vals, dtype, dev)
-        with pytest.raises(pkg.MerbitError):
-            pkg.Plan(r, c, v, nc, sigma=sigma, block_lanes=768, desc_bits=64)
-
-
 @pytest.mark.parametrize("dtype,sigma", [(torch.float32, 24), (torch.float64, 16)],
                          ids=["f32s24", "f64s16"])
 def test_desc64_rmat22_full_size(dtype, sigma):
