@@ -105,9 +105,14 @@ typedef struct {
                               in stacked order (values: re-copied by
                               merbit_plan_set_values, so in-place changes of the
                               array need that call) and two y' buffers [rows of A'].
-                              Needs nnz < 2^30.  SpMM, personalised / multi-graph
-                              PageRank, transpose, SDDMM and the adjoint return
-                              MERBIT_EUNSUPPORTED on such a plan.                       */
+                              With at least 12 tiles per wavefront the plan also owns
+                              one small tile-queue line per range (each launch resets
+                              it; two launches on one plan at once race, as every
+                              other plan state does).  Needs nnz < 2^30.  SpMM (and
+                              its dual / boundary calls), personalised PageRank,
+                              transpose and SDDMM return MERBIT_EUNSUPPORTED on such a
+                              plan; SpMV, PageRank, multi-graph PageRank, BiCGSTAB and
+                              the adjoint fixed point run on it.                        */
 } merbit_opts_t;
 
 typedef struct merbit_plan merbit_plan;
