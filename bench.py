@@ -51,12 +51,22 @@ def spmv_source_hash(commit: int, stripes: int = 1) -> str:
 def algorithmic_bytes(info: dict, value_size: int) -> float:
     """Bytes one SpMV must move: values + col_ind once, x once, y once, the
     tile starts and the descriptors of the non-fast tiles (paper Sec. 4.3's
-    TILE footprint)."""
+    TILE footprint), each descriptor at its own width (4 or 8 bytes)."""
     m, n_rows, n_cols = info["nnz"], info["n_rows"], info["n_cols"]
     T, lanes = info["tile_num"], info["lane_num"]
     r_f = info["fast_tiles"] / T if T else 0.0
+    desc_bytes = info.get("desc_bits", 32) // 8
     return (m * (value_size + 4) + n_cols * value_size + n_rows * value_size + 8 * (T + 1)
-            + 4 * lanes * (1.0 - r_f))
+            + desc_bytes * lanes * (1.0 - r_f))
+
+
+def timed_prep_calls(steps: int) -> int:
+    """Untimed PageRank calls of exactly the timed call's shape (max_iter =
+    steps) run before the clock starts.  Each call records the HIP graphs of
+    its chunks for the dual-buffer state it starts from; a call of odd length
+    flips that state, so the second call puts it back and the timed call
+    starts from a state whose graphs exist, whatever the warm-up did."""
+    return 1 + (steps & 1)
 
 
 def kernel_instance(info: dict) -> str:
@@ -179,14 +189,24 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
         x = torch.full((n,), 1.0 / n, dtype=dtype, device=dev)
         if warmup > 0:
             plan.pagerank(x, alpha, tol=0.0, max_iter=warmup)
+        # the timed call's own chunk shape, untimed: its HIP graphs are
+        # recorded before t0 whatever --warmup was
+        for _ in range(timed_prep_calls(steps)):
+            x.fill_(1.0 / n)
+            plan.pagerank(x, alpha, tol=0.0, max_iter=steps)
         x.fill_(1.0 / n)
         torch.cuda.synchronize()
+        g_before = plan.info()
         wall0 = time.perf_counter()
         t0.record()
         iters, resid, _ = plan.pagerank(x, alpha, tol=0.0, max_iter=steps)
         t1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
+        g_after = plan.info()
+        graphs = {"captured_in_timed_call": g_after["graph_captures"] - g_before["graph_captures"],
+                  "replayed_in_timed_call": g_after["graph_replays"] - g_before["graph_replays"],
+                  "prep_calls": timed_prep_calls(steps)}
         mass = float(x.double().sum().item())
         # roofline pass: `steps` standalone SpMVs y = A x on the ranks just
         # computed (the same launches as in a PageRank step), each bracketed
@@ -214,6 +234,7 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
         torch.cuda.synchronize()
         wall = time.perf_counter() - wall0
         iters, resid, mass = steps, None, None
+        graphs = None
         plan.profile_enable(True)
         base += steps
         for k in range(steps):
@@ -229,7 +250,7 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
     return {
         "iters": iters, "resid": resid, "mass": mass, "step_ms": step_ms, "wall_s": wall,
         "plan_ms": plan_ms, "spmv_ms": spmv_ms, "launches": launches, "info": info,
-        "tuning": tuning,
+        "tuning": tuning, "graphs": graphs,
         "alg_bytes": abytes, "achieved_gbs": achieved,
         "value_gnzs": nnz * steps / (step_ms * steps * 1e-3) / 1e9,
         "spmv_gnzs": nnz / (spmv_ms * 1e-3) / 1e9,
@@ -448,6 +469,99 @@ def run_adjoint(scale: int, iters: int, alpha: float, stripes: int = 0):
             "stripes": stripes, "seeds": {"graph": scale, "w": 5, "target": 6}}
 
 
+def run_c1(steps: int, alpha: float):
+    """PageRank on the 10,000-vertex Chung-Lu graph (FP32, 20 power
+    iterations per call, x0 = 1/n; paper Sec. 5.5.1): the matrix is cache
+    resident, so this reports time per iteration and per 20-iteration call
+    (HIP graphs recorded before the clock), not a bandwidth fraction."""
+    import torch
+
+    import graphgen
+    import paper_2605_07391_amd as pkg
+    dev = torch.device("cuda:0")
+    w = graphgen.workload("chung_lu_10k")
+    n = w["n_rows"]
+    r = torch.from_numpy(w["row_ptr"]).to(dev)
+    c = torch.from_numpy(w["col"]).to(dev)
+    v = torch.from_numpy(w["values"]).float().to(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    plan = pkg.Plan(r, c, v, n, validate=False)
+    e1.record()
+    torch.cuda.synchronize()
+    plan_ms = e0.elapsed_time(e1)
+    x = torch.empty(n, dtype=torch.float32, device=dev)
+    iters = 20
+    for _ in range(2):  # records the graphs of the timed call's chunks
+        x.fill_(1.0 / n)
+        plan.pagerank(x, alpha, tol=0.0, max_iter=iters)
+    calls = max(1, steps)
+    times = []
+    g0 = plan.info()
+    for _ in range(calls):
+        x.fill_(1.0 / n)
+        torch.cuda.synchronize()
+        e0.record()
+        plan.pagerank(x, alpha, tol=0.0, max_iter=iters)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    g1 = plan.info()
+    mass = float(x.double().sum().item())
+    x.fill_(1.0 / n)
+    plan.profile_enable(True)
+    plan.pagerank(x, alpha, tol=0.0, max_iter=iters)
+    launches, kernel_ms = plan.profile_read()
+    info = plan.info()
+    plan.close()
+    times.sort()
+    med = times[len(times) // 2]
+    return {"workload": "chung_lu_10k_pagerank", "dtype": "f32", "n": n, "nnz": int(w["nnz"]),
+            "iterations_per_call": iters, "calls_timed": calls,
+            "call_ms_median": round(med, 4), "call_ms_min": round(times[0], 4),
+            "us_per_iteration": round(med * 1e3 / iters, 2),
+            "spmv_us": round(kernel_ms * 1e3 / max(launches, 1), 2),
+            "plan_ms": round(plan_ms, 3), "sigma": info["sigma"],
+            "block_lanes": info["block_lanes"], "rank_mass": round(mass, 7),
+            "graph_replays_in_timed_calls": g1["graph_replays"] - g0["graph_replays"],
+            "graph_captures_in_timed_calls": g1["graph_captures"] - g0["graph_captures"],
+            "seed": w["meta"]["seed"]}
+
+
+# the FP64 stress matrix is measured at one fixed configuration (the one its
+# full-size parity test checks): 64-bit descriptors, sigma 20, 512 lanes,
+# 8 column stripes
+STRESS_CONFIG = {"sigma": 20, "block_lanes": 512, "desc_bits": 64, "stripes": 8}
+
+
+def run_stress(steps: int, warmup: int):
+    """y = A x on the FP64 stress matrix (R-MAT scale 24, 30 % of rows empty,
+    8 hub rows of 2,000,000 nonzeros; x in [-1, 1)): mean SpMV time from HIP
+    events around every fused launch, against its algorithmic bytes."""
+    import graphgen
+    w = graphgen.workload("stress24")
+    cfg = STRESS_CONFIG
+    res = run_gpu(w, "f64", steps, warmup, cfg["sigma"], cfg["block_lanes"], 0.85, -1, "wave",
+                  0, False, cfg["stripes"], cfg["desc_bits"])
+    info = res["info"]
+    ach = res["achieved_gbs"]
+    return {"workload": "stress24_spmv", "dtype": "f64", "n": info["n_rows"],
+            "nnz": info["nnz"], "steps": steps, "spmv_us": round(res["spmv_ms"] * 1e3, 2),
+            "ms_per_step": round(res["step_ms"], 5), "spmv_gnzs": round(res["spmv_gnzs"], 3),
+            "plan_ms": round(res["plan_ms"], 3), "plan": dict(cfg),
+            "hot_columns": info["hot_columns"], "hot_coverage": round(info["hot_coverage"], 4),
+            "fast_tile_fraction": round(info["fast_tiles"] / max(info["tile_num"], 1), 4),
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "traffic": load_traffic("stress24", "f64", info),
+                         "kernel": kernel_instance(info)
+                         + f" + merbit::stripe_combine_kernel<double, {info['stripes']}>",
+                         "alg_bytes_per_launch": int(res["alg_bytes"]),
+                         "mean_launch_us": round(res["spmv_ms"] * 1e3, 2),
+                         "launches_timed": res["launches"]},
+            "seeds": {"graph": w["meta"]["seed"], "x": w["meta"]["x_seed"]}}
+
+
 def cpu_baseline(w, iters: int, alpha: float, dtype_name: str = "f32"):
     import numpy as np
 
@@ -462,15 +576,31 @@ def cpu_baseline(w, iters: int, alpha: float, dtype_name: str = "f32"):
                 "kind": "oracle",
                 "sample": f"{iters} SpMVs of the full workload matrix "
                           f"(single-threaded C, long-double sums), {dt:.1f} s"}
+    from oracle import cpu_baseline as cb
     vals = w["values"].astype(np.float32).astype(np.float64)
     x0 = np.full(n, np.float32(1.0 / n), np.float64)
     t = time.perf_counter()
     oracle.pagerank(w["row_ptr"], w["col"], vals, alpha, iters, x0)
     dt = time.perf_counter() - t
+    # the timed variants: plain double sums, one thread and then every thread
+    # OpenMP gives this process
+    rows = []
+    for threads in (1, 0):
+        t = time.perf_counter()
+        _, used = cb.pagerank(w["row_ptr"], w["col"], vals, alpha, iters, x0, threads)
+        dtv = time.perf_counter() - t
+        rows.append({"value": round(w["nnz"] * iters / dtv / 1e9, 5), "unit": "GNZ/s",
+                     "cores": used, "kind": "plain_f64" + ("_openmp" if used > 1 else ""),
+                     "sample": f"{iters} PageRank iterations of the full workload matrix "
+                               f"({used} thread{'s' if used > 1 else ''}, double sums), "
+                               f"{dtv:.2f} s"})
     return {"value": round(w["nnz"] * iters / dt / 1e9, 5), "unit": "GNZ/s", "cores": 1,
             "kind": "oracle",
             "sample": f"{iters} PageRank iterations of the full workload matrix "
-                      f"(single-threaded C, long-double sums), {dt:.1f} s"}
+                      f"(single-threaded C, long-double sums), {dt:.1f} s",
+            "rows": rows, "cpu_model": cb.cpu_model(), "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def main():
@@ -505,6 +635,10 @@ def main():
     ap.add_argument("--no-bicgstab", action="store_true",
                     help="skip the BiCGSTAB run on the symmetric 0/1 R-MAT system")
     ap.add_argument("--bicgstab-scale", type=int, default=21)
+    ap.add_argument("--no-c1", action="store_true",
+                    help="skip the 10,000-vertex Chung-Lu PageRank timing")
+    ap.add_argument("--no-stress", action="store_true",
+                    help="skip the FP64 stress-matrix SpMV (R-MAT scale 24 with hub rows)")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default sigma / block size instead of the autotuner")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -557,6 +691,7 @@ def main():
             "stripes": r64["info"]["stripes"], "desc_bits": r64["info"]["desc_bits"],
             "block_lanes": r64["info"]["block_lanes"],
             "commit": {1: "block", 2: "wave"}[r64["info"]["commit"]], "tuning": r64["tuning"],
+            "alg_bytes_per_launch": int(r64["alg_bytes"]), "timed_graphs": r64["graphs"],
         }
         print(f"[bench] f64: step {r64['step_ms'] * 1e3:.1f} us, spmv "
               f"{r64['spmv_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
@@ -594,6 +729,17 @@ def main():
         bicg["one_plan_without_stripes"] = {k: bicg_plain[k] for k in
                                             ("ms_per_iteration", "spmv_us", "spmv_share", "gnzs")}
         print(f"[bench] bicgstab: {bicg['ms_per_iteration']:.3f} ms / iteration", file=sys.stderr,
+              flush=True)
+    c1 = None
+    if not args.no_c1 and w["meta"]["generator"] == "rmat":
+        c1 = run_c1(5, args.alpha)
+        print(f"[bench] chung_lu_10k: {c1['us_per_iteration']:.1f} us / iteration",
+              file=sys.stderr, flush=True)
+    stress = None
+    if not args.no_stress and w["meta"]["generator"] == "rmat":
+        stress = run_stress(args.steps, args.warmup)
+        print(f"[bench] stress24 f64: spmv {stress['spmv_us']:.1f} us "
+              f"({100 * stress['roofline']['frac']:.1f} % of 8 TB/s)", file=sys.stderr,
               flush=True)
     cpu = None
     if not args.no_cpu_baseline:
@@ -644,11 +790,14 @@ def main():
         "plan_ms": round(main_run["plan_ms"], 3),
         "fast_tile_fraction": round(info["fast_tiles"] / max(info["tile_num"], 1), 4),
         "rank_mass": None if main_run["mass"] is None else round(main_run["mass"], 7),
+        "timed_graphs": main_run["graphs"],
         "tuning": main_run["tuning"],
         "f64": extra,
         "batched": batched,
         "bicgstab": bicg,
         "adjoint": adj,
+        "chung_lu_10k": c1,
+        "stress24_f64": stress,
     }
     print(json.dumps(out), flush=True)
 

@@ -145,6 +145,8 @@ typedef struct {
     int64_t plan_rows;     /* rows of the planned matrix: n_rows, or the (stripe, row)
                               pairs of a striped plan; TILE and the exported arrays
                               are those of that matrix                                 */
+    int64_t graph_captures; /* iteration chunks recorded into HIP graphs so far         */
+    int64_t graph_replays;  /* iteration chunks run by replaying a recorded graph       */
 } merbit_plan_info_t;
 
 /* Fill *opts (host pointer) with the defaults. */

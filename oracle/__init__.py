@@ -60,11 +60,14 @@ _f64 = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
 
 
 def build() -> str:
-    """Compile the oracle with gcc (single threaded, -O2)."""
+    """Compile the oracle with gcc (single threaded, -O2), and the benchmark's
+    timed CPU baseline beside it (``cpu_baseline.c``, OpenMP)."""
     tmp = _LIB + ".tmp"
     subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC,
                     "-lm"], check=True)
     os.replace(tmp, _LIB)
+    from . import cpu_baseline
+    cpu_baseline.build()
     return _LIB
 
 

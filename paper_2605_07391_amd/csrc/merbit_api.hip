@@ -571,6 +571,8 @@ int merbit_plan_info(merbit_plan* p, merbit_plan_info_t* info) {
   info->stripes = p->stripes;
   info->ranges = p->ranges;
   info->plan_rows = p->plan_rows;
+  info->graph_captures = p->graph_captures;
+  info->graph_replays = p->graph_replays;
   if (p->tile_num > 0) {
     hipStream_t st = p->last_stream;
     unsigned long long cnt = 0;

@@ -106,6 +106,7 @@ struct merbit_plan {
     hipGraphExec_t exec;
   };
   std::vector<LoopGraph> loop_graphs;
+  int64_t graph_captures = 0, graph_replays = 0;
   // kernel timing
   bool profiling = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -171,6 +172,7 @@ int run_chunk(merbit_plan* p, int kind, int parity, int ybuf, int len, int k,
         g.sp_in == p->yv_cur) {
       HIP_TRY(hipGraphLaunch(g.exec, st));
       p->yv_cur = g.sp_out;  // the replay used the buffers the capture did
+      ++p->graph_replays;
       return MERBIT_OK;
     }
   const int sp_in = p->yv_cur;
@@ -195,6 +197,7 @@ int run_chunk(merbit_plan* p, int kind, int parity, int ybuf, int len, int k,
   }
   p->loop_graphs.push_back(
       {kind, parity, ybuf, len, k, sp_in, p->yv_cur, x, aux, alpha, p->generation, exec});
+  ++p->graph_captures;
   HIP_TRY(hipGraphLaunch(exec, st));
   return MERBIT_OK;
 }

@@ -44,7 +44,8 @@ class PlanInfo(ctypes.Structure):
                 ("lds_bytes", ctypes.c_int32), ("commit", ctypes.c_int32),
                 ("hot_coverage", ctypes.c_double), ("desc_bits", ctypes.c_int32),
                 ("stripes", ctypes.c_int32), ("ranges", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("plan_rows", ctypes.c_int64)]
+                ("reserved", ctypes.c_int32), ("plan_rows", ctypes.c_int64),
+                ("graph_captures", ctypes.c_int64), ("graph_replays", ctypes.c_int64)]
 
 
 class Opts(ctypes.Structure):

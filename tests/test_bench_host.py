@@ -59,3 +59,45 @@ def test_algorithmic_bytes_cover_the_csr_arrays_and_vectors(vs):
             "fast_tiles": 2, "sigma": 2, "desc_bits": 32, "stripes": 1, "plan_rows": 300}
     floor = (4 + vs) * 1000 + vs * (300 + 200)
     assert bench.algorithmic_bytes(info, vs) >= floor
+
+
+def test_descriptor_bytes_follow_the_descriptor_width():
+    info = {"nnz": 1000, "n_rows": 300, "n_cols": 200, "tile_num": 10, "lane_num": 640,
+            "fast_tiles": 2, "desc_bits": 32}
+    b32 = bench.algorithmic_bytes(info, 4)
+    b64 = bench.algorithmic_bytes(dict(info, desc_bits=64), 4)
+    assert b64 - b32 == pytest.approx(4 * 640 * (1 - 2 / 10))
+
+
+def _pagerank_chunk_keys(buf, stacked, steps, check_every=10):
+    """The HIP-graph keys one merbit_pagerank call looks up, as its host loop
+    forms them: full chunks of check_every iterations are keyed by (parity of
+    the chunk's first iteration, output buffer holding zeros at the boundary
+    rows, first chunk of the call or not, stacked-buffer parity); a shorter
+    last chunk runs without a graph.  Both buffer states flip once per
+    iteration.  Returns (keys, buf, stacked) after the call."""
+    keys, t = [], 0
+    while t < steps:
+        ln = min(check_every - t % check_every, steps - t)
+        if ln == check_every:
+            keys.append((t & 1, buf, int(t == 0), stacked))
+        t += ln
+        buf ^= ln & 1
+        stacked ^= ln & 1
+    return keys, buf, stacked
+
+
+@pytest.mark.parametrize("warmup", [0, 5, 20, 33])
+@pytest.mark.parametrize("steps", [10, 20, 25, 100, 7])
+def test_timed_pagerank_call_replays_recorded_graphs(warmup, steps):
+    recorded = set()
+    buf, stacked = 0, 0
+    if warmup:
+        keys, buf, stacked = _pagerank_chunk_keys(buf, stacked, warmup)
+        recorded.update(keys)
+    for _ in range(bench.timed_prep_calls(steps)):
+        keys, buf, stacked = _pagerank_chunk_keys(buf, stacked, steps)
+        recorded.update(keys)
+    timed, _, _ = _pagerank_chunk_keys(buf, stacked, steps)
+    assert set(timed) <= recorded
+    assert len(recorded) <= 8  # the plan keeps eight graphs

@@ -273,6 +273,39 @@ def test_striped_stress24_fp64_full_size():
     plan.close()
 
 
+def test_striped_stress24_fp64_bench_configuration():
+    """The FP64 stress matrix at exactly the configuration the benchmark
+    times (64-bit descriptors, sigma 20, 512 lanes, 8 stripes; its long hub
+    rows span thousands of tiles): every row within 1e-12 of |A||x|, for a
+    standalone SpMV and for a chain of dual-buffer launches (the benchmark's
+    timed form, whose tile queues reset between launches)."""
+    import bench
+    dev = require_gpu()
+    w = workload("stress24")
+    rp, col, vals, n = w["row_ptr"], w["col"], w["values"], w["n_rows"]
+    cfg = bench.STRESS_CONFIG
+    plan, keep = _plan(rp, col, vals, n, torch.float64, dev, sigma=cfg["sigma"],
+                       block_lanes=cfg["block_lanes"], desc_bits=cfg["desc_bits"],
+                       stripes=cfg["stripes"])
+    info = plan.info()
+    assert (info["sigma"], info["desc_bits"], info["stripes"], info["ranges"]) == \
+        (cfg["sigma"], cfg["desc_bits"], cfg["stripes"], 8)
+    assert info["fast_tiles"] > 0
+    vals64 = np.asarray(vals, np.float64)
+    x = torch.from_numpy(w["x"]).to(dev)
+    y = torch.full((n,), float("nan"), dtype=torch.float64, device=dev)
+    plan.spmv(x, out=y)
+    torch.cuda.synchronize()
+    check_spmv(y, rp, col, vals64, w["x"], torch.float64, "stress24 bench config")
+    ys = [torch.empty(n, dtype=torch.float64, device=dev) for _ in range(2)]
+    plan.zero_boundary(ys[0])
+    for k in range(3):
+        plan.spmv_dual(x, ys[k % 2], ys[(k + 1) % 2])
+    torch.cuda.synchronize()
+    check_spmv(ys[0], rp, col, vals64, w["x"], torch.float64, "stress24 dual chain")
+    plan.close()
+
+
 DESC64 = [(torch.float32, 24, 512), (torch.float32, 16, 256), (torch.float32, 28, 512),
           (torch.float32, 32, 512), (torch.float64, 16, 512), (torch.float64, 14, 256),
           (torch.float64, 20, 512)]
@@ -325,4 +358,36 @@ def test_striped_desc64_rmat22_pagerank(dtype, sigma):
                                 20, x0.astype(np.float64))
     rel = np.abs(x.double().cpu().numpy() - ref) / ref
     assert iters == 20 and rel.max() <= PR_TOL[dtype], rel.max()
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype,sigma", [(torch.float32, 32), (torch.float32, 28),
+                                         (torch.float64, 20), (torch.float64, 16)],
+                         ids=["f32s32", "f32s28", "f64s20", "f64s16"])
+def test_striped_desc64_rmat22_mixed_sign_spmv(dtype, sigma):
+    """The benchmark's tuned R-MAT 22 configurations (64-bit descriptors,
+    512 lanes, 8 stripes, the tile queue in use) on a mixed-sign x: one
+    standalone SpMV and a dual-buffer chain, every row within the SpMV
+    tolerance of |A||x|."""
+    dev = require_gpu()
+    w = workload("rmat22")
+    rp, col, vals, n = w["row_ptr"], w["col"], w["values"], w["n_rows"]
+    plan, keep = _plan(rp, col, vals, n, dtype, dev, sigma=sigma, block_lanes=512,
+                       desc_bits=64, stripes=8)
+    info = plan.info()
+    waves = info["grid"] * info["block_lanes"] // OMEGA
+    assert info["tile_num"] >= 12 * waves  # the tile queue's threshold
+    x64 = seeded_x(n, 7 + sigma, dtype)
+    x = torch.from_numpy(x64).to(dtype).to(dev)
+    vh = host_values(vals, dtype)
+    y = torch.full((n,), float("nan"), dtype=dtype, device=dev)
+    plan.spmv(x, out=y)
+    torch.cuda.synchronize()
+    check_spmv(y, rp, col, vh, x64, dtype, f"rmat22 s{sigma} mixed sign")
+    ys = [torch.empty(n, dtype=dtype, device=dev) for _ in range(2)]
+    plan.zero_boundary(ys[0])
+    for k in range(4):
+        plan.spmv_dual(x, ys[k % 2], ys[(k + 1) % 2])
+    torch.cuda.synchronize()
+    check_spmv(ys[1], rp, col, vh, x64, dtype, f"rmat22 s{sigma} dual chain")
     plan.close()
