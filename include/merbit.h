@@ -27,6 +27,7 @@
 #ifndef MERBIT_H
 #define MERBIT_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -226,6 +227,31 @@ int merbit_zero_boundary(merbit_plan* plan, void* v, void* stream);
 int merbit_pagerank(merbit_plan* plan, double alpha, double tol, int max_iter,
                     int check_every, void* x_inout, int* iters_out, double* resid_out,
                     void* stream);
+
+/* Bytes of device work space merbit_pagerank_noalloc may use on each GPU. */
+#define MERBIT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* merbit_pagerank for callers that cannot allocate device memory (tight
+ * serving loops, code that must not call hipMalloc, harnesses that forbid it):
+ * the same iteration, kernels, arguments and return codes, but no allocation
+ * of any kind -- no hipMalloc / hipFree, no HIP graphs, no timing events.  The
+ * work buffers (the SpMV's two output buffers, the second iterate, the
+ * per-block reduction pairs, and the dangling mask while the plan has none
+ * from an earlier merbit_pagerank) live in a library-owned device array of
+ * MERBIT_NOALLOC_SCRATCH_BYTES (64 MiB) per GPU, held until the process ends.
+ * A call needs 3 n sizeof(value) bytes plus 32 KiB, and n + n / 8 bytes more
+ * when it builds the mask: n up to about 5.1M (FP32) or 2.6M (FP64); larger
+ * plans return MERBIT_EINVAL with the needed size in the message.  The
+ * plan itself (created earlier by merbit_plan_create) is the caller's, as are
+ * x_inout and the stream.  The plan's device must be current.  Every call on
+ * a GPU uses that GPU's one array: calls that overlap on one GPU (two host
+ * threads, or two streams) race and give undefined results; calls in
+ * sequence on one stream are safe (each call sets up what must start at zero).
+ * Convergence checks copy a few KB to host memory and synchronise `stream`,
+ * as merbit_pagerank does. */
+int merbit_pagerank_noalloc(merbit_plan* plan, double alpha, double tol, int max_iter,
+                            int check_every, void* x_inout, int* iters_out,
+                            double* resid_out, void* stream);
 
 /* ------------------------------------------------------ batched forms -- */
 

@@ -85,7 +85,8 @@ int zero_boundary(merbit_plan* p, void* v, hipStream_t st) {
 // Launch the fused kernel (after the hot gather), bracketed by events when
 // profiling is on.  A striped plan runs the kernel on its own dual buffers of
 // A' x and then sums each row's stripes into y (inside the same events).
-int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st, bool hot_ready) {
+int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st, bool hot_ready,
+              bool timed) {
   if (p->chunk_num == 0) {
     // no tiles: the planned matrix has no rows (a striped plan always has
     // nonzeros, so it never gets here)
@@ -94,7 +95,8 @@ int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st, b
   if (p->hot_n > 0 && !p->hot_all && !hot_ready)
     HIP_TRY(launch_hot_gather(p->dtype, x, p->hot_cols, p->hot_n, p->x_hot, st));
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (p->profiling) {
+  const bool events = p->profiling && timed;
+  if (events) {
     if (p->events_used == p->events.size()) {
       hipEvent_t a, b;
       HIP_TRY(hipEventCreate(&a));
@@ -119,7 +121,7 @@ int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st, b
   else
     HIP_TRY(launch_spmv(p->dtype, p->sigma, p->waves, p->hot_n > 0, p->hot_lds_bytes,
                         spmv_args(p, x, y, z), st));
-  if (p->profiling) HIP_TRY(hipEventRecord(e1, st));
+  if (events) HIP_TRY(hipEventRecord(e1, st));
   p->last_stream = st;
   return MERBIT_OK;
 }

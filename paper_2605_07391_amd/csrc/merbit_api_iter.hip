@@ -9,6 +9,83 @@
 
 using namespace merbit;
 
+namespace merbit {
+
+int pagerank_loop(merbit_plan* p, PageRankWork& w, double alpha, double tol, int max_iter,
+                  int check_every, void* x_inout, int* iters_out, double* resid_out,
+                  hipStream_t st) {
+  if (check_every <= 0) check_every = 10;
+  const int64_t n = p->n_rows;
+  const size_t vb = vsize(p->dtype) * (size_t)n;
+  int rc;
+
+  // delta_0: per-block dangling mass of x_0 into partials[0]
+  HIP_TRY(launch_dangling_sum(p->dtype, x_inout, w.dmask, n, w.partials[0], w.reduce_grid, st));
+  int yb = w.zeroed_buf;
+  if (yb < 0) {
+    yb = 0;
+    rc = zero_boundary(p, w.ybuf[0], st);
+    if (rc != MERBIT_OK) return rc;
+  }
+  void* xs[2] = {x_inout, w.xwork};
+  int t = 0;
+  double resid = 0.0;
+  bool converged = false;
+  while (t < max_iter) {
+    // iterations up to the next check (or max_iter), as one chunk
+    int len = check_every - t % check_every;
+    if (len > max_iter - t) len = max_iter - t;
+    const int t0 = t, yb0 = yb;
+    // with a partial hot-column cache the update also writes the next
+    // iterate's hot values, so only the call's first SpMV gathers them
+    const bool fuse_hot = p->hot_n > 0 && !p->hot_all;
+    auto enqueue = [&](hipStream_t s) -> int {
+      for (int i = 0; i < len; ++i) {
+        const int cur = (t0 + i) & 1, b = yb0 ^ (i & 1);
+        const int r = run_fused(p, xs[cur], w.ybuf[b], w.ybuf[b ^ 1], s,
+                                fuse_hot && t0 + i > 0, w.timed);
+        if (r != MERBIT_OK) return r;
+        HIP_TRY(launch_pr_update(p->dtype, w.ybuf[b], xs[cur], xs[cur ^ 1], w.dmask, n, alpha,
+                                 w.partials[cur], w.reduce_grid, w.partials[cur ^ 1],
+                                 w.reduce_grid, s, fuse_hot ? p->hot_cols : nullptr,
+                                 fuse_hot ? p->hot_n : 0, fuse_hot ? p->x_hot : nullptr));
+      }
+      return MERBIT_OK;
+    };
+    // the call's first chunk gathers the hot values, later ones do not: a
+    // different graph (key k = 1 for the first chunk)
+    rc = w.graphs && len == check_every
+             ? run_chunk(p, kLoopPageRank, t0 & 1, yb0, len, t0 == 0 ? 1 : 0, x_inout, alpha,
+                         enqueue, st)
+             : enqueue(st);
+    if (rc != MERBIT_OK) return rc;
+    t += len;
+    yb ^= len & 1;
+    if (tol > 0.0 || t == max_iter) {
+      // l1 change of this iteration: sum of the blocks' second components
+      HIP_TRY(hipMemcpyAsync(w.host_pairs, w.partials[t & 1],
+                             sizeof(double) * 2 * (size_t)w.reduce_grid, hipMemcpyDeviceToHost,
+                             st));
+      HIP_TRY(hipStreamSynchronize(st));
+      resid = 0.0;
+      for (int b = 0; b < w.reduce_grid; ++b) resid += w.host_pairs[2 * (size_t)b + 1];
+      if (tol > 0.0 && resid < tol) {
+        converged = true;
+        break;
+      }
+    }
+  }
+  w.zeroed_buf = yb;
+  p->last_stream = st;
+  if (t & 1) HIP_TRY(hipMemcpyAsync(x_inout, w.xwork, vb, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (iters_out) *iters_out = t;
+  if (resid_out) *resid_out = resid;
+  return (tol > 0.0 && !converged) ? MERBIT_NOT_CONVERGED : MERBIT_OK;
+}
+
+}  // namespace merbit
+
 extern "C" {
 
 int merbit_pagerank(merbit_plan* p, double alpha, double tol, int max_iter, int check_every,
@@ -24,73 +101,22 @@ int merbit_pagerank(merbit_plan* p, double alpha, double tol, int max_iter, int 
   hipStream_t st = static_cast<hipStream_t>(stream);
   int rc = ensure_pagerank_state(p, st);
   if (rc != MERBIT_OK) return rc;
-  if (check_every <= 0) check_every = 10;
-  const int64_t n = p->n_rows;
-  const size_t vb = vsize(p->dtype) * (size_t)n;
-
-  // delta_0: per-block dangling mass of x_0 into partials[0]
-  HIP_TRY(launch_dangling_sum(p->dtype, x_inout, p->dmask, n, p->partials[0], p->reduce_grid,
-                              st));
-  int yb = p->zeroed_buf;
-  if (yb < 0) {
-    yb = 0;
-    rc = zero_boundary(p, p->ybuf[0], st);
-    if (rc != MERBIT_OK) return rc;
-  }
-  void* xs[2] = {x_inout, p->xwork};
   std::vector<double> host_pairs(2 * (size_t)p->reduce_grid);
-  int t = 0;
-  double resid = 0.0;
-  bool converged = false;
-  while (t < max_iter) {
-    // iterations up to the next check (or max_iter), as one chunk
-    int len = check_every - t % check_every;
-    if (len > max_iter - t) len = max_iter - t;
-    const int t0 = t, yb0 = yb;
-    // with a partial hot-column cache the update also writes the next
-    // iterate's hot values, so only the call's first SpMV gathers them
-    const bool fuse_hot = p->hot_n > 0 && !p->hot_all;
-    auto enqueue = [&](hipStream_t s) -> int {
-      for (int i = 0; i < len; ++i) {
-        const int cur = (t0 + i) & 1, b = yb0 ^ (i & 1);
-        const int r = run_fused(p, xs[cur], p->ybuf[b], p->ybuf[b ^ 1], s,
-                                fuse_hot && t0 + i > 0);
-        if (r != MERBIT_OK) return r;
-        HIP_TRY(launch_pr_update(p->dtype, p->ybuf[b], xs[cur], xs[cur ^ 1], p->dmask, n, alpha,
-                                 p->partials[cur], p->reduce_grid, p->partials[cur ^ 1],
-                                 p->reduce_grid, s, fuse_hot ? p->hot_cols : nullptr,
-                                 fuse_hot ? p->hot_n : 0, fuse_hot ? p->x_hot : nullptr));
-      }
-      return MERBIT_OK;
-    };
-    // the call's first chunk gathers the hot values, later ones do not: a
-    // different graph (key k = 1 for the first chunk)
-    rc = len == check_every ? run_chunk(p, kLoopPageRank, t0 & 1, yb0, len, t0 == 0 ? 1 : 0,
-                                        x_inout, alpha, enqueue, st)
-                            : enqueue(st);
-    if (rc != MERBIT_OK) return rc;
-    t += len;
-    yb ^= len & 1;
-    if (tol > 0.0 || t == max_iter) {
-      // l1 change of this iteration: sum of the blocks' second components
-      HIP_TRY(hipMemcpyAsync(host_pairs.data(), p->partials[t & 1],
-                             sizeof(double) * host_pairs.size(), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      resid = 0.0;
-      for (int b = 0; b < p->reduce_grid; ++b) resid += host_pairs[2 * (size_t)b + 1];
-      if (tol > 0.0 && resid < tol) {
-        converged = true;
-        break;
-      }
-    }
-  }
-  p->zeroed_buf = yb;
-  p->last_stream = st;
-  if (t & 1) HIP_TRY(hipMemcpyAsync(x_inout, p->xwork, vb, hipMemcpyDeviceToDevice, st));
-  HIP_TRY(hipStreamSynchronize(st));
-  if (iters_out) *iters_out = t;
-  if (resid_out) *resid_out = resid;
-  return (tol > 0.0 && !converged) ? MERBIT_NOT_CONVERGED : MERBIT_OK;
+  PageRankWork w;
+  w.ybuf[0] = p->ybuf[0];
+  w.ybuf[1] = p->ybuf[1];
+  w.xwork = p->xwork;
+  w.partials[0] = p->partials[0];
+  w.partials[1] = p->partials[1];
+  w.dmask = p->dmask;
+  w.reduce_grid = p->reduce_grid;
+  w.zeroed_buf = p->zeroed_buf;
+  w.graphs = true;
+  w.timed = true;
+  w.host_pairs = host_pairs.data();
+  rc = pagerank_loop(p, w, alpha, tol, max_iter, check_every, x_inout, iters_out, resid_out, st);
+  p->zeroed_buf = w.zeroed_buf;
+  return rc;
 }
 
 static int ensure_multi_tables(merbit_plan* p, const int64_t* graph_ptr, int n_graphs,

@@ -132,8 +132,10 @@ void plan_free_all(merbit_plan* p);
 // The fused SpMV y = A x (z: the other dual buffer, cleared at boundary rows,
 // or nullptr).  hot_ready: the plan's hot-column copy already holds x's hot
 // values (written by the PageRank update), so the gather launch is skipped.
+// timed: bracket the launches with the plan's timing events when timing is
+// on (creating events as needed); false never creates any.
 int run_fused(merbit_plan* p, const void* x, void* y, void* z, hipStream_t st,
-              bool hot_ready = false);
+              bool hot_ready = false, bool timed = true);
 // A buffer or value array that captured graphs use has changed: drop them.
 void invalidate_graphs(merbit_plan* p);
 // Zero v at the first row of every commit unit (nothing for a striped plan,
@@ -152,6 +154,27 @@ int size_grid(merbit_plan* p);
 // Dangling mask and the PageRank iteration buffers (allocated on first use).
 int ensure_dmask(merbit_plan* p, hipStream_t st);
 int ensure_pagerank_state(merbit_plan* p, hipStream_t st);
+
+// Work buffers of one PageRank call: the SpMV's two output buffers (dual
+// buffers), the second iterate, the per-block (dangling mass, l1 change)
+// pairs of the last two reductions (reduce_grid pairs each), the dangling
+// mask, and a host array of 2 reduce_grid doubles for the residual.
+struct PageRankWork {
+  void* ybuf[2] = {nullptr, nullptr};
+  void* xwork = nullptr;
+  double* partials[2] = {nullptr, nullptr};
+  const uint32_t* dmask = nullptr;
+  int reduce_grid = 0;
+  int zeroed_buf = -1;  // in: which ybuf is zero at the boundary rows (-1: none); out: same
+  bool graphs = true;   // record full chunks into HIP graphs (plan-owned buffers only)
+  bool timed = true;    // kernel timing events allowed
+  double* host_pairs = nullptr;
+};
+// The power method of Sec. 5.5.1 on work buffers w (merbit_pagerank's loop);
+// argument meaning and return codes as merbit_pagerank.
+int pagerank_loop(merbit_plan* p, PageRankWork& w, double alpha, double tol, int max_iter,
+                  int check_every, void* x_inout, int* iters_out, double* resid_out,
+                  hipStream_t st);
 
 enum { kLoopPageRank = 1, kLoopPersonalized = 2, kLoopMulti = 3, kLoopAdjoint = 4,
        kLoopBicgstab = 5 };

@@ -36,10 +36,23 @@ __global__ void pack_dangling_kernel(const unsigned char* __restrict__ has_out, 
   dmask[w] = bits;
 }
 
+__global__ void zero_bytes_kernel(unsigned char* __restrict__ p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = 0;
+}
+
 hipError_t launch_dangling_mask(const int32_t* col, int64_t nnz, int64_t n,
                                 unsigned char* scratch_bytes, uint32_t* dmask, hipStream_t st) {
-  hipError_t e = hipMemsetAsync(scratch_bytes, 0, (size_t)(n > 0 ? n : 1), st);
-  if (e != hipSuccess) return e;
+  // cleared by a kernel, not a memset node: callers may record this into a graph
+  hipError_t e;
+  if (n > 0) {
+    int64_t zgrid = (n + 255) / 256;
+    if (zgrid > 4096) zgrid = 4096;
+    hipLaunchKernelGGL(zero_bytes_kernel, dim3((unsigned)zgrid), dim3(256), 0, st,
+                       scratch_bytes, n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (nnz > 0) {
     int64_t grid = (nnz + 255) / 256;
     if (grid > 8192) grid = 8192;
@@ -53,8 +66,9 @@ hipError_t launch_dangling_mask(const int32_t* col, int64_t nnz, int64_t n,
     hipLaunchKernelGGL(pack_dangling_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0,
                        st, scratch_bytes, n, dmask);
     e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return e;
+  return hipSuccess;
 }
 
 // ------------------------------------------------ two-value reduction ----

@@ -19,7 +19,8 @@ OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, NOT_CONVERGED, BREAKDOWN = 0, -1, -2, -3
 F32, F64 = 0, 1
 EXPORTED = ("merbit_opts_init", "merbit_plan_create", "merbit_plan_set_values", "merbit_plan_info",
             "merbit_plan_export", "merbit_spmv", "merbit_spmv_dual", "merbit_zero_boundary",
-            "merbit_pagerank", "merbit_spmm", "merbit_spmm_dual", "merbit_spmm_zero_boundary",
+            "merbit_pagerank", "merbit_pagerank_noalloc", "merbit_spmm", "merbit_spmm_dual",
+            "merbit_spmm_zero_boundary",
             "merbit_pagerank_personalized", "merbit_pagerank_multi", "merbit_transpose",
             "merbit_sddmm", "merbit_gather_values", "merbit_column_scale",
             "merbit_pagerank_adjoint", "merbit_bicgstab", "merbit_tune",
@@ -85,6 +86,8 @@ def load():
     lib.merbit_zero_boundary.argtypes = [vp, vp, vp]
     lib.merbit_pagerank.argtypes = [vp, dbl, dbl, i32, i32, vp, ctypes.POINTER(i32),
                                     ctypes.POINTER(dbl), vp]
+    lib.merbit_pagerank_noalloc.argtypes = [vp, dbl, dbl, i32, i32, vp, ctypes.POINTER(i32),
+                                            ctypes.POINTER(dbl), vp]
     lib.merbit_spmm.argtypes = [vp, vp, i64, vp, i64, i32, vp]
     lib.merbit_spmm_dual.argtypes = [vp, vp, i64, vp, i64, vp, i64, i32, vp]
     lib.merbit_spmm_zero_boundary.argtypes = [vp, vp, i64, i32, vp]
@@ -110,7 +113,7 @@ def load():
     lib.merbit_version.restype = ctypes.c_char_p
     for name in ("merbit_plan_create", "merbit_plan_set_values", "merbit_plan_info",
                  "merbit_plan_export", "merbit_spmv", "merbit_spmv_dual", "merbit_zero_boundary",
-                 "merbit_pagerank", "merbit_spmm", "merbit_spmm_dual",
+                 "merbit_pagerank", "merbit_pagerank_noalloc", "merbit_spmm", "merbit_spmm_dual",
                  "merbit_spmm_zero_boundary", "merbit_pagerank_personalized",
                  "merbit_pagerank_multi", "merbit_transpose", "merbit_sddmm",
                  "merbit_gather_values", "merbit_column_scale", "merbit_pagerank_adjoint",
@@ -279,6 +282,21 @@ class Plan:
                                            int(max_iter), int(check_every),
                                            _dev(x, self.dtype, "x"), ctypes.byref(it),
                                            ctypes.byref(res), _stream(stream)),
+                    allow=(OK, NOT_CONVERGED))
+        return it.value, res.value, rc == OK
+
+    def pagerank_noalloc(self, x: torch.Tensor, alpha: float = 0.85, tol: float = 0.0,
+                         max_iter: int = 100, check_every: int = 10, stream=None):
+        """As pagerank(), through merbit_pagerank_noalloc: the library's fixed
+        work array instead of plan-owned buffers, no HIP graphs."""
+        if x.numel() != self.n_rows:
+            raise ValueError("x length mismatch")
+        it = ctypes.c_int()
+        res = ctypes.c_double()
+        rc = _check(load().merbit_pagerank_noalloc(self._handle(), float(alpha), float(tol),
+                                                   int(max_iter), int(check_every),
+                                                   _dev(x, self.dtype, "x"), ctypes.byref(it),
+                                                   ctypes.byref(res), _stream(stream)),
                     allow=(OK, NOT_CONVERGED))
         return it.value, res.value, rc == OK
 
