@@ -18,7 +18,7 @@ SOURCES = ["merbit_api.hip", "merbit_api_iter.hip", "merbit_api_batched.hip",
            "merbit_api_adjoint.hip", "merbit_api_tune.hip", "merbit_plan.hip", "merbit_spmv.hip",
            "merbit_pagerank.hip", "merbit_hot.hip", "merbit_spmv_wave.hip", "merbit_batched.hip",
            "merbit_adjoint.hip", "merbit_bicgstab.hip", "merbit_stripes.hip",
-           "merbit_api_stripes.hip", "merbit_api_noalloc.hip"]
+           "merbit_api_stripes.hip", "merbit_api_noalloc.hip", "merbit_sort.hip"]
 ARCH = os.environ.get("MERBIT_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

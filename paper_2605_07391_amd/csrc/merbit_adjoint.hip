@@ -10,8 +10,6 @@
 //   - the adjoint fixed-point update
 //       lambda' = g + alpha P^T lambda + (alpha / n) (1^T lambda) d,
 //     d the dangling indicator, with deterministic two-level sums.
-#include <hipcub/hipcub.hpp>
-
 #include "merbit_internal.hpp"
 
 namespace merbit {
@@ -81,11 +79,6 @@ hipError_t launch_tile_rows(int dtype, int sigma, bool sddmm, const TileRowsArgs
 
 // ------------------------------------------------------------ transpose --
 
-__global__ void iota_kernel(int32_t* __restrict__ v, int64_t m) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < m) v[i] = (int32_t)i;
-}
-
 // rowT[c] = first position of key c in the sorted keys (m if none follows),
 // for c = 0 .. n_cols: every c is written by exactly one thread.
 __global__ void row_starts_kernel(const uint32_t* __restrict__ keys, int64_t m, int64_t n_cols,
@@ -105,32 +98,44 @@ __global__ void gather_i32_kernel(const int32_t* __restrict__ src, const int32_t
 
 static unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
-hipError_t transpose_sort_bytes(int64_t m, int end_bit, size_t* bytes) {
-  return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const uint32_t*)nullptr,
-                                            (uint32_t*)nullptr, (const int32_t*)nullptr,
-                                            (int32_t*)nullptr, (int)m, 0, end_bit);
+static int radix_passes(int end_bit) { return (end_bit + 7) / 8; }
+
+size_t transpose_temp_bytes(int64_t m, int end_bit) {
+  // two key buffers and one spare position buffer, then the pass's own temp
+  const size_t arrays = 3 * (((size_t)(m > 0 ? m : 1) * sizeof(int32_t) + 255) & ~(size_t)255);
+  return arrays + radix_temp_bytes(m, end_bit < 8 ? end_bit : 8);
 }
 
 hipError_t launch_transpose(const int32_t* col, const int32_t* rows, int64_t m, int64_t n_cols,
-                            int end_bit, void* sort_tmp, size_t sort_bytes, uint32_t* keys_out,
-                            int32_t* iota, int32_t* rowT, int32_t* colT, int32_t* perm,
-                            hipStream_t st) {
+                            int end_bit, void* temp, int32_t* rowT, int32_t* colT,
+                            int32_t* perm, hipStream_t st) {
+  const size_t arr = ((size_t)(m > 0 ? m : 1) * sizeof(int32_t) + 255) & ~(size_t)255;
+  unsigned char* t = static_cast<unsigned char*>(temp);
+  uint32_t* keys[2] = {reinterpret_cast<uint32_t*>(t), reinterpret_cast<uint32_t*>(t + arr)};
+  int32_t* spare = reinterpret_cast<int32_t*>(t + 2 * arr);
+  void* pass_tmp = t + 3 * arr;
   if (m > 0) {
-    hipLaunchKernelGGL(iota_kernel, dim3(blocks_for(m)), dim3(256), 0, st, iota, m);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    // stable LSD radix sort of (column, position) pairs: within a column the
-    // positions stay increasing, i.e. rows of A in order
-    e = hipcub::DeviceRadixSort::SortPairs(sort_tmp, sort_bytes,
-                                           reinterpret_cast<const uint32_t*>(col), keys_out,
-                                           (const int32_t*)iota, perm, (int)m, 0, end_bit, st);
-    if (e != hipSuccess) return e;
+    // stable LSD radix sort of (column, position) pairs, 8 bits a pass: within
+    // a column the positions stay increasing, i.e. the rows of A in order.
+    // Pass p writes buffer (P - 1 - p) & 1, so the last one lands in perm.
+    const int P = radix_passes(end_bit);
+    int32_t* vals[2] = {perm, spare};
+    for (int p = 0; p < P; ++p) {
+      const int shift = 8 * p;
+      const int bits = end_bit - shift < 8 ? end_bit - shift : 8;
+      const int out = (P - 1 - p) & 1, in = out ^ 1;
+      const uint32_t* kin = p == 0 ? reinterpret_cast<const uint32_t*>(col) : keys[in];
+      const int32_t* vin = p == 0 ? nullptr : vals[in];
+      hipError_t e = launch_radix_pass(kin, vin, keys[out], vals[out], m, shift, bits, pass_tmp,
+                                       st);
+      if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(gather_i32_kernel, dim3(blocks_for(m)), dim3(256), 0, st, rows, perm,
                        colT, m);
-    e = hipGetLastError();
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(row_starts_kernel, dim3(blocks_for(m + 1)), dim3(256), 0, st, keys_out, m,
+  hipLaunchKernelGGL(row_starts_kernel, dim3(blocks_for(m + 1)), dim3(256), 0, st, keys[0], m,
                      n_cols, rowT);
   return hipGetLastError();
 }

@@ -262,76 +262,50 @@ static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
     p->hot_n = (int32_t)nc;
     p->hot_coverage = 1.0;
   } else {
-    int32_t* counts = nullptr;
-    int32_t* hist = nullptr;
-    HIP_TRY(hipMalloc(&counts, sizeof(int32_t) * (size_t)nc));
-    HIP_TRY(hipMalloc(&hist, sizeof(int32_t) * kHotHistBins));
-    std::vector<int32_t> h(kHotHistBins);
-    // sampled counts: one nonzero in `sample`, about two samples per column
+    // sampled counts: one nonzero in `sample`, about two samples per column;
+    // the cache takes the columns of count >= t for the smallest t that keeps
+    // them within cap (a tie at the cut is left out whole)
     int64_t sample = p->nnz / (2 * nc);
     sample = sample < 1 ? 1 : (sample > 8 ? 8 : sample);
-    hipError_t e = hot_count_columns(p->col, p->nnz, nc, (int)sample, counts, hist, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(h.data(), hist, sizeof(int32_t) * kHotHistBins, hipMemcpyDeviceToHost,
-                         st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e != hipSuccess) {
-      (void)hipFree(counts);
-      (void)hipFree(hist);
-      return fail_hip("hot column counts", e);
-    }
-    // smallest threshold t >= 1 with at most cap columns of (sampled) count >= t
+    int32_t *counts = nullptr, *hist = nullptr, *slot_of = nullptr;
+    void* sel_tmp = nullptr;
+    auto release = [&]() {
+      (void)hipStreamSynchronize(st);
+      if (counts) (void)hipFree(counts);
+      if (hist) (void)hipFree(hist);
+      if (slot_of) (void)hipFree(slot_of);
+      if (sel_tmp) (void)hipFree(sel_tmp);
+    };
+    hipError_t e = hipMalloc(&counts, sizeof(int32_t) * (size_t)nc);
+    if (e == hipSuccess) e = hipMalloc(&hist, sizeof(int32_t) * kHotHistBins);
+    if (e == hipSuccess) e = hipMalloc(&slot_of, sizeof(int32_t) * (size_t)nc);
+    if (e == hipSuccess) e = hipMalloc(&sel_tmp, hot_select_temp_bytes(nc));
+    if (e == hipSuccess) e = hipMalloc(&p->hot_cols, sizeof(int32_t) * (size_t)cap);
+    if (e == hipSuccess) e = hot_count_columns(p->col, p->nnz, nc, (int)sample, counts, hist, st);
     int64_t taken = 0;
     double covered = 0.0;
-    int32_t t = kHotHistBins;
-    for (int b = kHotHistBins - 1; b >= 1; --b) {
-      if (taken + h[b] > cap) break;
-      taken += h[b];
-      covered += (double)b * h[b];
-      t = b;
+    if (e == hipSuccess)
+      e = hot_select_top(counts, hist, nc, cap, true, sel_tmp, slot_of, p->hot_cols, &taken,
+                         &covered, st);
+    if (e != hipSuccess) {
+      release();
+      return fail_hip("hot column selection", e);
     }
     p->hot_coverage = covered * (double)sample / (double)p->nnz;  // estimate when sampled
     if (p->hot_coverage > 1.0) p->hot_coverage = 1.0;
     const bool keep = taken > 0 && (cap_req > 0 || p->hot_coverage >= 0.2);
     if (keep) {
-      const int nb = hot_select_blocks(nc);
-      int32_t* blk = nullptr;
-      int32_t* slot_of = nullptr;
-      std::vector<int32_t> hb(nb);
-      e = hipMalloc(&blk, sizeof(int32_t) * (size_t)nb);
-      if (e == hipSuccess) e = hipMalloc(&slot_of, sizeof(int32_t) * (size_t)nc);
-      if (e == hipSuccess) e = hipMalloc(&p->hot_cols, sizeof(int32_t) * (size_t)taken);
-      if (e == hipSuccess) e = hot_select_count(counts, nc, t, blk, st);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(hb.data(), blk, sizeof(int32_t) * (size_t)nb, hipMemcpyDeviceToHost,
-                           st);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      if (e == hipSuccess) {
-        int32_t acc = 0;
-        for (int b = 0; b < nb; ++b) {
-          const int32_t c = hb[b];
-          hb[b] = acc;
-          acc += c;
-        }
-        e = hipMemcpyAsync(blk, hb.data(), sizeof(int32_t) * (size_t)nb, hipMemcpyHostToDevice,
-                           st);
-      }
-      if (e == hipSuccess) e = hot_select_assign(counts, nc, t, blk, slot_of, p->hot_cols, st);
-      if (e == hipSuccess) e = hipMalloc(&p->colx, sizeof(int32_t) * (size_t)p->nnz);
+      e = hipMalloc(&p->colx, sizeof(int32_t) * (size_t)p->nnz);
       if (e == hipSuccess) e = hot_recode(p->col, p->nnz, slot_of, p->colx, st);
       if (e == hipSuccess) e = hipMalloc(&p->x_hot, vs * (size_t)taken);
-      if (e == hipSuccess) e = hipStreamSynchronize(st);
-      (void)hipFree(blk);
-      (void)hipFree(slot_of);
-      if (e != hipSuccess) {
-        (void)hipFree(counts);
-        (void)hipFree(hist);
-        return fail_hip("hot column selection", e);
-      }
-      p->hot_n = (int32_t)taken;
+      if (e == hipSuccess) p->hot_n = (int32_t)taken;
+    } else {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(p->hot_cols);
+      p->hot_cols = nullptr;
     }
-    (void)hipFree(counts);
-    (void)hipFree(hist);
+    release();
+    if (e != hipSuccess) return fail_hip("hot column recode", e);
   }
   if (p->hot_n > 0) {
     if (p->hot_all) {

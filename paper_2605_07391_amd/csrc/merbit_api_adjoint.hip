@@ -36,32 +36,24 @@ int merbit_transpose(merbit_plan* p, int32_t* rowT_ptr, int32_t* colT, int32_t* 
   const int64_t m = p->nnz;
   int end_bit = 1;
   while (end_bit < 31 && ((int64_t)1 << end_bit) < p->n_cols) ++end_bit;
-  size_t sort_bytes = 0;
-  if (m > 0) HIP_TRY(transpose_sort_bytes(m, end_bit, &sort_bytes));
-  int32_t *rows = nullptr, *iota = nullptr;
-  uint32_t* keys = nullptr;
+  int32_t* rows = nullptr;
   void* tmp = nullptr;
   auto cleanup = [&]() {
     (void)hipStreamSynchronize(st);
     if (rows) (void)hipFree(rows);
-    if (iota) (void)hipFree(iota);
-    if (keys) (void)hipFree(keys);
     if (tmp) (void)hipFree(tmp);
   };
   hipError_t e = hipSuccess;
   const size_t mm = (size_t)(m > 0 ? m : 1);
   if (e == hipSuccess) e = hipMalloc(&rows, sizeof(int32_t) * mm);
-  if (e == hipSuccess) e = hipMalloc(&iota, sizeof(int32_t) * mm);
-  if (e == hipSuccess) e = hipMalloc(&keys, sizeof(uint32_t) * mm);
-  if (e == hipSuccess) e = hipMalloc(&tmp, sort_bytes > 0 ? sort_bytes : 16);
+  if (e == hipSuccess) e = hipMalloc(&tmp, transpose_temp_bytes(m, end_bit));
   if (e == hipSuccess && m > 0) {
     TileRowsArgs a = tile_rows_args(p);
     a.rows = rows;
     e = launch_tile_rows(p->dtype, p->sigma, false, a, st);
   }
   if (e == hipSuccess)
-    e = launch_transpose(p->col, rows, m, p->n_cols, end_bit, tmp, sort_bytes, keys, iota,
-                         rowT_ptr, colT, perm, st);
+    e = launch_transpose(p->col, rows, m, p->n_cols, end_bit, tmp, rowT_ptr, colT, perm, st);
   cleanup();
   if (e != hipSuccess) return fail_hip("transpose", e);
   p->last_stream = st;

@@ -51,12 +51,8 @@ int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st) {
   p->words = a.words;
   const int64_t nw = a.stripes * a.words;
   Scratch tmp;
-  HIP_TRY(stripe_temp_bytes(m, nw, a.key_bits, &a.temp_bytes));
-  HIP_TRY(tmp.get(reinterpret_cast<unsigned char**>(&a.temp), a.temp_bytes));
+  HIP_TRY(tmp.get(reinterpret_cast<unsigned char**>(&a.temp), stripe_temp_bytes(m, nw, sbits)));
   HIP_TRY(tmp.get(&a.rows, (size_t)m));
-  HIP_TRY(tmp.get(&a.key, (size_t)m));
-  HIP_TRY(tmp.get(&a.pos, (size_t)m));
-  HIP_TRY(tmp.get(&a.skey, (size_t)m));
   HIP_TRY(tmp.get(&a.row_s, (size_t)m));
   HIP_TRY(tmp.get(&a.flag, (size_t)m));
   HIP_TRY(tmp.get(&a.vidx, (size_t)m));
@@ -146,44 +142,29 @@ int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
   if (cap > 0) {
     const int64_t nc = p->n_cols;
     Scratch tmp;
-    int32_t *counts = nullptr, *hist = nullptr, *iota = nullptr, *csorted = nullptr,
-            *cols = nullptr, *slot_of = nullptr;
-    unsigned char* sort_tmp = nullptr;
-    size_t sort_bytes = 0;
-    HIP_TRY(stripe_rank_bytes(nc, &sort_bytes));
-    HIP_TRY(tmp.get(&sort_tmp, sort_bytes));
+    int32_t *counts = nullptr, *hist = nullptr, *slot_of = nullptr;
+    unsigned char* sel_tmp = nullptr;
     HIP_TRY(tmp.get(&counts, (size_t)nc));
     HIP_TRY(tmp.get(&hist, (size_t)kHotHistBins));
-    HIP_TRY(tmp.get(&iota, (size_t)nc));
-    HIP_TRY(tmp.get(&csorted, (size_t)nc));
-    HIP_TRY(tmp.get(&cols, (size_t)nc));
     HIP_TRY(tmp.get(&slot_of, (size_t)nc));
+    HIP_TRY(tmp.get(&sel_tmp, hot_select_temp_bytes(nc)));
     HIP_TRY(hipMalloc(&p->hot_cols, sizeof(int32_t) * (size_t)(cap * R)));
     HIP_TRY(hipMalloc(&p->colx, sizeof(int32_t) * (size_t)p->nnz));
-    std::vector<int32_t> top((size_t)cap);
     // hot sets of the current ranges: hoff, cov (hot nonzeros per range)
     auto select = [&]() -> int {
       taken_max = 0;
       for (int k = 0; k < R; ++k) {
         const int64_t lo = spans[k], len = (int64_t)spans[k + 1] - spans[k];
-        // a 1-in-4 sample of a long range: the hot columns' counts are in the
-        // hundreds, and the hottest columns' global atomics serialise
-        HIP_TRY(hot_count_columns(p->scol + lo, len, nc, len > 64 * cap ? 4 : 1, counts, hist,
-                                  st));
-        HIP_TRY(launch_stripe_rank_columns(counts, nc, sort_tmp, sort_bytes, iota, csorted, cols,
-                                           st));
-        HIP_TRY(hipMemcpyAsync(top.data(), csorted, sizeof(int32_t) * (size_t)cap,
-                               hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        // counts are in decreasing order: keep the columns that occur
-        const int64_t taken =
-            std::lower_bound(top.begin(), top.end(), 0, std::greater<int32_t>()) - top.begin();
-        cov[k] = 0.0;
-        for (int64_t i = 0; i < taken; ++i) cov[k] += top[(size_t)i];
-        if (len > 64 * cap) cov[k] = std::min(4.0 * cov[k], (double)len);  // sampled counts
-        HIP_TRY(hipMemsetAsync(slot_of, 0xFF, sizeof(int32_t) * (size_t)nc, st));
-        HIP_TRY(launch_stripe_hot(cols, (int32_t)taken, sort_tmp, sort_bytes, csorted, slot_of,
-                                  p->hot_cols + hoff[k], st));
+        // a 1-in-4 sample of a long range: the hot columns' counts are in
+        // the hundreds, and the hottest columns' global atomics serialise
+        const int sample = len > 64 * cap ? 4 : 1;
+        HIP_TRY(hot_count_columns(p->scol + lo, len, nc, sample, counts, hist, st));
+        int64_t taken = 0;
+        double covered = 0.0;
+        HIP_TRY(hot_select_top(counts, hist, nc, cap, false, sel_tmp, slot_of,
+                               p->hot_cols + hoff[k], &taken, &covered, st));
+        cov[k] = sample > 1 ? std::min(sample * covered, (double)len) : covered;
+        if (taken == 0) HIP_TRY(hipMemsetAsync(slot_of, 0xFF, sizeof(int32_t) * (size_t)nc, st));
         HIP_TRY(hot_recode(p->scol + lo, len, slot_of, p->colx + lo, st));
         hoff[k + 1] = hoff[k] + (int32_t)taken;
         taken_max = std::max(taken_max, taken);

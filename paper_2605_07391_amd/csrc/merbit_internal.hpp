@@ -256,12 +256,16 @@ hipError_t spmv_wave_set_hot_lds(int dtype, int sigma, int waves, size_t bytes,
 // Hot-column cache.
 hipError_t hot_count_columns(const int32_t* col, int64_t nnz, int64_t n_cols, int sample,
                              int32_t* counts, int32_t* hist, hipStream_t st);
-int hot_select_blocks(int64_t n_cols);
-hipError_t hot_select_count(const int32_t* counts, int64_t n_cols, int32_t threshold,
-                            int32_t* block_counts, hipStream_t st);
-hipError_t hot_select_assign(const int32_t* counts, int64_t n_cols, int32_t threshold,
-                             const int32_t* block_offsets, int32_t* slot_of, int32_t* hot_cols,
-                             hipStream_t st);
+// Hot-column selection from the counts and their histogram (hot_count_columns):
+// the at most `cap` columns of largest count, ties by increasing column
+// (whole_ties: a tie at the cut is taken whole or not at all), get slots
+// 0 .. taken - 1 in column order: slot_of[c] (-1 for the others) and
+// hot_cols[slot].  *covered = the sum of the taken counts.  Synchronises st.
+// temp: hot_select_temp_bytes(n_cols) bytes.
+size_t hot_select_temp_bytes(int64_t n_cols);
+hipError_t hot_select_top(const int32_t* counts, const int32_t* hist, int64_t n_cols, int64_t cap,
+                          bool whole_ties, void* temp, int32_t* slot_of, int32_t* hot_cols,
+                          int64_t* taken, double* covered, hipStream_t st);
 hipError_t hot_recode(const int32_t* col, int64_t nnz, const int32_t* slot_of, int32_t* colx,
                       hipStream_t st);
 hipError_t launch_hot_gather(int dtype, const void* x, const int32_t* hot_cols, int32_t hot_n,
@@ -297,11 +301,13 @@ struct TileRowsArgs {
 };
 hipError_t launch_tile_rows(int dtype, int sigma, bool sddmm, const TileRowsArgs& a,
                             hipStream_t st);
-hipError_t transpose_sort_bytes(int64_t m, int end_bit, size_t* bytes);
+// CSR of A^T from the rows and columns of A's nonzeros (stable by row):
+// rowT [n_cols + 1], colT [m], perm [m] (A position of each A^T nonzero).
+// temp: transpose_temp_bytes(m, end_bit) bytes; columns are < 2^end_bit.
+size_t transpose_temp_bytes(int64_t m, int end_bit);
 hipError_t launch_transpose(const int32_t* col, const int32_t* rows, int64_t m, int64_t n_cols,
-                            int end_bit, void* sort_tmp, size_t sort_bytes, uint32_t* keys_out,
-                            int32_t* iota, int32_t* rowT, int32_t* colT, int32_t* perm,
-                            hipStream_t st);
+                            int end_bit, void* temp, int32_t* rowT, int32_t* colT,
+                            int32_t* perm, hipStream_t st);
 hipError_t launch_gather_values(int dtype, const int32_t* perm, const void* src, const void* src2,
                                 void* dst, int64_t m, hipStream_t st);
 hipError_t launch_column_scale(int dtype, const int32_t* col, const void* a, const void* t,
@@ -327,6 +333,19 @@ struct BicgArgs {
 int bicg_grid(int64_t n);
 hipError_t launch_bicg(int dtype, const BicgArgs& a, int stage, hipStream_t st);
 
+// Scans of int32 arrays (in == out allowed) and one stable radix-sort pass
+// of (key, value) pairs by the digit (key >> shift) & (2^bits - 1), bits in
+// 1..8 (val_in == nullptr: the values are the positions 0 .. n - 1).  temp:
+// scan_temp_bytes(n) / radix_temp_bytes(n, bits) bytes of device memory.
+enum ScanKind { kScanExclusiveSum = 0, kScanInclusiveSum = 1, kScanInclusiveMax = 2 };
+size_t scan_temp_bytes(int64_t n);
+hipError_t launch_scan_i32(const int32_t* in, int32_t* out, int64_t n, ScanKind kind,
+                           void* temp, hipStream_t st);
+size_t radix_temp_bytes(int64_t n, int bits);
+hipError_t launch_radix_pass(const uint32_t* key_in, const int32_t* val_in, uint32_t* key_out,
+                             int32_t* val_out, int64_t n, int shift, int bits, void* temp,
+                             hipStream_t st);
+
 // Column stripes (a matrix stacked by column stripe, rows = the non-empty
 // (stripe, row) pairs) and the per-row sum of the stripes' results.
 // Entry [w][s] of the combine table: which of rows 64 w .. 64 w + 63 have
@@ -341,14 +360,10 @@ struct StripeSplitArgs {
   const int32_t* col;      // [m]
   int64_t n_rows, m;
   int shift;               // stripe of column c = c >> shift
-  int key_bits;            // bits of the stripe index (radix sort)
+  int key_bits;            // bits of the stripe index (one radix pass)
   int64_t stripes, words;  // words = ceil(n_rows / 64) per stripe
-  void* temp;
-  size_t temp_bytes;
+  void* temp;              // stripe_temp_bytes()
   int32_t* rows;           // [m] row of each nonzero
-  uint32_t* key;           // [m] stripe of each nonzero
-  int32_t* pos;            // [m]
-  uint32_t* skey;          // [m] sorted stripes
   int32_t* perm;           // [m] position in the matrix of the i-th stacked nonzero
   int32_t* col_s;          // [m] stacked column stream
   int32_t* row_s;          // [m] row of each stacked nonzero
@@ -361,20 +376,11 @@ struct StripeSplitArgs {
   int32_t* wcnt;           // [stripes * words] popcounts, stripe-major
   int32_t* rank;           // [stripes * words] their exclusive scan
 };
-hipError_t stripe_temp_bytes(int64_t m, int64_t n_words, int key_bits, size_t* bytes);
+size_t stripe_temp_bytes(int64_t m, int64_t n_words, int key_bits);
 // rows, the stable sort by stripe, the stacked column stream and pair flags
 hipError_t launch_stripe_split(const StripeSplitArgs& a, hipStream_t st);
 // with V = number of pairs known: vrow_* , the bitmap and the ranks
 hipError_t launch_stripe_rows(const StripeSplitArgs& a, int64_t nv, hipStream_t st);
-hipError_t stripe_rank_bytes(int64_t n, size_t* bytes);
-// columns by decreasing count (ties: increasing column)
-hipError_t launch_stripe_rank_columns(const int32_t* counts, int64_t n, void* temp,
-                                      size_t temp_bytes, int32_t* iota, int32_t* counts_sorted,
-                                      int32_t* cols_sorted, hipStream_t st);
-// the taken most frequent columns (top_cols) get slots in column order
-hipError_t launch_stripe_hot(const int32_t* top_cols, int32_t taken, void* temp,
-                             size_t temp_bytes, int32_t* cols_sorted, int32_t* slot_of,
-                             int32_t* hot_cols, hipStream_t st);
 hipError_t launch_stripe_combine(int dtype, int stripes, const void* yv, int64_t nv,
                                  const StripeWord* sw, int64_t words, int64_t n_rows, void* y,
                                  hipStream_t st);

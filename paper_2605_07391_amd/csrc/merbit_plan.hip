@@ -1,14 +1,20 @@
 // One-time preprocessing: CSR validation and TILE generation
-// (Sec. 4.1.2 of the MERBIT paper; merge_search is Algorithm 1).
+// (Sec. 4.1.1 format, Sec. 4.1.2 preprocessing; the lane start search is
+// Algorithm 1).
 //
-// One thread per lane, one 64-lane wavefront per tile (omega = 64).  Each
-// thread finds its lane's start on the merge path by a binary search along
-// its diagonal j * sigma, takes the tile start from lane 0 of its wavefront,
-// walks its sigma steps recording a 1 bit per down step, packs the
-// descriptor (32 or 64 bits wide), and the wavefront votes whether any of its lanes left the tile's
-// start row (if none did, the tile is a single-row "fast" tile and bit 31 of
-// tile_y is set).  Cost O(lane_num (log n + sigma)); the row_ptr reads are
-// served from L2 after the first probes.
+// One thread per lane, one 64-lane wavefront per tile (omega = 64).  The
+// merge path (Sec. 3.3) leaves row r by its down step at path position
+// p(r) = row_ptr[r + 1] + r, and p increases strictly with r.  Lane j covers
+// positions [d, d + s) with d = j sigma, s = min(sigma, m + n - d):
+//   - its start row y0 is the number of rows with p(r) < d (a binary search
+//     over r, Algorithm 1) and its start column is d - y0;
+//   - its down steps are those of rows y0, y0 + 1, ... while p(r) < d + s,
+//     and the step at offset k is a down step exactly when p(r) = d + k for
+//     one of them, so the flag word is the OR of 1 << (p(r) - d) over those
+//     rows (one iteration per down step, not per step);
+//   - the tile starts at its lane 0, and a tile is a single-row ("fast")
+//     tile when none of its lanes has a down step.
+// Cost O(lane_num log n + n + m / sigma).
 #include "merbit_internal.hpp"
 
 namespace merbit {
@@ -42,16 +48,15 @@ hipError_t launch_validate(const int32_t* row_ptr, const int32_t* col, int64_t n
   return hipGetLastError();
 }
 
-// Algorithm 1: number of rows finished when the path crosses diagonal `diag`.
-// Row r is finished after diagonal row_ptr[r + 1] + r + 1, which increases
-// strictly with r, so a binary search over r finds the crossing.
+// Algorithm 1: number of rows finished before path position `diag`, i.e.
+// of rows r with p(r) = row_ptr[r + 1] + r < diag (p increases with r).
 __device__ __forceinline__ int32_t merge_search_rows(const int32_t* __restrict__ row_ptr,
                                                      int32_t n_rows, int32_t nnz, int32_t diag) {
   int32_t lo = diag - nnz > 0 ? diag - nnz : 0;
   int32_t hi = diag < n_rows ? diag : n_rows;
   while (lo < hi) {
     const int32_t mid = (lo + hi) >> 1;
-    if (row_ptr[mid + 1] <= diag - mid - 1) lo = mid + 1;
+    if (row_ptr[mid + 1] + mid < diag) lo = mid + 1;
     else hi = mid;
   }
   return lo;
@@ -64,33 +69,27 @@ __global__ __launch_bounds__(256) void plan_kernel(PlanArgs a, D* __restrict__ l
   const int lid = threadIdx.x & (kOmega - 1);
   const int32_t L = a.nnz + a.n_rows;
   if (j < a.lane_num) {
-    const int32_t diag = (int32_t)j * a.sigma;
-    int32_t cy = merge_search_rows(a.row_ptr, a.n_rows, a.nnz, diag);
-    int32_t cx = diag - cy;
-    // lane 0 of the wavefront starts the tile (it is active whenever any
-    // lane of this wavefront is)
-    const int32_t tx = __shfl(cx, 0, kOmega);
-    const int32_t ty = __shfl(cy, 0, kOmega);
-    const D x_off = (D)(cx - tx);
-    const D y_off = (D)(cy - ty);
-    const int32_t steps = (L - diag) < a.sigma ? (L - diag) : a.sigma;
+    const int32_t d = (int32_t)j * a.sigma;
+    const int32_t end = L - d < a.sigma ? L : d + a.sigma;
+    const int32_t y0 = merge_search_rows(a.row_ptr, a.n_rows, a.nnz, d);
     D flags = 0;
-    for (int32_t k = 0; k < steps; ++k) {
-      if (cy >= a.n_rows) break;  // only reachable for a malformed row_ptr
-      if (cx < a.row_ptr[cy + 1]) {
-        ++cx;
-      } else {
-        flags |= (D)1 << k;
-        ++cy;
-      }
+    for (int32_t r = y0; r < a.n_rows; ++r) {
+      const int32_t pos = a.row_ptr[r + 1] + r;
+      // pos < d only for a row_ptr that is not monotone (never validated)
+      if (pos >= end || pos < d) break;
+      flags |= (D)1 << (pos - d);
     }
+    // the tile's start: lane 0 of the wavefront, active whenever any lane is
+    const int32_t ty = __builtin_amdgcn_readfirstlane(y0);
+    const int32_t tx = __builtin_amdgcn_readfirstlane(d - y0);
+    const D x_off = (D)(d - y0 - tx);
+    const D y_off = (D)(y0 - ty);
     lane_desc[j] = (flags << (2 * a.bits)) | (y_off << a.bits) | x_off;
-    const unsigned long long active = __ballot(1);
-    const unsigned long long stayed = __ballot(cy == ty);
+    const bool single_row = __ballot(flags != 0) == 0ull;
     if (lid == 0) {
       const int64_t i = j / kOmega;
       a.tile_x[i] = tx;
-      a.tile_y[i] = (uint32_t)ty | (stayed == active ? kFastBit : 0u);
+      a.tile_y[i] = (uint32_t)ty | (single_row ? kFastBit : 0u);
     }
   } else if (j == a.lane_num) {
     a.tile_x[a.tile_num] = a.nnz;

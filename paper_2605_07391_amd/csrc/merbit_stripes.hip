@@ -16,8 +16,6 @@
 //   y[r] = sum over stripes s holding a nonzero of row r of y'[v(s, r)],
 // with v(s, r) found from a bitmap of the rows present in each stripe and
 // the rank of each 64-row word.
-#include <hipcub/hipcub.hpp>
-
 #include "merbit_internal.hpp"
 
 namespace merbit {
@@ -32,30 +30,21 @@ __global__ void row_heads_kernel(const int32_t* __restrict__ row_ptr, int64_t n_
   if (r < n_rows && row_ptr[r + 1] > row_ptr[r]) rows[row_ptr[r]] = (int32_t)r;
 }
 
-// key[i] = stripe of nonzero i, pos[i] = i
-__global__ void stripe_key_kernel(const int32_t* __restrict__ col, int64_t m, int shift,
-                                  uint32_t* __restrict__ key, int32_t* __restrict__ pos) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= m) return;
-  key[i] = (uint32_t)col[i] >> shift;
-  pos[i] = (int32_t)i;
-}
-
-// After the stable sort by stripe: col_s[i] = col[perm[i]], row_s[i] =
-// rows[perm[i]], and flag[i] = 1 where a new (stripe, row) pair begins.
+// After the stable sort by stripe (col_s = the stacked column stream, perm =
+// matrix position of each stacked nonzero): row_s[i] = rows[perm[i]], and
+// flag[i] = 1 where a new (stripe, row) pair begins.
 __global__ void stripe_gather_kernel(const int32_t* __restrict__ perm,
-                                     const int32_t* __restrict__ col,
                                      const int32_t* __restrict__ rows,
-                                     const uint32_t* __restrict__ skey, int64_t m,
-                                     int32_t* __restrict__ col_s, int32_t* __restrict__ row_s,
-                                     int32_t* __restrict__ flag) {
+                                     const int32_t* __restrict__ col_s, int shift, int64_t m,
+                                     int32_t* __restrict__ row_s, int32_t* __restrict__ flag) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= m) return;
-  const int32_t k = perm[i];
-  const int32_t r = rows[k];
-  col_s[i] = col[k];
+  const int32_t r = rows[perm[i]];
   row_s[i] = r;
-  flag[i] = (i == 0 || skey[i] != skey[i - 1] || rows[perm[i - 1]] != r) ? 1 : 0;
+  flag[i] = (i == 0 || ((uint32_t)col_s[i] >> shift) != ((uint32_t)col_s[i - 1] >> shift) ||
+             rows[perm[i - 1]] != r)
+                ? 1
+                : 0;
 }
 
 // For each pair start i (flag set): v = vidx[i], vrow_ptr[v] = i, and the
@@ -63,7 +52,7 @@ __global__ void stripe_gather_kernel(const int32_t* __restrict__ perm,
 __global__ void vrow_emit_kernel(const int32_t* __restrict__ flag,
                                  const int32_t* __restrict__ vidx,
                                  const int32_t* __restrict__ row_s,
-                                 const uint32_t* __restrict__ skey, int64_t m,
+                                 const int32_t* __restrict__ col_s, int shift, int64_t m,
                                  int32_t* __restrict__ vrow_ptr, int32_t* __restrict__ vrow_row,
                                  uint32_t* __restrict__ vrow_stripe) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -71,7 +60,7 @@ __global__ void vrow_emit_kernel(const int32_t* __restrict__ flag,
   const int32_t v = vidx[i];
   vrow_ptr[v] = (int32_t)i;
   vrow_row[v] = row_s[i];
-  vrow_stripe[v] = skey[i];
+  vrow_stripe[v] = (uint32_t)col_s[i] >> shift;
 }
 
 __global__ void store_i32_kernel(int32_t* __restrict__ p, int32_t v) {
@@ -104,21 +93,6 @@ __global__ void rank_store_kernel(const int32_t* __restrict__ rank, int64_t stri
   if (i >= stripes * words) return;
   const int64_t s = i / words, w = i - s * words;
   sw[w * stripes + s].rank = rank[i];
-}
-
-// slot_of[cols[i]] = i and hot_cols[i] = cols[i] for i < taken
-__global__ void slot_assign_kernel(const int32_t* __restrict__ cols, int32_t taken,
-                                   int32_t* __restrict__ slot_of, int32_t* __restrict__ hot_cols) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= taken) return;
-  const int32_t c = cols[i];
-  slot_of[c] = i;
-  hot_cols[i] = c;
-}
-
-__global__ void iota32_kernel(int32_t* __restrict__ v, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) v[i] = (int32_t)i;
 }
 
 // One wavefront per 64-row word: lane b sums row 64 w + b over the stripes.
@@ -170,56 +144,40 @@ __global__ __launch_bounds__(256) void stripe_combine_kernel(const V* __restrict
 
 // ------------------------------------------------------------ launchers --
 
-hipError_t stripe_temp_bytes(int64_t m, int64_t n_words, int key_bits, size_t* bytes) {
-  size_t a = 0, b = 0, c = 0;
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, a, (const uint32_t*)nullptr,
-                                                    (uint32_t*)nullptr, (const int32_t*)nullptr,
-                                                    (int32_t*)nullptr, (int)m, 0, key_bits);
-  if (e != hipSuccess) return e;
-  e = hipcub::DeviceScan::InclusiveScan(nullptr, b, (const int32_t*)nullptr, (int32_t*)nullptr,
-                                        hipcub::Max(), (int)m);
-  if (e != hipSuccess) return e;
-  const int64_t big = m > n_words ? m : n_words;
-  e = hipcub::DeviceScan::ExclusiveSum(nullptr, c, (const int32_t*)nullptr, (int32_t*)nullptr,
-                                       (int)big);
-  if (e != hipSuccess) return e;
-  *bytes = a > b ? a : b;
-  if (c > *bytes) *bytes = c;
-  return hipSuccess;
+size_t stripe_temp_bytes(int64_t m, int64_t n_words, int key_bits) {
+  const size_t a = scan_temp_bytes(m > n_words ? m : n_words);
+  const size_t b = radix_temp_bytes(m, key_bits);
+  return a > b ? a : b;
 }
 
 hipError_t launch_stripe_split(const StripeSplitArgs& a, hipStream_t st) {
   const int64_t m = a.m;
   hipError_t e;
-  // row of every nonzero: row starts (in pos), then a running maximum
-  e = hipMemsetAsync(a.pos, 0, sizeof(int32_t) * (size_t)m, st);
+  // row of every nonzero: the row's index at its first nonzero, 0 elsewhere,
+  // then a running maximum
+  e = hipMemsetAsync(a.rows, 0, sizeof(int32_t) * (size_t)m, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(row_heads_kernel, dim3(blocks_of(a.n_rows)), dim3(256), 0, st, a.row_ptr,
-                     a.n_rows, a.pos);
+                     a.n_rows, a.rows);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  size_t tb = a.temp_bytes;
-  e = hipcub::DeviceScan::InclusiveScan(a.temp, tb, a.pos, a.rows, hipcub::Max(), (int)m, st);
+  e = launch_scan_i32(a.rows, a.rows, m, kScanInclusiveMax, a.temp, st);
   if (e != hipSuccess) return e;
-  // stable sort of the positions by stripe
-  hipLaunchKernelGGL(stripe_key_kernel, dim3(blocks_of(m)), dim3(256), 0, st, a.col, m, a.shift,
-                     a.key, a.pos);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  tb = a.temp_bytes;
-  e = hipcub::DeviceRadixSort::SortPairs(a.temp, tb, a.key, a.skey, a.pos, a.perm, (int)m, 0,
-                                         a.key_bits, st);
+  // stable sort of the nonzeros by stripe: one pass over the stripe digit of
+  // the column (the columns come out in stacked order, with their positions)
+  e = launch_radix_pass(reinterpret_cast<const uint32_t*>(a.col), nullptr,
+                        reinterpret_cast<uint32_t*>(a.col_s), a.perm, m, a.shift, a.key_bits,
+                        a.temp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(stripe_gather_kernel, dim3(blocks_of(m)), dim3(256), 0, st, a.perm, a.col,
-                     a.rows, a.skey, m, a.col_s, a.row_s, a.flag);
+  hipLaunchKernelGGL(stripe_gather_kernel, dim3(blocks_of(m)), dim3(256), 0, st, a.perm, a.rows,
+                     a.col_s, a.shift, m, a.row_s, a.flag);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  tb = a.temp_bytes;
-  e = hipcub::DeviceScan::ExclusiveSum(a.temp, tb, a.flag, a.vidx, (int)m, st);
-  return e;
+  return launch_scan_i32(a.flag, a.vidx, m, kScanExclusiveSum, a.temp, st);
 }
 
 hipError_t launch_stripe_rows(const StripeSplitArgs& a, int64_t nv, hipStream_t st) {
   hipError_t e;
   hipLaunchKernelGGL(vrow_emit_kernel, dim3(blocks_of(a.m)), dim3(256), 0, st, a.flag, a.vidx,
-                     a.row_s, a.skey, a.m, a.vrow_ptr, a.vrow_row, a.vrow_stripe);
+                     a.row_s, a.col_s, a.shift, a.m, a.vrow_ptr, a.vrow_row, a.vrow_stripe);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(store_i32_kernel, dim3(1), dim3(64), 0, st, a.vrow_ptr + nv, (int32_t)a.m);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -235,47 +193,11 @@ hipError_t launch_stripe_rows(const StripeSplitArgs& a, int64_t nv, hipStream_t 
   hipLaunchKernelGGL(popcount_kernel, dim3(blocks_of(nw)), dim3(256), 0, st, a.sw, a.stripes,
                      a.words, a.wcnt);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  size_t tb = a.temp_bytes;
-  e = hipcub::DeviceScan::ExclusiveSum(a.temp, tb, a.wcnt, a.rank, (int)nw, st);
+  e = launch_scan_i32(a.wcnt, a.rank, nw, kScanExclusiveSum, a.temp, st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(rank_store_kernel, dim3(blocks_of(nw)), dim3(256), 0, st, a.rank, a.stripes,
                      a.words, a.sw);
   return hipGetLastError();
-}
-
-hipError_t launch_stripe_hot(const int32_t* top_cols, int32_t taken, void* temp,
-                             size_t temp_bytes, int32_t* cols_sorted, int32_t* slot_of,
-                             int32_t* hot_cols, hipStream_t st) {
-  if (taken <= 0) return hipSuccess;
-  // slots in column order: the hot-value gathers then walk x in order
-  hipError_t e = hipcub::DeviceRadixSort::SortKeys(temp, temp_bytes, top_cols, cols_sorted,
-                                                   (int)taken, 0, 32, st);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(slot_assign_kernel, dim3(blocks_of(taken)), dim3(256), 0, st, cols_sorted,
-                     taken, slot_of, hot_cols);
-  return hipGetLastError();
-}
-
-hipError_t stripe_rank_bytes(int64_t n, size_t* bytes) {
-  size_t a = 0, b = 0;
-  hipError_t e = hipcub::DeviceRadixSort::SortPairsDescending(
-      nullptr, a, (const int32_t*)nullptr, (int32_t*)nullptr, (const int32_t*)nullptr,
-      (int32_t*)nullptr, (int)n);
-  if (e != hipSuccess) return e;
-  e = hipcub::DeviceRadixSort::SortKeys(nullptr, b, (const int32_t*)nullptr, (int32_t*)nullptr,
-                                        (int)n, 0, 32);
-  *bytes = a > b ? a : b;
-  return e;
-}
-
-hipError_t launch_stripe_rank_columns(const int32_t* counts, int64_t n, void* temp,
-                                      size_t temp_bytes, int32_t* iota, int32_t* counts_sorted,
-                                      int32_t* cols_sorted, hipStream_t st) {
-  hipLaunchKernelGGL(iota32_kernel, dim3(blocks_of(n)), dim3(256), 0, st, iota, n);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return hipcub::DeviceRadixSort::SortPairsDescending(temp, temp_bytes, counts, counts_sorted,
-                                                      iota, cols_sorted, (int)n, 0, 32, st);
 }
 
 template <typename V, int S>
