@@ -73,7 +73,9 @@ typedef struct {
                               concentrate their nonzeros on few columns.  -1 = automatic
                               (wave commit only: largest cache that fits one block per
                               CU, kept only when the hot columns hold >= 20 % of the
-                              nonzeros; the block kernel gets none), 0 = off,
+                              nonzeros and the plan has at least 4 tiles per wavefront
+                              of one block per CU -- a smaller plan cannot amortise the
+                              copy into LDS; the block kernel gets none), 0 = off,
                               k > 0 = at most k columns (MERBIT_EUNSUPPORTED if k values
                               do not fit in LDS).  With the cache the plan owns a
                               recoded copy of col_ind (int32[nnz]) and each SpMV first

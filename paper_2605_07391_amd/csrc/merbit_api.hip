@@ -238,6 +238,8 @@ int64_t hot_cap_lds(const merbit_plan* p) {
   return (cap / 256) * 256;
 }
 
+constexpr int64_t kHotMinTilesPerWave = 4;
+
 static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
   p->hot_n = 0;
   if (cap_req == 0 || p->nnz == 0 || p->n_cols == 0) return MERBIT_OK;
@@ -246,6 +248,15 @@ static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
   // every wavefront of a block wait for the slowest, which measured slower
   // than no cache at every size (R-MAT 22).  An explicit size is honoured.
   if (cap_req < 0 && p->commit != MERBIT_COMMIT_WAVE) return MERBIT_OK;
+  // Nor for a plan too small to amortise the fill: with fewer than
+  // kHotMinTilesPerWave tiles per wavefront of one block per CU, each block
+  // copies x into LDS for about one tile of work (the 10,000-vertex
+  // Chung-Lu matrix: 7.3 instead of 8.9 us per SpMV without the cache).
+  if (cap_req < 0) {
+    int cus = 0;
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, p->device));
+    if (p->tile_num < (int64_t)kHotMinTilesPerWave * cus * p->waves) return MERBIT_OK;
+  }
   if (!kernel_supported(p, true))
     return cap_req > 0 ? fail(MERBIT_EUNSUPPORTED, "hot cache not built for this block size")
                        : MERBIT_OK;

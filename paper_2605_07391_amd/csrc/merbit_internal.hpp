@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+
 namespace merbit {
 
 constexpr int kOmega = 64;                 // lanes per tile = CDNA wavefront size
@@ -225,6 +227,7 @@ struct SpmmArgs {
   void* Y;         // row stride ldy
   void* Z;         // dual buffer (row stride ldz) cleared at tile starts, or nullptr
   int64_t ldx, ldy, ldz;
+  int64_t x_rows;  // rows of X (the matrix's column count)
   int32_t k;       // columns in this slab, 1..64
   int32_t tile_num;
   int32_t lane_num;
@@ -252,6 +255,24 @@ hipError_t launch_spmv_wave(int dtype, int sigma, int waves, bool hot, size_t ho
                             const SpmvArgs& a, hipStream_t st, bool desc64 = false);
 hipError_t spmv_wave_set_hot_lds(int dtype, int sigma, int waves, size_t bytes,
                                  bool desc64 = false);
+
+constexpr int kMaxLdsDevices = 64;
+// Dynamic-LDS opt-in of one kernel instance.  The attribute belongs to the
+// instance (per device), not to a plan, so it only ever grows: a plan built
+// later with a smaller hot set must not shrink what an earlier plan of the
+// same instance launches with.
+inline hipError_t raise_dynamic_lds(const void* fn, size_t bytes, std::mutex& mu,
+                                    size_t* granted) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxLdsDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (bytes <= granted[dev]) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) granted[dev] = bytes;
+  return e;
+}
 
 // Hot-column cache.
 hipError_t hot_count_columns(const int32_t* col, int64_t nnz, int64_t n_cols, int sample,

@@ -245,8 +245,10 @@ static hipError_t launch_t(const SpmvArgs& a, size_t dyn, hipStream_t st) {
 
 template <typename V, int S, int W, bool H>
 static hipError_t set_lds_t(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&spmv_kernel<V, S, W, H>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  static std::mutex mu;
+  static size_t granted[kMaxLdsDevices] = {};
+  return raise_dynamic_lds(reinterpret_cast<const void*>(&spmv_kernel<V, S, W, H>), bytes, mu,
+                           granted);
 }
 
 struct KernelEntry {

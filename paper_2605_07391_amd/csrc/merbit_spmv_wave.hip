@@ -338,8 +338,10 @@ static hipError_t launch_wave_t(const SpmvArgs& a, size_t dyn, hipStream_t st) {
 
 template <typename V, int S, int W, bool H, typename D>
 static hipError_t set_wave_lds_t(size_t bytes) {
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&spmv_wave_kernel<V, S, W, H, D>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  static std::mutex mu;
+  static size_t granted[kMaxLdsDevices] = {};
+  return raise_dynamic_lds(reinterpret_cast<const void*>(&spmv_wave_kernel<V, S, W, H, D>), bytes,
+                           mu, granted);
 }
 
 struct WaveEntry {

@@ -48,15 +48,17 @@ def test_plan_bit_exact(name, sigma):
     plan.close()
 
 
-# hot: 0 = no LDS x cache, -1 = automatic (every column fits here), 37 = a
-# partial cache of the 37 most frequent columns
+# hot: 0 = no LDS x cache, -1 = automatic (off for matrices this small: too
+# few tiles per wavefront to amortise the fill), 37 = a partial cache of the
+# 37 most frequent columns, 4096 = every column of a matrix with at most
+# 4096 columns (the x-copy form), the 4096 most frequent otherwise
 # commit: "block" = b lanes buffered per block (the paper's layout), "wave" =
 # one commit unit per tile (b = 64), persistent blocks
 CONFIGS = [(1, 256, 0, "block"), (4, 128, -1, "block"), (7, 256, 37, "block"),
            (12, 256, -1, "block"), (12, 512, 0, "block"), (12, 1024, 37, "block"),
            (3, 128, 0, "block"), (2, 512, 37, "block"),
            (1, 256, 0, "wave"), (4, 256, -1, "wave"), (7, 1024, 37, "wave"),
-           (12, 1024, -1, "wave"), (12, 512, 0, "wave"), (5, 1024, -1, "wave"),
+           (12, 1024, 4096, "wave"), (12, 512, 0, "wave"), (5, 1024, -1, "wave"),
            (12, 256, 37, "wave"), (7, 512, 0, "wave")]
 
 
@@ -75,14 +77,14 @@ def test_spmv_parity(name, sigma, block_lanes, hot, commit, dtype):
                     commit=commit)
     info = plan.info()
     assert info["commit"] == {"block": 1, "wave": 2}[commit]
-    if hot == 0 or block_lanes == 128 or len(col) == 0 or (hot == -1 and commit == "block"):
-        assert info["hot_columns"] == 0  # automatic sizing enables the cache for the wave kernel
+    if hot in (0, -1) or block_lanes == 128 or len(col) == 0:
+        assert info["hot_columns"] == 0  # automatic sizing: these plans are too small
     elif hot == 37:
         assert 0 < info["hot_columns"] <= 37 or nc <= 37
-    elif nc <= 4096:
+    elif nc <= hot:
         assert info["hot_columns"] == nc  # every column fits in LDS
     else:
-        assert 0 <= info["hot_columns"] <= nc  # partial cache within the LDS budget
+        assert 0 < info["hot_columns"] <= hot  # partial cache of the most frequent columns
     y = torch.full((len(rp) - 1,), float("nan"), dtype=dtype, device=dev)
     plan.spmv(x, out=y)
     torch.cuda.synchronize()
@@ -138,6 +140,36 @@ def test_dual_buffer_chain(dtype, hot, commit):
         torch.cuda.synchronize()
         check_spmv(bufs[it % 2], rp, col, host_values(vals, dtype), x64, dtype, f"iter {it}")
     plan.close()
+
+
+@pytest.mark.parametrize("stripes", [0, 8], ids=["plain", "striped8"])
+def test_smaller_hot_set_later_keeps_earlier_plan_launchable(stripes):
+    """Two plans of one kernel instance: the second, built later with a much
+    smaller hot set, must not shrink the dynamic-LDS allowance the first one
+    launches with (the allowance belongs to the kernel, not to a plan)."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    dtype = torch.float32
+    rp, col, vals, nc = _matrix("chung_lu_10k", seed=3)
+    r, c, v = to_device(rp, col, vals, dtype, dev)
+    big = pkg.Plan(r, c, v, nc, commit="wave", stripes=stripes, hot_columns=8192)
+    rp2, col2, vals2, nc2 = _matrix("random2_1200x800", seed=4)
+    r2, c2, v2 = to_device(rp2, col2, vals2, dtype, dev)
+    small = pkg.Plan(r2, c2, v2, nc2, commit="wave", stripes=stripes, hot_columns=64)
+    ib, isml = big.info(), small.info()
+    assert (ib["sigma"], ib["block_lanes"], ib["desc_bits"]) == \
+        (isml["sigma"], isml["block_lanes"], isml["desc_bits"])
+    assert ib["lds_bytes"] > isml["lds_bytes"]
+    x64 = seeded_x(nc, 21, dtype)
+    y = big.spmv(torch.from_numpy(x64).to(dtype).to(dev))
+    torch.cuda.synchronize()
+    check_spmv(y, rp, col, host_values(vals, dtype), x64, dtype, "earlier plan")
+    x64b = seeded_x(nc2, 22, dtype)
+    y2 = small.spmv(torch.from_numpy(x64b).to(dtype).to(dev))
+    torch.cuda.synchronize()
+    check_spmv(y2, rp2, col2, host_values(vals2, dtype), x64b, dtype, "later plan")
+    big.close()
+    small.close()
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
