@@ -59,6 +59,13 @@ class DiffPageRank:
                            stripes=self.stripes, stream=stream)
         self.ones = torch.ones(n, dtype=dtype, device=dev)
         self.x0 = torch.full((n,), 1.0 / n, dtype=dtype, device=dev)
+        # the iterates live in buffers owned here, so every call hands the
+        # library the same pointers and its recorded HIP graphs of the
+        # iteration chunks replay from one training step to the next; results
+        # are copied out
+        self.x_work = torch.empty(n, dtype=dtype, device=dev)
+        self.g_work = torch.empty(n, dtype=dtype, device=dev)
+        self.lam_work = torch.empty(n, dtype=dtype, device=dev)
         self.last_forward = None   # (iterations, l1 change) of the last forward solve
         self.last_adjoint = None
 
@@ -121,9 +128,10 @@ class _PageRank(torch.autograd.Function):
         op.values.copy_(P)
         if op.plan_fwd is not op.plan:
             op.plan_fwd.set_values(op.values)
-        x = op.x0.clone()
-        it, res, _ = op.plan_fwd.pagerank(x, op.alpha, op.tol, op.max_iter, op.check_every,
-                                          stream=op.stream)
+        op.x_work.copy_(op.x0)
+        it, res, _ = op.plan_fwd.pagerank(op.x_work, op.alpha, op.tol, op.max_iter,
+                                          op.check_every, stream=op.stream)
+        x = op.x_work.clone()
         op.last_forward = (it, res)
         ctx.op = op
         ctx.save_for_backward(P, x)
@@ -136,9 +144,10 @@ class _PageRank(torch.autograd.Function):
         gx = gx.contiguous().to(op.dtype)
         gather_values(op.perm, P, out=op.values_t, stream=op.stream)   # P^T's values
         op.refresh_transpose_values()
-        lam = gx.clone()
-        it, res, _ = op.plan.pagerank_adjoint(op.plan_t, gx, lam, op.alpha, op.adj_tol,
-                                              op.adj_max_iter, op.check_every,
+        op.g_work.copy_(gx)
+        op.lam_work.copy_(gx)
+        it, res, _ = op.plan.pagerank_adjoint(op.plan_t, op.g_work, op.lam_work, op.alpha,
+                                              op.adj_tol, op.adj_max_iter, op.check_every,
                                               stream=op.stream)
         op.last_adjoint = (it, res)
-        return op.plan.sddmm(lam, x, op.alpha, stream=op.stream), None
+        return op.plan.sddmm(op.lam_work, x, op.alpha, stream=op.stream), None

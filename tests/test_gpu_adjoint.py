@@ -228,3 +228,41 @@ def test_rmat20_fp32_gradient_vs_fp64_oracle_and_finite_differences():
             assert abs(fd - g64[e]) <= 1e-4 * scale + 1e-3 * abs(g64[e]), (e, fd, g64[e])
     for op, _ in grads.values():
         op.close()
+
+
+@pytest.mark.parametrize("stripes", [0, 8])
+def test_training_steps_replay_the_recorded_graphs(stripes):
+    """Five gradient steps on the Chung-Lu graph: the forward power method and
+    the adjoint fixed point record their iteration-chunk HIP graphs in the
+    first step only and replay them afterwards, and every step's gradient
+    matches a fresh DiffPageRank (no graphs kept) on the same weights."""
+    dev = require_gpu()
+    g = workload("chung_lu_10k")
+    n, m = g["n_rows"], len(g["col"])
+    op = _diff_setup(g, torch.float32, dev, max_iter=20, check_every=10, stripes=stripes)
+    rng = np.random.default_rng(11)
+    w = torch.tensor(0.5 + rng.random(m), dtype=torch.float32, device=dev, requires_grad=True)
+    tgt = torch.from_numpy(rng.dirichlet(np.ones(n))).float().to(dev)
+    # forward graphs live on the forward plan, adjoint graphs on the plan of P^T
+    plans = [op.plan_fwd, op.plan_t]
+    captures, replays = [], []
+    for step in range(5):
+        x = op(w)
+        loss = ((x - tgt) ** 2).sum()
+        loss.backward()
+        grad = w.grad.detach().clone()
+        ref_op = _diff_setup(g, torch.float32, dev, max_iter=20, check_every=10, stripes=stripes)
+        w_ref = w.detach().clone().requires_grad_(True)
+        ((ref_op(w_ref) - tgt) ** 2).sum().backward()
+        ref_op.close()
+        scale = w_ref.grad.abs().max().item()
+        assert (grad - w_ref.grad).abs().max().item() <= 1e-4 * scale, f"step {step}"
+        captures.append([p.info()["graph_captures"] for p in plans])
+        replays.append([p.info()["graph_replays"] for p in plans])
+        with torch.no_grad():
+            w -= 2e3 * w.grad
+            w.clamp_(min=0.1)
+        w.grad = None
+    assert all(c == captures[0] for c in captures[1:]), captures
+    assert all(r1 > r0 for r0, r1 in zip(replays[0], replays[-1])), replays
+    op.close()
