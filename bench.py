@@ -98,6 +98,59 @@ def load_traffic(workload: str, dtype: str, info: dict):
     return None
 
 
+def traffic_record(workload: str, dtype: str, info: dict, alg_bytes: float, fetch_dir: str,
+                   write_dir: str, copy_fetch_dir: str, copy_write_dir: str) -> dict:
+    """HBM bytes of one SpMV (fused launch + stripe sum) from four rocprofv3
+    --pmc runs (FETCH_SIZE and WRITE_SIZE of the bench at this configuration,
+    and of --copy-calibration-mib 1024), each counter scaled by what it reads
+    for the plain 1 GiB copy; the record load_traffic() matches against."""
+    import collections
+    import csv
+
+    def per_dispatch(d, counter):
+        acc = collections.defaultdict(lambda: collections.defaultdict(float))
+        with open(os.path.join(d, "run_counter_collection.csv")) as f:
+            for r in csv.DictReader(f):
+                if r["Counter_Name"] == counter:
+                    acc[r["Kernel_Name"]][r["Dispatch_Id"]] += float(r["Counter_Value"])
+        return acc
+
+    def mean_of(acc, name):
+        keys = [k for k in acc if name in k]
+        if len(keys) != 1:
+            raise RuntimeError(f"{name}: {len(keys)} matching kernels")
+        vals = list(acc[keys[0]].values())
+        return sum(vals) / len(vals), len(vals)
+
+    stripes = info["stripes"]
+    names = [kernel_instance(info)] + (
+        [f"merbit::stripe_combine_kernel<{'float' if info['dtype'] == 0 else 'double'}, "
+         f"{stripes}>"] if stripes > 1 else [])
+    fetch, write = per_dispatch(fetch_dir, "FETCH_SIZE"), per_dispatch(write_dir, "WRITE_SIZE")
+    f_kib = [mean_of(fetch, k) for k in names]
+    w_kib = [mean_of(write, k) for k in names]
+    copy_f, _ = mean_of(per_dispatch(copy_fetch_dir, "FETCH_SIZE"), "copyBuffer")
+    copy_w, _ = mean_of(per_dispatch(copy_write_dir, "WRITE_SIZE"), "copyBuffer")
+    nbytes = 1 << 30
+    ff, wf = nbytes / 1024 / copy_f, nbytes / 1024 / copy_w
+    f_raw, w_raw = sum(v for v, _ in f_kib), sum(v for v, _ in w_kib)
+    rec = {"kernel": names[0], "workload": workload, "dtype": dtype, "stripes": stripes,
+           "combine_kernel": names[1] if stripes > 1 else None,
+           "spmv_source_files": [src for _, src in spmv_kernels(info["commit"], stripes)],
+           "spmv_source_sha256_16": spmv_source_hash(info["commit"], stripes),
+           "fetch_size_kib_per_spmv_raw": round(f_raw, 1),
+           "write_size_kib_per_spmv_raw": round(w_raw, 1),
+           "launches_counted": [f_kib[0][1], w_kib[0][1]],
+           "copy_calibration": {"bytes_copied": nbytes, "fetch_kib_raw": round(copy_f, 1),
+                                "write_kib_raw": round(copy_w, 1), "fetch_factor": round(ff, 5),
+                                "write_factor": round(wf, 5)},
+           "hbm_fetch_bytes_per_launch": int(f_raw * 1024 * ff),
+           "hbm_write_bytes_per_launch": int(w_raw * 1024 * wf)}
+    rec["hbm_bytes_per_launch"] = rec["hbm_fetch_bytes_per_launch"] + rec["hbm_write_bytes_per_launch"]
+    rec["algorithmic_bytes_per_launch"] = int(alg_bytes)
+    return rec
+
+
 def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes: int,
             alpha: float, hot_columns: int = -1, commit: str = "auto", blocks_per_cu: int = 0,
             tune: bool = False, stripes: int = 0, desc_bits: int = 32):
@@ -260,7 +313,10 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
 def run_ppr(w, k: int, steps: int, warmup: int, alpha: float):
     """Personalised PageRank for k sources at once on the workload graph
     (FP32): a step is one SpMM over k right-hand sides plus the per-column
-    update.  Returns step and SpMM-kernel times."""
+    update, on a plan whose sigma the autotuner measured fastest for the SpMM.
+    Returns step and SpMM-kernel times and the SpMM's bandwidth against its
+    compulsory bytes (A once, X once, Y once, the plan's tiles and
+    descriptors)."""
     import torch
 
     import graphgen
@@ -270,7 +326,10 @@ def run_ppr(w, k: int, steps: int, warmup: int, alpha: float):
     r = torch.from_numpy(w["row_ptr"]).to(dev)
     c = torch.from_numpy(w["col"]).to(dev)
     v = torch.from_numpy(w["values"]).float().to(dev)
-    plan = pkg.Plan(r, c, v, n, validate=False)
+    # sigma of the SpMM by measurement on this matrix (untimed)
+    best, table = pkg.tune(r, c, v, n, sigmas=list(range(4, 13)), block_lanes=[256], reps=5,
+                           rhs=k)
+    plan = pkg.Plan(r, c, v, n, validate=False, sigma=best["sigma"])
     src = graphgen.ppr_sources(n, k, seed=4)
     # untimed: warm-up iterations in the timed run's chunk shape, so its HIP
     # graph is recorded before the clock starts
@@ -290,19 +349,32 @@ def run_ppr(w, k: int, steps: int, warmup: int, alpha: float):
     plan.profile_enable(True)
     plan.pagerank_personalized(src, X=X, alpha=alpha, max_iter=steps)
     launches, kernel_ms = plan.profile_read()
+    info = plan.info()
     plan.close()
     spmm_ms = kernel_ms / max(launches, 1)
     nnz = w["nnz"]
+    # compulsory bytes: the single-vector count with x and y widened to k columns
+    alg = algorithmic_bytes(info, 4) + (k - 1) * 4 * (info["n_cols"] + info["n_rows"])
+    ach = alg / (spmm_ms * 1e-3) / 1e9
     return {"k": k, "steps": steps, "ms_per_step": round(step_ms, 4),
-            "spmm_us": round(spmm_ms * 1e3, 1),
+            "spmm_us": round(spmm_ms * 1e3, 1), "sigma": best["sigma"],
+            "tuning_spmm_us": {f"s{a}": round(t, 1) for (a, _), t in table.items()},
             "gnz_rhs_per_s": round(nnz * k / (spmm_ms * 1e-3) / 1e9, 2),
             "step_gnz_rhs_per_s": round(nnz * k / (step_ms * 1e-3) / 1e9, 2),
-            "max_mass_error": mass_err, "sources_seed": 4}
+            "max_mass_error": mass_err, "sources_seed": 4,
+            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                         "kernel": f"merbit::spmm_kernel<float, {best['sigma']}>",
+                         "alg_bytes_per_launch": int(alg),
+                         "mean_launch_us": round(spmm_ms * 1e3, 1)}}
 
 
-def run_multi(steps: int, warmup: int, alpha: float, stripes: int = 0, plan_kw=None):
+def run_multi(steps: int, warmup: int, alpha: float, stripes: int = 0, plan_kw=None,
+              tune: bool = False):
     """PageRank of the 256 Chung-Lu graphs stored on one diagonal, FP32, one
-    plan: a step is one fused SpMV over all graphs plus the per-graph update."""
+    plan: a step is one fused SpMV over all graphs plus the per-graph update.
+    tune: sigma and block size of the striped plan with 64-bit descriptors
+    measured on this matrix (the autotuner, untimed) instead of plan_kw."""
     import numpy as np
     import torch
 
@@ -314,6 +386,13 @@ def run_multi(steps: int, warmup: int, alpha: float, stripes: int = 0, plan_kw=N
     r = torch.from_numpy(w["row_ptr"]).to(dev)
     c = torch.from_numpy(w["col"]).to(dev)
     v = torch.from_numpy(w["values"]).float().to(dev)
+    tuning = None
+    if tune:
+        best, table = pkg.tune(r, c, v, n, reps=10, commit="wave", desc_bits=64,
+                               block_lanes=[256, 512], stripes=stripes)
+        plan_kw = {"sigma": best["sigma"], "block_lanes": best["block_lanes"], "desc_bits": 64,
+                   "commit": "wave"}
+        tuning = {f"s{a}_b{b}": round(t, 1) for (a, b), t in table.items()}
     plan = pkg.Plan(r, c, v, n, validate=False, stripes=stripes, **(plan_kw or {}))
     sizes = np.diff(gp)
     x0 = torch.from_numpy(np.repeat(1.0 / sizes, sizes)).float().to(dev)
@@ -338,7 +417,8 @@ def run_multi(steps: int, warmup: int, alpha: float, stripes: int = 0, plan_kw=N
             "ms_per_step": round(step_ms, 4), "spmv_us": round(spmv_ms * 1e3, 1),
             "gnzs": round(nnz / (step_ms * 1e-3) / 1e9, 3),
             "spmv_gnzs": round(nnz / (spmv_ms * 1e-3) / 1e9, 3),
-            "stripes": stripes, "plan": plan_kw or "default", "seed": w["meta"]["seed"]}
+            "stripes": stripes, "plan": plan_kw or "default", "tuning_us_per_spmv": tuning,
+            "seed": w["meta"]["seed"]}
 
 
 def tuned_kw(info) -> dict:
@@ -473,7 +553,9 @@ def run_c1(steps: int, alpha: float):
     """PageRank on the 10,000-vertex Chung-Lu graph (FP32, 20 power
     iterations per call, x0 = 1/n; paper Sec. 5.5.1): the matrix is cache
     resident, so this reports time per iteration and per 20-iteration call
-    (HIP graphs recorded before the clock), not a bandwidth fraction."""
+    (HIP graphs recorded before the clock), not a bandwidth fraction.  The
+    plan takes the sigma and block size the autotuner measures fastest on
+    this matrix."""
     import torch
 
     import graphgen
@@ -484,9 +566,14 @@ def run_c1(steps: int, alpha: float):
     r = torch.from_numpy(w["row_ptr"]).to(dev)
     c = torch.from_numpy(w["col"]).to(dev)
     v = torch.from_numpy(w["values"]).float().to(dev)
+    # sigma and block size by measurement on this matrix (the tuner's
+    # candidates, untimed; the plan build is timed on its own below)
+    best, table = pkg.tune(r, c, v, n, sigmas=list(range(2, 13)), block_lanes=[256, 512, 1024],
+                           reps=20)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    plan = pkg.Plan(r, c, v, n, validate=False)
+    plan = pkg.Plan(r, c, v, n, validate=False, sigma=best["sigma"],
+                    block_lanes=best["block_lanes"])
     e1.record()
     torch.cuda.synchronize()
     plan_ms = e0.elapsed_time(e1)
@@ -522,7 +609,9 @@ def run_c1(steps: int, alpha: float):
             "us_per_iteration": round(med * 1e3 / iters, 2),
             "spmv_us": round(kernel_ms * 1e3 / max(launches, 1), 2),
             "plan_ms": round(plan_ms, 3), "sigma": info["sigma"],
-            "block_lanes": info["block_lanes"], "rank_mass": round(mass, 7),
+            "block_lanes": info["block_lanes"], "hot_columns": info["hot_columns"],
+            "tuning_us_per_spmv": {f"s{a}_b{b}": round(t, 2) for (a, b), t in table.items()},
+            "rank_mass": round(mass, 7),
             "graph_replays_in_timed_calls": g1["graph_replays"] - g0["graph_replays"],
             "graph_captures_in_timed_calls": g1["graph_captures"] - g0["graph_captures"],
             "seed": w["meta"]["seed"]}
@@ -644,7 +733,33 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="only run a plain device copy of this many MiB (5 times), used to "
                          "scale rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--traffic-record", nargs=5,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR", "OUT"),
+                    help="only build the plan of the given configuration and write its HBM "
+                         "traffic record from four rocprofv3 --pmc output directories")
     args = ap.parse_args()
+    if args.traffic_record:
+        import torch
+
+        import graphgen
+        import paper_2605_07391_amd as pkg
+        w = graphgen.workload(args.workload)
+        dt = torch.float32 if args.dtype == "f32" else torch.float64
+        dev = torch.device("cuda:0")
+        plan = pkg.Plan(torch.from_numpy(w["row_ptr"]).to(dev), torch.from_numpy(w["col"]).to(dev),
+                        torch.from_numpy(w["values"]).to(dt).to(dev), w["n_rows"],
+                        sigma=args.sigma, block_lanes=args.block_lanes, commit=args.commit,
+                        hot_columns=args.hot_columns, stripes=max(args.stripes, 0),
+                        desc_bits=args.desc_bits, validate=False)
+        info = plan.info()
+        plan.close()
+        rec = traffic_record(args.workload, args.dtype, info,
+                             algorithmic_bytes(info, 4 if args.dtype == "f32" else 8),
+                             *args.traffic_record[:4])
+        with open(args.traffic_record[4], "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec), flush=True)
+        return
     if args.copy_calibration_mib > 0:
         import torch
         nbytes = args.copy_calibration_mib << 20
@@ -701,10 +816,8 @@ def main():
         ppr["vs_plain_spmv"] = round(ppr["gnz_rhs_per_s"] / main_run["spmv_gnzs"], 3)
         print(f"[bench] ppr64: step {ppr['ms_per_step']:.3f} ms, spmm {ppr['spmm_us']:.1f} us",
               file=sys.stderr, flush=True)
-        # the striped runs take the (sigma, lanes, descriptor width) tuned on the
-        # R-MAT matrix of the same value type
-        multi = run_multi(args.batched_steps, 2, args.alpha, stripes=8,
-                          plan_kw=tuned_kw(main_run["info"]) if args.dtype == "f32" else None)
+        # the striped plan of the 256 graphs is tuned on its own matrix
+        multi = run_multi(args.batched_steps, 2, args.alpha, stripes=8, tune=True)
         multi_plain = run_multi(args.batched_steps, 2, args.alpha)
         multi["one_plan_without_stripes"] = {k: multi_plain[k] for k in
                                              ("ms_per_step", "spmv_us", "gnzs", "spmv_gnzs")}

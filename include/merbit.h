@@ -116,6 +116,8 @@ typedef struct {
                               transpose and SDDMM return MERBIT_EUNSUPPORTED on such a
                               plan; SpMV, PageRank, multi-graph PageRank, BiCGSTAB and
                               the adjoint fixed point run on it.                        */
+    int32_t tune_rhs;      /* merbit_tune only (plans ignore it): 0 = time the SpMV;
+                              k in 1..64 = time merbit_spmm with k right-hand sides    */
 } merbit_opts_t;
 
 typedef struct merbit_plan merbit_plan;
@@ -393,7 +395,10 @@ int merbit_bicgstab(merbit_plan* plan, const void* b, void* x_inout, double tol,
  * every candidate pair a plan is built from the given CSR (device pointers as
  * in merbit_plan_create; validation off), the dual-buffer SpMV is launched
  * 2 + reps times on `stream` with a constant nonzero x, and the mean time of
- * the last reps launches is taken.
+ * the last reps launches is taken.  With opts_inout->tune_rhs = k > 0 the
+ * timed call is merbit_spmm over k right-hand sides (X constant, row-major
+ * n_cols x k; the SpMM kernel's block size is fixed, so block_lanes only
+ * repeats the measurement).
  *   sigmas, n_sigmas      host int32 candidates; NULL or n <= 0 = 7..12 (F32),
  *                         4..10 (F64)
  *   block_lanes, n_blocks host int32 candidates; NULL or n <= 0 = 256, 512, 1024

@@ -23,6 +23,7 @@ static SpmmArgs spmm_args(const merbit_plan* p, const void* X, int64_t ldx, void
   a.ldx = ldx;
   a.ldy = ldy;
   a.ldz = ldz;
+  a.x_rows = p->n_cols;
   a.k = k;
   a.tile_num = (int32_t)p->tile_num;
   a.lane_num = (int32_t)p->lane_num;

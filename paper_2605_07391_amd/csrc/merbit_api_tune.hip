@@ -30,8 +30,11 @@ int merbit_tune(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* row_
     block_lanes = def_blocks;
     n_blocks = 3;
   }
+  const int rhs = opts_inout->tune_rhs;
+  if (rhs < 0 || rhs > 64) return fail(MERBIT_EINVAL, "tune_rhs must be in 0..64");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t vs = vsize(dtype);
+  const size_t width = rhs > 0 ? (size_t)rhs : 1;  // values per row of x / y
   void *x = nullptr, *y0 = nullptr, *y1 = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   auto cleanup = [&]() {
@@ -49,12 +52,12 @@ int merbit_tune(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* row_
       return fail_hip(#expr, _e);               \
     }                                           \
   } while (0)
-  TUNE_TRY(hipMalloc(&x, vs * (size_t)(n_cols > 0 ? n_cols : 1)));
-  TUNE_TRY(hipMalloc(&y0, vs * (size_t)(n_rows > 0 ? n_rows : 1)));
-  TUNE_TRY(hipMalloc(&y1, vs * (size_t)(n_rows > 0 ? n_rows : 1)));
+  TUNE_TRY(hipMalloc(&x, vs * width * (size_t)(n_cols > 0 ? n_cols : 1)));
+  TUNE_TRY(hipMalloc(&y0, vs * width * (size_t)(n_rows > 0 ? n_rows : 1)));
+  TUNE_TRY(hipMalloc(&y1, vs * width * (size_t)(n_rows > 0 ? n_rows : 1)));
   // x = 1.0f (F32) or the double with two 1.0f words (about 1.0000002, F64)
   TUNE_TRY(hipMemsetD32Async(reinterpret_cast<hipDeviceptr_t>(x), 0x3f800000u,
-                             (vs / 4) * (size_t)(n_cols > 0 ? n_cols : 1), st));
+                             (vs / 4) * width * (size_t)(n_cols > 0 ? n_cols : 1), st));
   TUNE_TRY(hipEventCreate(&e0));
   TUNE_TRY(hipEventCreate(&e1));
   float best = -1.0f;
@@ -74,14 +77,16 @@ int merbit_tune(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* row_
         cleanup();
         return rc;
       }
-      int r2 = merbit_zero_boundary(p, y0, stream);
+      int r2 = rhs > 0 ? MERBIT_OK : merbit_zero_boundary(p, y0, stream);
       void* ys[2] = {y0, y1};
       for (int k = 0; r2 == MERBIT_OK && k < 2 + reps; ++k) {
         if (k == 2) {
           hipError_t e = hipEventRecord(e0, st);
           if (e != hipSuccess) r2 = fail_hip("hipEventRecord", e);
         }
-        if (r2 == MERBIT_OK) r2 = run_fused(p, x, ys[k & 1], ys[(k + 1) & 1], st);
+        if (r2 != MERBIT_OK) break;
+        r2 = rhs > 0 ? merbit_spmm(p, x, rhs, ys[k & 1], rhs, rhs, stream)
+                     : run_fused(p, x, ys[k & 1], ys[(k + 1) & 1], st);
       }
       float ms = 0.0f;
       if (r2 == MERBIT_OK) {

@@ -7,23 +7,31 @@
 // tile's merge-path segment (Sec. 4.1) fixes its nonzeros [x_ws, x_we) and
 // rows [y_ws, y_we]; every nonzero is a 64-wide row operation
 // Y[row, :] += v * X[col, :], so each X access is one coalesced row load.
-//   1. col_ind / values of the tile are staged in LDS with coalesced loads;
-//   2. each lane decodes its 32-bit descriptor (Sec. 4.1.1) and writes, for
-//      each of its right steps, the row (relative to the tile) of that
-//      nonzero: nonzero x_off + r of lane j lies in row y_off + (downs before
-//      it) -- no scan is needed;
-//   3. the wavefront walks the tile's nonzeros in order, with the X rows of
-//      the next kChunk nonzeros in flight while the current ones are summed;
-//      a change of row finishes the previous one.
-// Rows strictly inside the tile are stored; the tile's first and last rows
-// (shared with neighbouring tiles) are added atomically to Y, which is zero
-// there before the launch.  Empty rows inside the tile are written as 0.
+//   1. each lane decodes its descriptor (Sec. 4.1.1) and writes, for each of
+//      its right steps, the row (relative to the tile) of that nonzero into
+//      LDS: nonzero x_off + r of lane j lies in row y_off + (downs before it);
+//   2. the tile's nonzeros are taken 64 at a time, lane l holding nonzero
+//      q0 + l (coalesced loads of col_ind / values, its row from LDS, the
+//      byte offset of its X row); one ballot marks the nonzeros that start a
+//      new row;
+//   3. the wavefront then walks those 64 nonzeros in order: each X row load
+//      takes its offset from the owning lane (a lane read into a scalar
+//      register, used as the buffer load's scalar offset), kSpmmGroup rows
+//      are in flight before the first is used, each product is one fused
+//      multiply-add with the value read from its lane, and a marked nonzero
+//      first finishes the previous row.
+// Per nonzero the wavefront spends one load and a few lane reads, not an
+// LDS round trip, so the X row loads (the bulk of the traffic) stay
+// back to back.  Rows strictly inside the tile are stored; the tile's first
+// and last rows (shared with neighbouring tiles) are added atomically to Y,
+// which is zero there before the launch.  Empty rows inside the tile are
+// written as 0.
 #include "merbit_internal.hpp"
 
 namespace merbit {
 
 constexpr int kSpmmWaves = 4;
-constexpr int kChunk = 16;
+constexpr int kSpmmGroup = 16;
 
 template <typename V>
 __device__ __forceinline__ void spmm_commit(V* Y, int64_t ld, int row_abs, int rel, int last_rel,
@@ -33,26 +41,116 @@ __device__ __forceinline__ void spmm_commit(V* Y, int64_t ld, int row_abs, int r
   if (rel == 0 || rel == last_rel) {
     if (row_abs < n_rows) global_add(p, acc);  // shared with a neighbouring tile
   } else {
-    *p = acc;
+    __builtin_nontemporal_store(acc, p);  // written once, not read here again
+  }
+}
+
+// value of lane `lane` of v (lane uniform), in scalar registers
+__device__ __forceinline__ int lane_value(int v, int lane) {
+  return __builtin_amdgcn_readlane(v, lane);
+}
+__device__ __forceinline__ float lane_value(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+__device__ __forceinline__ double lane_value(double v, int lane) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// word 3 of a raw (unformatted, stride 0) buffer resource on gfx950
+constexpr int kSpmmBufferWord3 = 0x00020000;
+
+// One X row element per lane for the nonzero held by lane q of this chunk:
+// through a buffer resource with the row's byte offset as the scalar offset
+// (X no larger than 2 GiB), or through a 64-bit scalar row address.
+// Every lane loads (no branch, so the group's loads go out back to back):
+// lanes at or past k read a neighbouring element of the same row, or 0 past
+// the end of X (buffer range check), and their values are never stored.
+template <typename V, bool BUF>
+__device__ __forceinline__ V load_x_row(__amdgpu_buffer_rsrc_t rx, const V* __restrict__ X,
+                                        int64_t ldx, uint32_t off_l, int c_l, int q, int lane) {
+  if constexpr (BUF) {
+    const int soff = __builtin_amdgcn_readlane((int)off_l, q);
+    if constexpr (sizeof(V) == 4)
+      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b32(rx, lane * 4, soff, 0));
+    else
+      return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b64(rx, lane * 8, soff, 0));
+  } else {
+    const V* __restrict__ xr = X + (int64_t)lane_value(c_l, q) * ldx;
+    return xr[lane];
+  }
+}
+
+template <typename V, int SIGMA, bool BUF>
+__device__ __forceinline__ void spmm_walk(const SpmmArgs& a, const int32_t* __restrict__ wrow,
+                                          int x_ws, int x_se, int y_ws, int last_rel, int lid,
+                                          bool lane_on, V& acc, int& cur) {
+  const V* __restrict__ X = static_cast<const V*>(a.X);
+  V* __restrict__ Y = static_cast<V*>(a.Y);
+  const int32_t* __restrict__ col = a.col + x_ws;
+  const V* __restrict__ val = static_cast<const V*>(a.val) + x_ws;
+  const int64_t ldx = a.ldx, ldy = a.ldy;
+  // (unused by the 64-bit path)
+  const int bytes = BUF ? (int)((((int64_t)a.x_rows - 1) * ldx + a.k) * (int64_t)sizeof(V)) : 0;
+  const __amdgpu_buffer_rsrc_t rx =
+      __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, bytes, kSpmmBufferWord3);
+  const uint32_t row_bytes = (uint32_t)(ldx * (int64_t)sizeof(V));
+  // the 64-bit path keeps lanes past k on the row's last column
+  const int lane = BUF ? lid : min(lid, a.k - 1);
+  for (int q0 = 0; q0 < x_se; q0 += kOmega) {
+    const int ql = q0 + lid;
+    const bool valid = ql < x_se;
+    // the matrix stream is read once: non-temporal, so it does not push the
+    // reused X rows out of L2
+    const int c_l = valid ? __builtin_nontemporal_load(col + ql) : 0;
+    const V v_l = valid ? __builtin_nontemporal_load(val + ql) : V(0);
+    const int r_l = valid ? wrow[ql] : 0;
+    const uint32_t off_l = (uint32_t)c_l * row_bytes;
+    // bit l: nonzero q0 + l lies in another row than the nonzero before it
+    // (every lane takes part in the shuffle: a lane outside it gives no value)
+    const int up = __shfl_up(r_l, 1, kOmega);
+    const int prev = lid == 0 ? cur : up;
+    const unsigned long long starts = __ballot(valid && r_l != prev);
+    const int cnt = min(kOmega, x_se - q0);
+    for (int u0 = 0; u0 < cnt; u0 += kSpmmGroup) {
+      V xr[kSpmmGroup];
+#pragma unroll
+      for (int u = 0; u < kSpmmGroup; ++u) {
+        const int q = min(u0 + u, cnt - 1);  // past the end: a repeat, never used
+        xr[u] = load_x_row<V, BUF>(rx, X, ldx, off_l, c_l, q, lane);
+      }
+#pragma unroll
+      for (int u = 0; u < kSpmmGroup; ++u) {
+        const int q = u0 + u;
+        if (q < cnt) {
+          if ((starts >> q) & 1ull) {
+            const int r = lane_value(r_l, q);
+            spmm_commit(Y, ldy, y_ws + cur, cur, last_rel, a.n_rows, acc, lane_on, lid);
+            for (int e = cur + 1; e < r; ++e)  // empty rows strictly inside the tile
+              if (lane_on) Y[(int64_t)(y_ws + e) * ldy + lid] = V(0);
+            cur = r;
+            acc = V(0);
+          }
+          acc += lane_value(v_l, q) * xr[u];
+        }
+      }
+    }
   }
 }
 
 template <typename V, int SIGMA>
 __global__ __launch_bounds__(kSpmmWaves * 64) void spmm_kernel(SpmmArgs a) {
   constexpr int WLDS = kOmega * SIGMA;
-  __shared__ int32_t s_col[kSpmmWaves * WLDS];
-  __shared__ V s_val[kSpmmWaves * WLDS];
   __shared__ int32_t s_row[kSpmmWaves * WLDS];
 
   const int lid = threadIdx.x & (kOmega - 1);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kOmega);
   const int t = blockIdx.x * kSpmmWaves + wid;
   if (t >= a.tile_num) return;  // no block-wide synchronisation in this kernel
-  int32_t* wcol = s_col + wid * WLDS;
-  V* wval = s_val + wid * WLDS;
   int32_t* wrow = s_row + wid * WLDS;
 
-  const V* __restrict__ X = static_cast<const V*>(a.X);
   V* __restrict__ Y = static_cast<V*>(a.Y);
   const bool lane_on = lid < a.k;
   const int x_ws = a.tile_x[t];
@@ -62,44 +160,17 @@ __global__ __launch_bounds__(kSpmmWaves * 64) void spmm_kernel(SpmmArgs a) {
   const int y_we = (int)(a.tile_y[t + 1] & kRowMask);
   const int last_rel = y_we - y_ws;
 
-  if (x_se > 0) {
-    const int32_t* __restrict__ tc = a.col + x_ws;
-    const V* __restrict__ tv = static_cast<const V*>(a.val) + x_ws;
-    for (int q = lid; q < x_se; q += kOmega) {
-      wcol[q] = __builtin_nontemporal_load(tc + q);
-      wval[q] = __builtin_nontemporal_load(tv + q);
-    }
-  }
   tile_nz_rows<SIGMA>(a.lane_desc, a.lane_num, a.path_len, t, tyw, x_se, lid, wrow);
   wave_lds_sync();
 
-  // walk the nonzeros in order; X rows of a chunk are loaded before use
   V acc = V(0);
   int cur = 0;  // current row, relative to y_ws
-  const int64_t ldx = a.ldx, ldy = a.ldy;
-  for (int q0 = 0; q0 < x_se; q0 += kChunk) {
-    V xr[kChunk];
-#pragma unroll
-    for (int u = 0; u < kChunk; ++u) {
-      const int q = min(q0 + u, x_se - 1);
-      xr[u] = lane_on ? X[(int64_t)wcol[q] * ldx + lid] : V(0);
-    }
-#pragma unroll
-    for (int u = 0; u < kChunk; ++u) {
-      const int q = q0 + u;
-      if (q < x_se) {
-        const int r = wrow[q];
-        if (r != cur) {
-          spmm_commit(Y, ldy, y_ws + cur, cur, last_rel, a.n_rows, acc, lane_on, lid);
-          for (int e = cur + 1; e < r; ++e)  // empty rows strictly inside the tile
-            if (lane_on) Y[(int64_t)(y_ws + e) * ldy + lid] = V(0);
-          cur = r;
-          acc = V(0);
-        }
-        acc += wval[q] * xr[u];
-      }
-    }
-  }
+  const bool buf = ((int64_t)a.x_rows * a.ldx) * (int64_t)sizeof(V) < ((int64_t)1 << 31);
+  if (buf)
+    spmm_walk<V, SIGMA, true>(a, wrow, x_ws, x_se, y_ws, last_rel, lid, lane_on, acc, cur);
+  else
+    spmm_walk<V, SIGMA, false>(a, wrow, x_ws, x_se, y_ws, last_rel, lid, lane_on, acc, cur);
+  const int64_t ldy = a.ldy;
   if (x_se > 0) spmm_commit(Y, ldy, y_ws + cur, cur, last_rel, a.n_rows, acc, lane_on, lid);
   // rows after the last nonzero and strictly inside the tile are empty
   for (int e = (x_se > 0 ? cur + 1 : 1); e < last_rel; ++e)

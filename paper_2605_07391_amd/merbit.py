@@ -54,7 +54,7 @@ class Opts(ctypes.Structure):
                 ("commit", ctypes.c_int32), ("hot_columns", ctypes.c_int32),
                 ("validate", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("eager_loops", ctypes.c_int32), ("desc_bits", ctypes.c_int32),
-                ("stripes", ctypes.c_int32)]
+                ("stripes", ctypes.c_int32), ("tune_rhs", ctypes.c_int32)]
 
 
 COMMIT_AUTO, COMMIT_BLOCK, COMMIT_WAVE = 0, 1, 2
@@ -497,9 +497,11 @@ def column_scale(col: torch.Tensor, a: torch.Tensor, s: torch.Tensor,
 
 def tune(row_ptr: torch.Tensor, col_ind: torch.Tensor, values: torch.Tensor, n_cols: int, *,
          sigmas=None, block_lanes=None, reps: int = 20, commit: str = "auto",
-         hot_columns: int = -1, desc_bits: int = 32, stripes: int = 0, stream=None):
-    """Time the fused SpMV for every (sigma, block_lanes) candidate on this
-    matrix.  Returns ({"sigma": s, "block_lanes": b}, {(s, b): mean us})."""
+         hot_columns: int = -1, desc_bits: int = 32, stripes: int = 0, rhs: int = 0,
+         stream=None):
+    """Time the fused SpMV (rhs = 0) or the SpMM over rhs right-hand sides
+    for every (sigma, block_lanes) candidate on this matrix.  Returns
+    ({"sigma": s, "block_lanes": b}, {(s, b): mean us})."""
     import numpy as np
     lib = load()
     code = _vdtype(values)
@@ -519,6 +521,7 @@ def tune(row_ptr: torch.Tensor, col_ind: torch.Tensor, values: torch.Tensor, n_c
     opts.hot_columns = hot_columns
     opts.desc_bits = desc_bits
     opts.stripes = stripes
+    opts.tune_rhs = rhs
     _check(lib.merbit_tune(n_rows, int(n_cols), col_ind.numel(),
                            _dev(row_ptr, torch.int32, "row_ptr"),
                            _dev(col_ind, torch.int32, "col_ind"),

@@ -101,3 +101,35 @@ def test_timed_pagerank_call_replays_recorded_graphs(warmup, steps):
     timed, _, _ = _pagerank_chunk_keys(buf, stacked, steps)
     assert set(timed) <= recorded
     assert len(recorded) <= 8  # the plan keeps eight graphs
+
+
+def _counter_csv(path, rows):
+    path.mkdir()
+    with open(path / "run_counter_collection.csv", "w") as f:
+        f.write('"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"\n')
+        for disp, name, ctr, val in rows:
+            f.write(f'{disp},"{name}","{ctr}",{val}\n')
+
+
+def test_traffic_record_from_counter_runs(tmp_path):
+    """FETCH / WRITE per SpMV = fused + stripe-sum launches, averaged over the
+    dispatches (summing the per-instance rows of one dispatch), scaled by the
+    1 GiB copy's counters."""
+    info = _info()
+    fused = "void " + bench.kernel_instance(info) + "(merbit::SpmvArgs)"
+    comb = "void merbit::stripe_combine_kernel<float, 8>(float const*, long)"
+    _counter_csv(tmp_path / "f", [(1, fused, "FETCH_SIZE", 100.0), (1, fused, "FETCH_SIZE", 50.0),
+                                  (2, fused, "FETCH_SIZE", 170.0), (3, comb, "FETCH_SIZE", 10.0),
+                                  (4, "other", "FETCH_SIZE", 1e6)])
+    _counter_csv(tmp_path / "w", [(1, fused, "WRITE_SIZE", 20.0), (2, comb, "WRITE_SIZE", 4.0)])
+    _counter_csv(tmp_path / "cf", [(1, "__amd_rocclr_copyBuffer", "FETCH_SIZE", 524288.0)])
+    _counter_csv(tmp_path / "cw", [(1, "__amd_rocclr_copyBuffer", "WRITE_SIZE", 1048576.0)])
+    rec = bench.traffic_record("rmat22", "f32", info, 1.5e8, str(tmp_path / "f"),
+                               str(tmp_path / "w"), str(tmp_path / "cf"), str(tmp_path / "cw"))
+    assert rec["fetch_size_kib_per_spmv_raw"] == 170.0   # (150 + 170) / 2 + 10
+    assert rec["write_size_kib_per_spmv_raw"] == 24.0
+    assert rec["copy_calibration"]["fetch_factor"] == 2.0
+    assert rec["hbm_fetch_bytes_per_launch"] == 170 * 1024 * 2
+    assert rec["hbm_write_bytes_per_launch"] == 24 * 1024
+    assert rec["spmv_source_sha256_16"] == bench.spmv_source_hash(2, 8)
+    assert rec["kernel"] == bench.kernel_instance(info) and rec["stripes"] == 8

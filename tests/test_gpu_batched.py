@@ -59,6 +59,41 @@ def test_spmm_parity(name, sigma, k, dtype):
     plan.close()
 
 
+@pytest.mark.parametrize("k", [64, 13])
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+def test_spmm_x_beyond_2gib(dtype, k):
+    """X of more than 2 GiB (the kernel's 64-bit row-address path instead of
+    the buffer path): 2^23 + 5 (FP32) or 2^22 + 5 (FP64) rows of 64 values,
+    1,000 rows of A with columns spread over all of X, the last rows
+    included.  Checked against the oracle on the X rows A uses."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    n_cols = (1 << 23) + 5 if dtype == torch.float32 else (1 << 22) + 5
+    ldx = 64
+    assert n_cols * ldx * (4 if dtype == torch.float32 else 8) >= 1 << 31
+    rng = np.random.default_rng(31)
+    lens = rng.integers(0, 120, 1000)
+    lens[::97] = 0
+    rp = np.r_[0, np.cumsum(lens)].astype(np.int32)
+    m = int(rp[-1])
+    col = rng.integers(0, n_cols, m).astype(np.int32)
+    col[:20] = n_cols - 1 - np.arange(20)          # the last rows of X
+    vals = rng.uniform(-1, 1, m)
+    r, c, v = to_device(rp, col, vals, dtype, dev)
+    plan = pkg.Plan(r, c, v, n_cols, sigma=7)
+    X = torch.empty((n_cols, ldx), dtype=dtype, device=dev)
+    X.uniform_(-1.0, 1.0, generator=torch.Generator(device=dev).manual_seed(5))
+    Y = torch.full((len(rp) - 1, k), float("nan"), dtype=dtype, device=dev)
+    plan.spmm(X[:, :k], out=Y)
+    torch.cuda.synchronize()
+    used, remap = np.unique(col, return_inverse=True)
+    X_used = X[torch.from_numpy(used.astype(np.int64)).to(dev), :k].double().cpu().numpy()
+    del X
+    check_spmm(Y, rp, remap.astype(np.int32), host_values(vals, dtype), X_used, dtype,
+               f"X > 2 GiB k{k}")
+    plan.close()
+
+
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
 def test_spmm_strided_and_many_slabs(dtype):
     """k = 150 runs as slabs of 64, 64 and 22 columns; X and Y are column
