@@ -278,36 +278,40 @@ static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
     // them within cap (a tie at the cut is left out whole)
     int64_t sample = p->nnz / (2 * nc);
     sample = sample < 1 ? 1 : (sample > 8 ? 8 : sample);
-    int32_t *counts = nullptr, *hist = nullptr, *slot_of = nullptr;
-    void* sel_tmp = nullptr;
+    HotSeg seg{};
+    seg.lo = 0;
+    seg.len = p->nnz;
+    seg.span = nc;
+    seg.c_lo = 0;
+    seg.sample = (int32_t)sample;
+    // one temporary allocation: the selection's work space, then its result
+    const size_t wb = (hot_select_layout(&seg, 1) + 255) & ~(size_t)255;
+    unsigned char* tmp = nullptr;
     auto release = [&]() {
       (void)hipStreamSynchronize(st);
-      if (counts) (void)hipFree(counts);
-      if (hist) (void)hipFree(hist);
-      if (slot_of) (void)hipFree(slot_of);
-      if (sel_tmp) (void)hipFree(sel_tmp);
+      if (tmp) (void)hipFree(tmp);
     };
-    hipError_t e = hipMalloc(&counts, sizeof(int32_t) * (size_t)nc);
-    if (e == hipSuccess) e = hipMalloc(&hist, sizeof(int32_t) * kHotHistBins);
-    if (e == hipSuccess) e = hipMalloc(&slot_of, sizeof(int32_t) * (size_t)nc);
-    if (e == hipSuccess) e = hipMalloc(&sel_tmp, hot_select_temp_bytes(nc));
+    hipError_t e = hipMalloc(&tmp, wb + sizeof(HotSel));
+    HotSel* sel_dev = reinterpret_cast<HotSel*>(tmp + wb);
     if (e == hipSuccess) e = hipMalloc(&p->hot_cols, sizeof(int32_t) * (size_t)cap);
-    if (e == hipSuccess) e = hot_count_columns(p->col, p->nnz, nc, (int)sample, counts, hist, st);
-    int64_t taken = 0;
-    double covered = 0.0;
     if (e == hipSuccess)
-      e = hot_select_top(counts, hist, nc, cap, true, sel_tmp, slot_of, p->hot_cols, &taken,
-                         &covered, st);
+      e = hot_select_ranges(p->col, &seg, 1, cap, true, tmp, p->hot_cols, sel_dev, st);
+    HotSel sel{};
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&sel, sel_dev, sizeof sel, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) {
       release();
       return fail_hip("hot column selection", e);
     }
+    const int64_t taken = sel.taken;
+    const double covered = sel.covered;
     p->hot_coverage = covered * (double)sample / (double)p->nnz;  // estimate when sampled
     if (p->hot_coverage > 1.0) p->hot_coverage = 1.0;
     const bool keep = taken > 0 && (cap_req > 0 || p->hot_coverage >= 0.2);
     if (keep) {
       e = hipMalloc(&p->colx, sizeof(int32_t) * (size_t)p->nnz);
-      if (e == hipSuccess) e = hot_recode(p->col, p->nnz, slot_of, p->colx, st);
+      if (e == hipSuccess) e = hot_recode_ranges(p->col, &seg, 1, tmp, p->colx, st);
       if (e == hipSuccess) e = hipMalloc(&p->x_hot, vs * (size_t)taken);
       if (e == hipSuccess) p->hot_n = (int32_t)taken;
     } else {
@@ -322,7 +326,7 @@ static int build_hot_cache(merbit_plan* p, int cap_req, hipStream_t st) {
     if (p->hot_all) {
       // slot = column: the recoded stream is -1 - col
       HIP_TRY(hipMalloc(&p->colx, sizeof(int32_t) * (size_t)p->nnz));
-      HIP_TRY(hot_recode(p->col, p->nnz, nullptr, p->colx, st));
+      HIP_TRY(hot_recode_all(p->col, p->nnz, p->colx, st));
     }
     p->hot_lds_bytes = vs * (size_t)p->hot_n;
     if (p->commit == MERBIT_COMMIT_WAVE)

@@ -11,22 +11,47 @@
 namespace merbit {
 
 namespace {
-// device buffers freed when the build leaves
-struct Scratch {
-  std::vector<void*> bufs;
-  ~Scratch() {
-    for (void* b : bufs)
-      if (b) (void)hipFree(b);
+// Device temporaries of a build step in one allocation (each part 256-byte
+// aligned), freed when the step leaves: add() every part, then alloc().
+class Pool {
+ public:
+  Pool() = default;
+  Pool(const Pool&) = delete;
+  Pool& operator=(const Pool&) = delete;
+  ~Pool() {
+    if (base_) (void)hipFree(base_);
   }
   template <typename T>
-  hipError_t get(T** out, size_t count) {
-    void* b = nullptr;
-    hipError_t e = hipMalloc(&b, count > 0 ? count * sizeof(T) : 1);
-    if (e == hipSuccess) bufs.push_back(b);
-    *out = static_cast<T*>(b);
+  void add(T** out, size_t count) {
+    const size_t off = bytes_;
+    bytes_ += (count * sizeof(T) + 255) & ~(size_t)255;
+    sets_.push_back([out, off](unsigned char* b) { *out = reinterpret_cast<T*>(b + off); });
+  }
+  hipError_t alloc() {
+    const hipError_t e = hipMalloc(&base_, bytes_ > 0 ? bytes_ : 1);
+    if (e == hipSuccess)
+      for (auto& set : sets_) set(base_);
     return e;
   }
+
+ private:
+  unsigned char* base_ = nullptr;
+  size_t bytes_ = 0;
+  std::vector<std::function<void(unsigned char*)>> sets_;
 };
+
+// vals[i] = src[idx[i]] (device array, host indices): one kernel, one copy
+int peek(const int32_t* src, const std::vector<int64_t>& idx, int32_t* buf, int32_t* vals,
+         hipStream_t st) {
+  for (size_t i0 = 0; i0 < idx.size(); i0 += kMaxPeek) {
+    const int n = (int)std::min(idx.size() - i0, (size_t)kMaxPeek);
+    HIP_TRY(launch_peek(src, idx.data() + i0, n, buf, st));
+    HIP_TRY(hipMemcpyAsync(vals + i0, buf, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost,
+                           st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  return MERBIT_OK;
+}
 }  // namespace
 
 int stripes_copy_values(merbit_plan* p, const void* values, hipStream_t st) {
@@ -45,17 +70,23 @@ int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st) {
   a.n_rows = n;
   a.m = m;
   a.shift = cbits > sbits ? cbits - sbits : 0;
+  p->stripe_shift = a.shift;
   a.key_bits = sbits;  // stripe indices are < 2^sbits
   a.stripes = p->stripes;
   a.words = (n + kOmega - 1) / kOmega;
   p->words = a.words;
   const int64_t nw = a.stripes * a.words;
-  Scratch tmp;
-  HIP_TRY(tmp.get(reinterpret_cast<unsigned char**>(&a.temp), stripe_temp_bytes(m, nw, sbits)));
-  HIP_TRY(tmp.get(&a.rows, (size_t)m));
-  HIP_TRY(tmp.get(&a.row_s, (size_t)m));
-  HIP_TRY(tmp.get(&a.flag, (size_t)m));
-  HIP_TRY(tmp.get(&a.vidx, (size_t)m));
+  Pool tmp;
+  unsigned char* split_temp = nullptr;
+  int32_t* peek_buf = nullptr;
+  tmp.add(&split_temp, stripe_temp_bytes(m, nw, sbits));
+  tmp.add(&a.rows, (size_t)m);
+  tmp.add(&a.row_s, (size_t)m);
+  tmp.add(&a.flag, (size_t)m);
+  tmp.add(&a.vidx, (size_t)m);
+  tmp.add(&peek_buf, (size_t)kMaxPeek);
+  HIP_TRY(tmp.alloc());
+  a.temp = split_temp;
   HIP_TRY(hipMalloc(&p->sperm, sizeof(int32_t) * (size_t)m));
   HIP_TRY(hipMalloc(&p->scol, sizeof(int32_t) * (size_t)m));
   a.perm = p->sperm;
@@ -69,11 +100,13 @@ int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st) {
   const int64_t nv = (int64_t)last[0] + last[1];
   if (nv < 1 || nv > m) return fail(MERBIT_EHIP, "column stripes: bad pair count");
   p->plan_rows = nv;
-  HIP_TRY(tmp.get(&a.vrow_ptr, (size_t)nv + 1));
-  HIP_TRY(tmp.get(&a.vrow_row, (size_t)nv));
-  HIP_TRY(tmp.get(&a.vrow_stripe, (size_t)nv));
-  HIP_TRY(tmp.get(&a.wcnt, (size_t)nw));
-  HIP_TRY(tmp.get(&a.rank, (size_t)nw));
+  Pool tmp2;
+  tmp2.add(&a.vrow_ptr, (size_t)nv + 1);
+  tmp2.add(&a.vrow_row, (size_t)nv);
+  tmp2.add(&a.vrow_stripe, (size_t)nv);
+  tmp2.add(&a.wcnt, (size_t)nw);
+  tmp2.add(&a.rank, (size_t)nw);
+  HIP_TRY(tmp2.alloc());
   HIP_TRY(hipMalloc(&p->swords, sizeof(StripeWord) * (size_t)nw));
   a.sw = p->swords;
   HIP_TRY(launch_stripe_rows(a, nv, st));
@@ -129,50 +162,99 @@ int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
   std::vector<int32_t> rt(R + 1), spans(R + 1), hoff(R + 1, 0);
   std::vector<double> cov(R, 0.0);
   for (int k = 0; k <= R; ++k) rt[k] = (int32_t)(p->tile_num * k / R);
+  Pool tmp;
+  int32_t* peek_buf = nullptr;
+  int32_t* stage = nullptr;  // each range's hot columns at k * cap, before packing
+  HotSel* sel_dev = nullptr;
+  tmp.add(&peek_buf, (size_t)kMaxPeek);
+  if (cap > 0) {
+    tmp.add(&stage, (size_t)(cap * R));
+    tmp.add(&sel_dev, (size_t)R);
+  }
+  HIP_TRY(tmp.alloc());
+  // spans[k] = first nonzero of range k (the x coordinate of its first tile)
   auto read_spans = [&]() -> int {
-    for (int k = 0; k <= R; ++k)
-      HIP_TRY(hipMemcpyAsync(&spans[k], p->tile_x + rt[k], sizeof(int32_t),
-                             hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    return MERBIT_OK;
+    std::vector<int64_t> idx(rt.begin(), rt.end());
+    return peek(p->tile_x, idx, peek_buf, spans.data(), st);
   };
   rc = read_spans();
   if (rc != MERBIT_OK) return rc;
   int64_t taken_max = 0;
   if (cap > 0) {
     const int64_t nc = p->n_cols;
-    Scratch tmp;
-    int32_t *counts = nullptr, *hist = nullptr, *slot_of = nullptr;
-    unsigned char* sel_tmp = nullptr;
-    HIP_TRY(tmp.get(&counts, (size_t)nc));
-    HIP_TRY(tmp.get(&hist, (size_t)kHotHistBins));
-    HIP_TRY(tmp.get(&slot_of, (size_t)nc));
-    HIP_TRY(tmp.get(&sel_tmp, hot_select_temp_bytes(nc)));
+    void* work = nullptr;  // the selection's work space, grown when a new cut needs more
+    size_t work_bytes = 0;
+    struct Free {
+      void*& w;
+      ~Free() {
+        if (w) (void)hipFree(w);
+      }
+    } free_work{work};
     HIP_TRY(hipMalloc(&p->hot_cols, sizeof(int32_t) * (size_t)(cap * R)));
     HIP_TRY(hipMalloc(&p->colx, sizeof(int32_t) * (size_t)p->nnz));
-    // hot sets of the current ranges: hoff, cov (hot nonzeros per range)
-    auto select = [&]() -> int {
+    std::vector<HotSel> sel((size_t)R);
+    std::vector<HotSeg> segs((size_t)R);
+    // hot sets of the current ranges: hoff, cov (hot nonzeros per range).
+    // The stripes of a range's first and last nonzero bound its columns (the
+    // stacked stream is stripe-major): counts, selection and the slot map
+    // cover that span only.  All ranges are selected, recoded and packed by
+    // the same launches; one copy brings back what the host needs.
+    auto select = [&](bool recode) -> int {
       taken_max = 0;
+      // the first and last column of every non-empty range
+      std::vector<int64_t> idx;
+      for (int k = 0; k < R; ++k)
+        if (spans[k] < spans[k + 1]) {
+          idx.push_back(spans[k]);
+          idx.push_back(spans[k + 1] - 1);
+        }
+      std::vector<int32_t> got(idx.size()), ends(2 * (size_t)R, 0);
+      int rc2 = peek(p->scol, idx, peek_buf, got.data(), st);
+      if (rc2 != MERBIT_OK) return rc2;
+      for (int k = 0, j = 0; k < R; ++k)
+        if (spans[k] < spans[k + 1]) {
+          ends[2 * k] = got[j++];
+          ends[2 * k + 1] = got[j++];
+        }
+      const int sh = p->stripe_shift;
       for (int k = 0; k < R; ++k) {
-        const int64_t lo = spans[k], len = (int64_t)spans[k + 1] - spans[k];
+        HotSeg& g = segs[k];
+        g = HotSeg{};
+        g.lo = spans[k];
+        g.len = (int64_t)spans[k + 1] - spans[k];
+        g.c_lo = g.len > 0 ? (ends[2 * k] >> sh) << sh : 0;
+        const int64_t c_hi = std::min((int64_t)((ends[2 * k + 1] >> sh) + 1) << sh, nc);
+        g.span = g.len > 0 ? c_hi - g.c_lo : 1;
         // a 1-in-4 sample of a long range: the hot columns' counts are in
-        // the hundreds, and the hottest columns' global atomics serialise
-        const int sample = len > 64 * cap ? 4 : 1;
-        HIP_TRY(hot_count_columns(p->scol + lo, len, nc, sample, counts, hist, st));
-        int64_t taken = 0;
-        double covered = 0.0;
-        HIP_TRY(hot_select_top(counts, hist, nc, cap, false, sel_tmp, slot_of,
-                               p->hot_cols + hoff[k], &taken, &covered, st));
-        cov[k] = sample > 1 ? std::min(sample * covered, (double)len) : covered;
-        if (taken == 0) HIP_TRY(hipMemsetAsync(slot_of, 0xFF, sizeof(int32_t) * (size_t)nc, st));
-        HIP_TRY(hot_recode(p->scol + lo, len, slot_of, p->colx + lo, st));
-        hoff[k + 1] = hoff[k] + (int32_t)taken;
+        // the hundreds
+        g.sample = g.len > 64 * cap ? 4 : 1;
+      }
+      const size_t need = hot_select_layout(segs.data(), R);
+      if (need > work_bytes) {
+        HIP_TRY(hipStreamSynchronize(st));  // the old space may still be read
+        if (work) (void)hipFree(work);
+        work = nullptr;
+        HIP_TRY(hipMalloc(&work, need));
+        work_bytes = need;
+      }
+      HIP_TRY(hot_select_ranges(p->scol, segs.data(), R, cap, false, work, stage, sel_dev, st));
+      if (recode) HIP_TRY(hot_recode_ranges(p->scol, segs.data(), R, work, p->colx, st));
+      HIP_TRY(hot_pack_ranges(stage, cap, sel_dev, R, p->hot_cols, st));
+      HIP_TRY(hipMemcpyAsync(sel.data(), sel_dev, sizeof(HotSel) * (size_t)R,
+                             hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      for (int k = 0; k < R; ++k) {
+        const int64_t len = segs[k].len;
+        const int64_t taken = sel[k].taken;
+        const double covered = sel[k].covered;
+        cov[k] = segs[k].sample > 1 ? std::min(segs[k].sample * covered, (double)len) : covered;
+        hoff[k + 1] = hoff[k] + (int32_t)taken;  // range k's columns at hoff[k]
         taken_max = std::max(taken_max, taken);
       }
-      HIP_TRY(hipStreamSynchronize(st));
       return MERBIT_OK;
     };
-    rc = select();
+    // the column stream is recoded for the final ranges only
+    rc = select(R == 1);
     if (rc != MERBIT_OK) return rc;
     if (R > 1) {
       // equal estimated cost per range: the cost is spread evenly over the
@@ -197,7 +279,7 @@ int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
       }
       rt = cut;
       rc = read_spans();
-      if (rc == MERBIT_OK) rc = select();
+      if (rc == MERBIT_OK) rc = select(true);
       if (rc != MERBIT_OK) return rc;
     }
     double covered = 0.0;

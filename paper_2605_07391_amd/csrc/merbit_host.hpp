@@ -51,6 +51,7 @@ struct merbit_plan {
   int stripes = 1;
   int64_t plan_rows = 0;
   int64_t words = 0;                 // 64-row words per stripe
+  int stripe_shift = 0;              // stripe of column c = c >> stripe_shift
   int32_t* sperm = nullptr;          // [nnz] stacked position -> matrix position
   int32_t* scol = nullptr;           // [nnz] stacked column stream
   void* svals = nullptr;             // [nnz] stacked values

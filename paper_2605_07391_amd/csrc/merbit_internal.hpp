@@ -275,20 +275,51 @@ inline hipError_t raise_dynamic_lds(const void* fn, size_t bytes, std::mutex& mu
 }
 
 // Hot-column cache.
-hipError_t hot_count_columns(const int32_t* col, int64_t nnz, int64_t n_cols, int sample,
-                             int32_t* counts, int32_t* hist, hipStream_t st);
-// Hot-column selection from the counts and their histogram (hot_count_columns):
-// the at most `cap` columns of largest count, ties by increasing column
-// (whole_ties: a tie at the cut is taken whole or not at all), get slots
-// 0 .. taken - 1 in column order: slot_of[c] (-1 for the others) and
-// hot_cols[slot].  *covered = the sum of the taken counts.  Synchronises st.
-// temp: hot_select_temp_bytes(n_cols) bytes.
-size_t hot_select_temp_bytes(int64_t n_cols);
-hipError_t hot_select_top(const int32_t* counts, const int32_t* hist, int64_t n_cols, int64_t cap,
-                          bool whole_ties, void* temp, int32_t* slot_of, int32_t* hot_cols,
-                          int64_t* taken, double* covered, hipStream_t st);
-hipError_t hot_recode(const int32_t* col, int64_t nnz, const int32_t* slot_of, int32_t* colx,
-                      hipStream_t st);
+// The hot columns of R column streams are chosen at once (one stream per
+// tile range of a column-stripe plan, R = 1 for a plain plan).  Range k
+// counts col[lo .. lo + len) on every sample-th nonzero over its column span
+// c_lo .. c_lo + span - 1 and takes the at most `cap` columns of largest
+// count, ties by increasing column (whole_ties: a tie at the cut is taken
+// whole or not at all), in slots 0 .. taken - 1 of increasing column.
+struct HotSeg {
+  int64_t lo, len;  // the range's nonzeros in the column stream
+  int64_t span;     // its columns: c_lo .. c_lo + span - 1
+  int64_t coff;     // its counts and slot map in the work space (hot_select_layout)
+  int64_t boff;     // its selection blocks in the work space (hot_select_layout)
+  int32_t c_lo;
+  int32_t sample;   // >= 1
+};
+struct HotSel {
+  int32_t t;       // cut count: columns above it are taken
+  int32_t extra;   // columns at the cut count taken (the first in column order)
+  int64_t taken;
+  double covered;  // sum of the taken columns' (sampled) counts
+};
+// Sets every range's coff and boff; returns the bytes of the work space that
+// hot_select_ranges and hot_recode_ranges take for these ranges.
+size_t hot_select_layout(HotSeg* segs, int R);
+// Range k's hot columns (full column indices) go to hot_cols[k * cap ..] and
+// its HotSel to sel[k] (both device); the work space keeps each range's slot
+// map for hot_recode_ranges.  Asynchronous on st; segs (host) must stay
+// alive until the stream has passed this call.
+hipError_t hot_select_ranges(const int32_t* col, const HotSeg* segs, int R, int64_t cap,
+                             bool whole_ties, void* work, int32_t* hot_cols, HotSel* sel,
+                             hipStream_t st);
+// colx[lo + i] = -1 - slot for a column that hot_select_ranges took, the
+// column otherwise, over every range
+hipError_t hot_recode_ranges(const int32_t* col, const HotSeg* segs, int R, const void* work,
+                             int32_t* colx, hipStream_t st);
+// colx[k] = -1 - col[k]: a cache of every column (slot = column)
+hipError_t hot_recode_all(const int32_t* col, int64_t nnz, int32_t* colx, hipStream_t st);
+// packed = range 0's taken columns, then range 1's, ...: the parts
+// stage[k * cap ..] of sel[k].taken columns each (sel on the device)
+hipError_t hot_pack_ranges(const int32_t* stage, int64_t cap, const HotSel* sel, int R,
+                           int32_t* packed, hipStream_t st);
+// out[i] = src[idx[i]] for i < n <= kMaxPeek: a few scattered values of a
+// device array gathered for one copy to the host (idx on the host)
+constexpr int kMaxPeek = 64;
+hipError_t launch_peek(const int32_t* src, const int64_t* idx, int n, int32_t* out,
+                       hipStream_t st);
 hipError_t launch_hot_gather(int dtype, const void* x, const int32_t* hot_cols, int32_t hot_n,
                              void* x_hot, hipStream_t st);
 // zero v at tile_y[k * unit] for k < units (the first row of every commit unit)

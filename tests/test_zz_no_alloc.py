@@ -42,7 +42,13 @@ def _run_pair(plan, n, dtype, dev, iters, tol=0.0, check_every=10, label=""):
     xb = _x0(n, dtype, dev)
     ib, rb, cb = plan.pagerank(xb, ALPHA, tol=tol, max_iter=iters, check_every=check_every)
     assert (ia, ca) == (ib, cb), f"{label}: iterations {ia} / {ib}, converged {ca} / {cb}"
-    assert abs(ra - rb) <= 1e-3 * rb + 1e-9, f"{label}: residual {ra} / {rb}"
+    # the residual is the l1 change of the last step, so by the triangle
+    # inequality two runs' residuals differ by at most the l1 differences of
+    # their last two iterates: rows that span tiles are finished with float
+    # atomics, whose order varies, and in FP32 near convergence the residual
+    # is of the size of those rounding differences
+    slack = 4.0 * float((xa.double() - xb.double()).abs().sum())
+    assert abs(ra - rb) <= 1e-3 * rb + slack + 1e-12, f"{label}: residual {ra} / {rb}"
     _compare(xa, xb, dtype, label)
     return xa
 
