@@ -717,6 +717,8 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 companion run")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched runs (64-source PPR, 256 graphs)")
+    ap.add_argument("--no-multi", action="store_true",
+                    help="skip the 256-graph block of the batched runs (keep the 64-source PPR)")
     ap.add_argument("--batched-steps", type=int, default=10)
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the differentiable-PageRank run (R-MAT scale 20)")
@@ -816,15 +818,18 @@ def main():
         ppr["vs_plain_spmv"] = round(ppr["gnz_rhs_per_s"] / main_run["spmv_gnzs"], 3)
         print(f"[bench] ppr64: step {ppr['ms_per_step']:.3f} ms, spmm {ppr['spmm_us']:.1f} us",
               file=sys.stderr, flush=True)
-        # the striped plan of the 256 graphs is tuned on its own matrix
-        multi = run_multi(args.batched_steps, 2, args.alpha, stripes=8, tune=True)
-        multi_plain = run_multi(args.batched_steps, 2, args.alpha)
-        multi["one_plan_without_stripes"] = {k: multi_plain[k] for k in
-                                             ("ms_per_step", "spmv_us", "gnzs", "spmv_gnzs")}
-        multi["vs_plain"] = round(multi["gnzs"] / main_run["value_gnzs"], 3)
-        print(f"[bench] multi256: step {multi['ms_per_step']:.3f} ms", file=sys.stderr,
-              flush=True)
-        batched = {"ppr64_" + args.workload + "_f32": ppr, "chung_lu_multi256_f32": multi}
+        batched = {"ppr64_" + args.workload + "_f32": ppr}
+        if not args.no_multi:
+            # the striped plan of the 256 graphs is tuned on its own matrix
+            multi = run_multi(args.batched_steps, 2, args.alpha, stripes=8, tune=True)
+            multi_plain = run_multi(args.batched_steps, 2, args.alpha)
+            multi["one_plan_without_stripes"] = {k: multi_plain[k] for k in
+                                                 ("ms_per_step", "spmv_us", "gnzs",
+                                                  "spmv_gnzs")}
+            multi["vs_plain"] = round(multi["gnzs"] / main_run["value_gnzs"], 3)
+            print(f"[bench] multi256: step {multi['ms_per_step']:.3f} ms", file=sys.stderr,
+                  flush=True)
+            batched["chung_lu_multi256_f32"] = multi
     adj = None
     if not args.no_adjoint and w["meta"]["generator"] == "rmat":
         adj = run_adjoint(args.adjoint_scale, 50, args.alpha, stripes=8)

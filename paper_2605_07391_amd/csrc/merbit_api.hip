@@ -496,8 +496,7 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   int rc;
   if (stripes > 1 && nnz > 0) {
     p->stripes = stripes;
-    rc = build_stripes(p, row_ptr, st);
-    if (rc == MERBIT_OK) rc = build_range_hot(p, hot_columns, st);
+    rc = build_striped(p, row_ptr, hot_columns, st);
   } else {
     p->plan_rows = n_rows;
     rc = build_tile(p, row_ptr, st);

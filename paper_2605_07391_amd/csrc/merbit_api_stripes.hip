@@ -11,33 +11,47 @@
 namespace merbit {
 
 namespace {
-// Device temporaries of a build step in one allocation (each part 256-byte
-// aligned), freed when the step leaves: add() every part, then alloc().
-class Pool {
+// Device temporaries of a striped plan build: one allocation reserved up
+// front and handed out in 256-byte aligned parts; reset() hands the space out
+// again (the parts given before are dead: every user is on the build's one
+// stream, so later work is ordered after earlier reads), and a request
+// beyond the reserve gets an allocation of its own.  Everything is freed
+// when the build leaves: a hipFree of a large block costs about 0.3 ms
+// (R-MAT 22), so the build frees one.
+class Arena {
  public:
-  Pool() = default;
-  Pool(const Pool&) = delete;
-  Pool& operator=(const Pool&) = delete;
-  ~Pool() {
+  Arena() = default;
+  Arena(const Arena&) = delete;
+  Arena& operator=(const Arena&) = delete;
+  ~Arena() {
     if (base_) (void)hipFree(base_);
+    for (void* b : extra_) (void)hipFree(b);
   }
-  template <typename T>
-  void add(T** out, size_t count) {
-    const size_t off = bytes_;
-    bytes_ += (count * sizeof(T) + 255) & ~(size_t)255;
-    sets_.push_back([out, off](unsigned char* b) { *out = reinterpret_cast<T*>(b + off); });
-  }
-  hipError_t alloc() {
-    const hipError_t e = hipMalloc(&base_, bytes_ > 0 ? bytes_ : 1);
-    if (e == hipSuccess)
-      for (auto& set : sets_) set(base_);
+  hipError_t reserve(size_t bytes) {
+    const hipError_t e = hipMalloc(&base_, bytes > 0 ? bytes : 1);
+    cap_ = e == hipSuccess ? bytes : 0;
     return e;
   }
+  template <typename T>
+  hipError_t get(T** out, size_t count) {
+    const size_t b = (count * sizeof(T) + 255) & ~(size_t)255;
+    if (used_ + b <= cap_) {
+      *out = reinterpret_cast<T*>(base_ + used_);
+      used_ += b;
+      return hipSuccess;
+    }
+    void* q = nullptr;
+    const hipError_t e = hipMalloc(&q, b > 0 ? b : 1);
+    if (e == hipSuccess) extra_.push_back(q);
+    *out = static_cast<T*>(q);
+    return e;
+  }
+  void reset() { used_ = 0; }
 
  private:
   unsigned char* base_ = nullptr;
-  size_t bytes_ = 0;
-  std::vector<std::function<void(unsigned char*)>> sets_;
+  size_t cap_ = 0, used_ = 0;
+  std::vector<void*> extra_;
 };
 
 // vals[i] = src[idx[i]] (device array, host indices): one kernel, one copy
@@ -59,7 +73,7 @@ int stripes_copy_values(merbit_plan* p, const void* values, hipStream_t st) {
   return MERBIT_OK;
 }
 
-int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st) {
+static int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st, Arena& tmp) {
   const int64_t m = p->nnz, n = p->n_rows;
   const int sbits = ceil_log2(p->stripes);
   int cbits = 0;  // columns are < 2^cbits
@@ -76,16 +90,17 @@ int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st) {
   a.words = (n + kOmega - 1) / kOmega;
   p->words = a.words;
   const int64_t nw = a.stripes * a.words;
-  Pool tmp;
+  // the reserve holds the split's temporaries and, for at most m pairs, the
+  // stacked rows' arrays
+  const auto part = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  HIP_TRY(tmp.reserve(part(stripe_temp_bytes(m, nw, sbits)) + 7 * part(sizeof(int32_t) * (size_t)m) +
+                      2 * part(sizeof(int32_t) * (size_t)nw) + part(sizeof(int32_t) * kMaxPeek) + 256));
   unsigned char* split_temp = nullptr;
-  int32_t* peek_buf = nullptr;
-  tmp.add(&split_temp, stripe_temp_bytes(m, nw, sbits));
-  tmp.add(&a.rows, (size_t)m);
-  tmp.add(&a.row_s, (size_t)m);
-  tmp.add(&a.flag, (size_t)m);
-  tmp.add(&a.vidx, (size_t)m);
-  tmp.add(&peek_buf, (size_t)kMaxPeek);
-  HIP_TRY(tmp.alloc());
+  HIP_TRY(tmp.get(&split_temp, stripe_temp_bytes(m, nw, sbits)));
+  HIP_TRY(tmp.get(&a.rows, (size_t)m));
+  HIP_TRY(tmp.get(&a.row_s, (size_t)m));
+  HIP_TRY(tmp.get(&a.flag, (size_t)m));
+  HIP_TRY(tmp.get(&a.vidx, (size_t)m));
   a.temp = split_temp;
   HIP_TRY(hipMalloc(&p->sperm, sizeof(int32_t) * (size_t)m));
   HIP_TRY(hipMalloc(&p->scol, sizeof(int32_t) * (size_t)m));
@@ -100,13 +115,11 @@ int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st) {
   const int64_t nv = (int64_t)last[0] + last[1];
   if (nv < 1 || nv > m) return fail(MERBIT_EHIP, "column stripes: bad pair count");
   p->plan_rows = nv;
-  Pool tmp2;
-  tmp2.add(&a.vrow_ptr, (size_t)nv + 1);
-  tmp2.add(&a.vrow_row, (size_t)nv);
-  tmp2.add(&a.vrow_stripe, (size_t)nv);
-  tmp2.add(&a.wcnt, (size_t)nw);
-  tmp2.add(&a.rank, (size_t)nw);
-  HIP_TRY(tmp2.alloc());
+  HIP_TRY(tmp.get(&a.vrow_ptr, (size_t)nv + 1));
+  HIP_TRY(tmp.get(&a.vrow_row, (size_t)nv));
+  HIP_TRY(tmp.get(&a.vrow_stripe, (size_t)nv));
+  HIP_TRY(tmp.get(&a.wcnt, (size_t)nw));
+  HIP_TRY(tmp.get(&a.rank, (size_t)nw));
   HIP_TRY(hipMalloc(&p->swords, sizeof(StripeWord) * (size_t)nw));
   a.sw = p->swords;
   HIP_TRY(launch_stripe_rows(a, nv, st));
@@ -123,8 +136,6 @@ int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st) {
   HIP_TRY(hipMemsetAsync(p->yv[0], 0, yb, st));
   HIP_TRY(hipMemsetAsync(p->yv[1], 0, yb, st));
   p->yv_cur = 0;
-  // the temporaries are freed on return: finish the work that reads them
-  HIP_TRY(hipStreamSynchronize(st));
   return MERBIT_OK;
 }
 
@@ -145,7 +156,7 @@ int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st) {
 // and the hot columns hold under 20 % of the nonzeros.
 constexpr double kColdWeightF32 = 1.0 / 384.0, kColdWeightF64 = 1.0 / 768.0;
 
-int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
+static int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st, Arena& tmp) {
   const size_t vs = vsize(p->dtype);
   const int64_t cap_lds = hot_cap_lds(p);
   int64_t cap = cap_req > 0 ? cap_req : (cap_req < 0 ? cap_lds : 0);
@@ -162,16 +173,16 @@ int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
   std::vector<int32_t> rt(R + 1), spans(R + 1), hoff(R + 1, 0);
   std::vector<double> cov(R, 0.0);
   for (int k = 0; k <= R; ++k) rt[k] = (int32_t)(p->tile_num * k / R);
-  Pool tmp;
+  // the stacked matrix is built: its temporaries are dead
+  tmp.reset();
   int32_t* peek_buf = nullptr;
   int32_t* stage = nullptr;  // each range's hot columns at k * cap, before packing
   HotSel* sel_dev = nullptr;
-  tmp.add(&peek_buf, (size_t)kMaxPeek);
+  HIP_TRY(tmp.get(&peek_buf, (size_t)kMaxPeek));
   if (cap > 0) {
-    tmp.add(&stage, (size_t)(cap * R));
-    tmp.add(&sel_dev, (size_t)R);
+    HIP_TRY(tmp.get(&stage, (size_t)(cap * R)));
+    HIP_TRY(tmp.get(&sel_dev, (size_t)R));
   }
-  HIP_TRY(tmp.alloc());
   // spans[k] = first nonzero of range k (the x coordinate of its first tile)
   auto read_spans = [&]() -> int {
     std::vector<int64_t> idx(rt.begin(), rt.end());
@@ -182,14 +193,8 @@ int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
   int64_t taken_max = 0;
   if (cap > 0) {
     const int64_t nc = p->n_cols;
-    void* work = nullptr;  // the selection's work space, grown when a new cut needs more
+    unsigned char* work = nullptr;  // the selection's work space, a new part when a cut needs more
     size_t work_bytes = 0;
-    struct Free {
-      void*& w;
-      ~Free() {
-        if (w) (void)hipFree(w);
-      }
-    } free_work{work};
     HIP_TRY(hipMalloc(&p->hot_cols, sizeof(int32_t) * (size_t)(cap * R)));
     HIP_TRY(hipMalloc(&p->colx, sizeof(int32_t) * (size_t)p->nnz));
     std::vector<HotSel> sel((size_t)R);
@@ -199,7 +204,7 @@ int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
     // stacked stream is stripe-major): counts, selection and the slot map
     // cover that span only.  All ranges are selected, recoded and packed by
     // the same launches; one copy brings back what the host needs.
-    auto select = [&](bool recode) -> int {
+    auto select = [&](bool final_cut) -> int {
       taken_max = 0;
       // the first and last column of every non-empty range
       std::vector<int64_t> idx;
@@ -226,19 +231,17 @@ int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
         const int64_t c_hi = std::min((int64_t)((ends[2 * k + 1] >> sh) + 1) << sh, nc);
         g.span = g.len > 0 ? c_hi - g.c_lo : 1;
         // a 1-in-4 sample of a long range: the hot columns' counts are in
-        // the hundreds
-        g.sample = g.len > 64 * cap ? 4 : 1;
+        // the hundreds.  A cut that is re-cut afterwards only estimates each
+        // range's hot share for the new cut: 1 in 16 there
+        g.sample = g.len > 64 * cap ? (final_cut ? 4 : 16) : 1;
       }
       const size_t need = hot_select_layout(segs.data(), R);
       if (need > work_bytes) {
-        HIP_TRY(hipStreamSynchronize(st));  // the old space may still be read
-        if (work) (void)hipFree(work);
-        work = nullptr;
-        HIP_TRY(hipMalloc(&work, need));
+        HIP_TRY(tmp.get(&work, need));
         work_bytes = need;
       }
       HIP_TRY(hot_select_ranges(p->scol, segs.data(), R, cap, false, work, stage, sel_dev, st));
-      if (recode) HIP_TRY(hot_recode_ranges(p->scol, segs.data(), R, work, p->colx, st));
+      if (final_cut) HIP_TRY(hot_recode_ranges(p->scol, segs.data(), R, work, p->colx, st));
       HIP_TRY(hot_pack_ranges(stage, cap, sel_dev, R, p->hot_cols, st));
       HIP_TRY(hipMemcpyAsync(sel.data(), sel_dev, sizeof(HotSel) * (size_t)R,
                              hipMemcpyDeviceToHost, st));
@@ -316,6 +319,16 @@ int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st) {
   if (p->ranges != ranges) return fail(MERBIT_EHIP, "column stripes: range count changed");
   HIP_TRY(hipStreamSynchronize(st));  // host vectors above are read by queued copies
   return MERBIT_OK;
+}
+
+int build_striped(merbit_plan* p, const int32_t* row_ptr, int hot_columns, hipStream_t st) {
+  Arena tmp;
+  int rc = build_stripes(p, row_ptr, st, tmp);
+  if (rc == MERBIT_OK) rc = build_range_hot(p, hot_columns, st, tmp);
+  // the temporaries are freed on return: finish the work that reads them
+  const hipError_t e = hipStreamSynchronize(st);
+  if (rc == MERBIT_OK && e != hipSuccess) rc = fail_hip("column-stripe plan build", e);
+  return rc;
 }
 
 }  // namespace merbit

@@ -143,8 +143,7 @@ void invalidate_graphs(merbit_plan* p);
 // whose fused kernel writes only its own buffers).
 int zero_boundary(merbit_plan* p, void* v, hipStream_t st);
 // Striped plans: the stacked matrix, its plan, and the per-range hot sets.
-int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st);
-int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st);
+int build_striped(merbit_plan* p, const int32_t* row_ptr, int hot_columns, hipStream_t st);
 // copy values into the stacked order
 int stripes_copy_values(merbit_plan* p, const void* values, hipStream_t st);
 // allocate TILE for plan_rows rows and build it from row_ptr
