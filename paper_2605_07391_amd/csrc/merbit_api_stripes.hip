@@ -145,16 +145,20 @@ static int build_stripes(merbit_plan* p, const int32_t* row_ptr, hipStream_t st,
 // ranges; each range takes the (at most cap) most frequent columns of its own
 // nonzeros (counted on every 4th nonzero of a long range), ties by
 // increasing column, in slots of increasing column.  The ranges first get
-// equal tile
-// counts; with a cache they are then re-cut so that every range carries the
-// same estimated cost, tiles plus the gathers its cache does not serve
-// (kColdWeight tiles per gather: a range whose columns are less concentrated
-// gets fewer tiles), and the hot sets are chosen again for the new ranges.
-// The weight was measured on R-MAT 22 (1/96 .. 1/768 swept): 1/384 in FP32;
-// FP64 tiles stream 12 instead of 8 bytes per nonzero, so a gather weighs
-// less against a tile there, 1/768.  The cache is dropped when cap_req < 0
-// and the hot columns hold under 20 % of the nonzeros.
-constexpr double kColdWeightF32 = 1.0 / 384.0, kColdWeightF64 = 1.0 / 768.0;
+// equal tile counts; with a cache they are then re-cut so that every range
+// carries the same estimated cost, tiles plus the gathers its cache does not
+// serve (kColdWeight tiles per gather: a range whose columns are less
+// concentrated gets fewer tiles), and the hot sets are chosen again for the
+// new ranges.  The weights were swept on R-MAT 22 at the tuned
+// configurations (512-lane blocks, 64-bit descriptors, 8 stripes; us per
+// SpMV): FP32 sigma 32 at 0 / 1/3072 / 1/2048 / 1/1536 / 1/1024 / 1/768 /
+// 1/384 / 1/192: 227 / 220 / 218 / 217 / 220 / 224 / 229 / 236; FP64 sigma 20
+// at 0 / 1/3072 / 1/1536 / 1/768 / 1/384: 306 / 302 / 299 / 297 / 301.
+// (Per-wavefront end stamps at 1/384 in FP32: the ranges' wavefronts ended
+// 168 to 207 us, on average per range, into a 212 us launch, the ranges
+// given the most tiles last.)  The cache is dropped when cap_req < 0 and the
+// hot columns hold under 20 % of the nonzeros.
+constexpr double kColdWeightF32 = 1.0 / 1536.0, kColdWeightF64 = 1.0 / 768.0;
 
 static int build_range_hot(merbit_plan* p, int cap_req, hipStream_t st, Arena& tmp) {
   const size_t vs = vsize(p->dtype);
