@@ -142,7 +142,9 @@ typedef struct {
     int32_t commit;        /* merbit_commit of the plan                                 */
     double hot_coverage;   /* fraction of nonzeros whose column is hot (estimated from
                               a 1-in-s sample of the column stream, s <= 8, when the
-                              cache holds only part of the columns)                     */
+                              cache holds only part of the columns; with column
+                              stripes, per range: exact for a range of at most
+                              64 hot_columns nonzeros, else from every 4th)             */
     int32_t desc_bits;     /* lane descriptor width: 32 or 64                           */
     int32_t stripes;       /* column stripes (1 = none)                                 */
     int32_t ranges;        /* contiguous tile ranges of the fused launch (1 = none)     */
