@@ -37,7 +37,7 @@ extern "C" {
 typedef enum {
     MERBIT_OK = 0,
     MERBIT_EINVAL = -1,       /* bad argument or failed CSR validation        */
-    MERBIT_ENOMEM = -2,       /* device allocation failed                      */
+    MERBIT_ENOMEM = -2,       /* device (or host) allocation failed            */
     MERBIT_EHIP = -3,         /* a HIP runtime call failed (message has it)    */
     MERBIT_EUNSUPPORTED = -4, /* dtype / sigma / block size not built          */
     MERBIT_NOT_CONVERGED = 1, /* an iterative driver reached max_iter above tol */

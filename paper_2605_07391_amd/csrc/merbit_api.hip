@@ -5,6 +5,9 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <exception>
+#include <new>
+
 #include "merbit_host.hpp"
 
 namespace merbit {
@@ -13,6 +16,23 @@ static thread_local std::string g_last_error;
 
 int fail(int code, const std::string& msg) {
   g_last_error = msg;
+  return code;
+}
+
+int host_exception() noexcept {
+  int code = MERBIT_EHIP;
+  const char* msg = "unexpected C++ exception on the host";
+  try {
+    throw;
+  } catch (const std::bad_alloc&) {
+    code = MERBIT_ENOMEM;
+    msg = "host memory exhausted";
+  } catch (...) {
+  }
+  try {
+    g_last_error = msg;
+  } catch (...) {
+  }
   return code;
 }
 
@@ -389,7 +409,7 @@ void merbit_opts_init(merbit_opts_t* o) {
 
 int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* row_ptr,
                        const int32_t* col_ind, const void* values, int dtype,
-                       const merbit_opts_t* opts_in, void* stream, merbit_plan** out) {
+                       const merbit_opts_t* opts_in, void* stream, merbit_plan** out) try {
   g_last_error.clear();
   merbit_opts_t opts;
   if (opts_in) opts = *opts_in;
@@ -447,6 +467,14 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
 
   hipStream_t st = static_cast<hipStream_t>(stream);
   merbit_plan* p = new merbit_plan();
+  // a host exception during the build (the error returns free the plan
+  // themselves) frees it on the way out
+  struct FreeOnThrow {
+    merbit_plan* p;
+    ~FreeOnThrow() {
+      if (std::uncaught_exceptions() > 0) plan_free_all(p);
+    }
+  } free_on_throw{p};
   p->n_rows = n_rows;
   p->n_cols = n_cols;
   p->nnz = nnz;
@@ -522,9 +550,11 @@ int merbit_plan_create(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_
   }
   *out = p;
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
-int merbit_plan_set_values(merbit_plan* p, const void* values) {
+int merbit_plan_set_values(merbit_plan* p, const void* values) try {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (p->nnz > 0 && !values) return fail(MERBIT_EINVAL, "values is NULL");
   if (p->stripes > 1) {
@@ -535,9 +565,11 @@ int merbit_plan_set_values(merbit_plan* p, const void* values) {
   if (values != p->values) invalidate_graphs(p);
   p->values = values;
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
-int merbit_plan_info(merbit_plan* p, merbit_plan_info_t* info) {
+int merbit_plan_info(merbit_plan* p, merbit_plan_info_t* info) try {
   if (!p || !info) return fail(MERBIT_EINVAL, "NULL argument");
   memset(info, 0, sizeof *info);
   info->n_rows = p->n_rows;
@@ -573,10 +605,12 @@ int merbit_plan_info(merbit_plan* p, merbit_plan_info_t* info) {
     info->fast_tiles = (int64_t)cnt;
   }
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 int merbit_plan_export(merbit_plan* p, int32_t* tile_x, uint32_t* tile_y, void* lane_desc,
-                       int64_t* tile_num, int64_t* lane_num) {
+                       int64_t* tile_num, int64_t* lane_num) try {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (tile_num) *tile_num = p->tile_num;
   if (lane_num) *lane_num = p->lane_num;
@@ -594,9 +628,11 @@ int merbit_plan_export(merbit_plan* p, int32_t* tile_x, uint32_t* tile_y, void* 
                       (size_t)(p->desc_bits / 8) * (size_t)p->lane_num,
                       hipMemcpyDeviceToHost));
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
-int merbit_zero_boundary(merbit_plan* p, void* v, void* stream) {
+int merbit_zero_boundary(merbit_plan* p, void* v, void* stream) try {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (p->chunk_num == 0) return MERBIT_OK;
   if (!v) return fail(MERBIT_EINVAL, "vector is NULL");
@@ -605,9 +641,11 @@ int merbit_zero_boundary(merbit_plan* p, void* v, void* stream) {
   if (rc != MERBIT_OK) return rc;
   p->last_stream = st;
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
-int merbit_spmv(merbit_plan* p, const void* x, void* y, void* stream) {
+int merbit_spmv(merbit_plan* p, const void* x, void* y, void* stream) try {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (p->n_rows == 0) return MERBIT_OK;
   if (!y || (p->nnz > 0 && !x)) return fail(MERBIT_EINVAL, "x or y is NULL");
@@ -616,23 +654,29 @@ int merbit_spmv(merbit_plan* p, const void* x, void* y, void* stream) {
   const int rc = zero_boundary(p, y, st);
   if (rc != MERBIT_OK) return rc;
   return run_fused(p, x, y, nullptr, st);
+} catch (...) {
+  return merbit::host_exception();
 }
 
-int merbit_spmv_dual(merbit_plan* p, const void* x, void* y, void* z, void* stream) {
+int merbit_spmv_dual(merbit_plan* p, const void* x, void* y, void* z, void* stream) try {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (p->n_rows == 0) return MERBIT_OK;
   if (!y || !z || (p->nnz > 0 && !x)) return fail(MERBIT_EINVAL, "x, y or z is NULL");
   if (x == y || y == z || x == z) return fail(MERBIT_EINVAL, "x, y, z must be distinct");
   return run_fused(p, x, y, z, static_cast<hipStream_t>(stream));
+} catch (...) {
+  return merbit::host_exception();
 }
 
-int merbit_profile_enable(merbit_plan* p, int enable) {
+int merbit_profile_enable(merbit_plan* p, int enable) try {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   p->profiling = enable != 0;
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
-int merbit_profile_read(merbit_plan* p, int64_t* launches, double* total_ms) {
+int merbit_profile_read(merbit_plan* p, int64_t* launches, double* total_ms) try {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   double total = 0.0;
   for (size_t k = 0; k < p->events_used; ++k) {
@@ -645,6 +689,8 @@ int merbit_profile_read(merbit_plan* p, int64_t* launches, double* total_ms) {
   if (total_ms) *total_ms = total;
   p->events_used = 0;
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 void merbit_plan_destroy(merbit_plan* p) { plan_free_all(p); }

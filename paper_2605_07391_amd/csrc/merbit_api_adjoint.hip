@@ -25,7 +25,7 @@ static TileRowsArgs tile_rows_args(const merbit_plan* p) {
 }
 
 int merbit_transpose(merbit_plan* p, int32_t* rowT_ptr, int32_t* colT, int32_t* perm,
-                     void* stream) {
+                     void* stream) try {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (p->stripes > 1) return fail(MERBIT_EUNSUPPORTED, "not available on a striped plan");
   if (p->desc_bits != 32)
@@ -58,10 +58,12 @@ int merbit_transpose(merbit_plan* p, int32_t* rowT_ptr, int32_t* colT, int32_t* 
   if (e != hipSuccess) return fail_hip("transpose", e);
   p->last_stream = st;
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 int merbit_sddmm(merbit_plan* p, const void* g, const void* x, double scale, void* out,
-                 void* stream) {
+                 void* stream) try {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (p->stripes > 1) return fail(MERBIT_EUNSUPPORTED, "not available on a striped plan");
   if (p->desc_bits != 32)
@@ -77,10 +79,12 @@ int merbit_sddmm(merbit_plan* p, const void* g, const void* x, double scale, voi
   HIP_TRY(launch_tile_rows(p->dtype, p->sigma, true, a, st));
   p->last_stream = st;
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 int merbit_gather_values(int dtype, int64_t nnz, const int32_t* perm, const void* src,
-                         const void* src2, void* dst, void* stream) {
+                         const void* src2, void* dst, void* stream) try {
   if (dtype != MERBIT_F32 && dtype != MERBIT_F64) return fail(MERBIT_EUNSUPPORTED, "dtype");
   if (nnz < 0) return fail(MERBIT_EINVAL, "nnz < 0");
   if (nnz == 0) return MERBIT_OK;
@@ -88,16 +92,20 @@ int merbit_gather_values(int dtype, int64_t nnz, const int32_t* perm, const void
   if (dst == src || (src2 && dst == src2)) return fail(MERBIT_EINVAL, "dst aliases an input");
   HIP_TRY(launch_gather_values(dtype, perm, src, src2, dst, nnz, static_cast<hipStream_t>(stream)));
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 int merbit_column_scale(int dtype, int64_t nnz, const int32_t* col, const void* a, const void* t,
-                        const void* s, void* out, void* stream) {
+                        const void* s, void* out, void* stream) try {
   if (dtype != MERBIT_F32 && dtype != MERBIT_F64) return fail(MERBIT_EUNSUPPORTED, "dtype");
   if (nnz < 0) return fail(MERBIT_EINVAL, "nnz < 0");
   if (nnz == 0) return MERBIT_OK;
   if (!col || !a || !s || !out) return fail(MERBIT_EINVAL, "col, a, s or out is NULL");
   HIP_TRY(launch_column_scale(dtype, col, a, t, s, out, nnz, static_cast<hipStream_t>(stream)));
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 }  // extern "C"

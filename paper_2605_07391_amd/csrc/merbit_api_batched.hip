@@ -64,7 +64,7 @@ static int run_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t
 }
 
 int merbit_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy, int k,
-                void* stream) {
+                void* stream) try {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (p->stripes > 1) return fail(MERBIT_EUNSUPPORTED, "not available on a striped plan");
   if (p->desc_bits != 32)
@@ -82,10 +82,12 @@ int merbit_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy
                              static_cast<char*>(Y) + vs * c0, ldy, kk, st));
   }
   return run_spmm(p, X, ldx, Y, ldy, nullptr, 0, k, st);
+} catch (...) {
+  return merbit::host_exception();
 }
 
 int merbit_spmm_dual(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy, void* Z,
-                     int64_t ldz, int k, void* stream) {
+                     int64_t ldz, int k, void* stream) try {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (p->stripes > 1) return fail(MERBIT_EUNSUPPORTED, "not available on a striped plan");
   if (p->desc_bits != 32)
@@ -96,9 +98,11 @@ int merbit_spmm_dual(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_
   if (!Y || !Z || (p->nnz > 0 && !X)) return fail(MERBIT_EINVAL, "X, Y or Z is NULL");
   if (X == Y || Y == Z || X == Z) return fail(MERBIT_EINVAL, "X, Y, Z must be distinct");
   return run_spmm(p, X, ldx, Y, ldy, Z, ldz, k, static_cast<hipStream_t>(stream));
+} catch (...) {
+  return merbit::host_exception();
 }
 
-int merbit_spmm_zero_boundary(merbit_plan* p, void* Y, int64_t ldy, int k, void* stream) {
+int merbit_spmm_zero_boundary(merbit_plan* p, void* Y, int64_t ldy, int k, void* stream) try {
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (p->stripes > 1) return fail(MERBIT_EUNSUPPORTED, "not available on a striped plan");
   if (k < 1 || ldy < k) return fail(MERBIT_EINVAL, "bad k / leading dimension");
@@ -113,6 +117,8 @@ int merbit_spmm_zero_boundary(merbit_plan* p, void* Y, int64_t ldy, int k, void*
   }
   p->last_stream = st;
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 static int ensure_ppr_state(merbit_plan* p, int k, hipStream_t st) {
@@ -141,7 +147,7 @@ static int ensure_ppr_state(merbit_plan* p, int k, hipStream_t st) {
 
 int merbit_pagerank_personalized(merbit_plan* p, double alpha, double tol, int max_iter,
                                  int check_every, const int32_t* sources, int k, void* X_inout,
-                                 int* iters_out, double* resid_out, void* stream) {
+                                 int* iters_out, double* resid_out, void* stream) try {
   if (iters_out) *iters_out = 0;
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (p->stripes > 1) return fail(MERBIT_EUNSUPPORTED, "not available on a striped plan");
@@ -220,6 +226,8 @@ int merbit_pagerank_personalized(merbit_plan* p, double alpha, double tol, int m
   HIP_TRY(hipStreamSynchronize(st));
   if (iters_out) *iters_out = t;
   return (tol > 0.0 && !converged) ? MERBIT_NOT_CONVERGED : MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 // Row-chunk tables for the graphs of graph_ptr (rebuilt when it changes).

@@ -89,7 +89,7 @@ int pagerank_loop(merbit_plan* p, PageRankWork& w, double alpha, double tol, int
 extern "C" {
 
 int merbit_pagerank(merbit_plan* p, double alpha, double tol, int max_iter, int check_every,
-                    void* x_inout, int* iters_out, double* resid_out, void* stream) {
+                    void* x_inout, int* iters_out, double* resid_out, void* stream) try {
   if (iters_out) *iters_out = 0;
   if (resid_out) *resid_out = 0.0;
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
@@ -117,6 +117,8 @@ int merbit_pagerank(merbit_plan* p, double alpha, double tol, int max_iter, int 
   rc = pagerank_loop(p, w, alpha, tol, max_iter, check_every, x_inout, iters_out, resid_out, st);
   p->zeroed_buf = w.zeroed_buf;
   return rc;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 static int ensure_multi_tables(merbit_plan* p, const int64_t* graph_ptr, int n_graphs,
@@ -167,7 +169,7 @@ static int ensure_multi_tables(merbit_plan* p, const int64_t* graph_ptr, int n_g
 
 int merbit_pagerank_multi(merbit_plan* p, const int64_t* graph_ptr, int n_graphs, double alpha,
                           double tol, int max_iter, int check_every, void* x_inout,
-                          int* iters_out, double* resid_out, void* stream) {
+                          int* iters_out, double* resid_out, void* stream) try {
   if (iters_out) *iters_out = 0;
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
   if (p->n_rows != p->n_cols) return fail(MERBIT_EINVAL, "PageRank needs a square matrix");
@@ -252,11 +254,13 @@ int merbit_pagerank_multi(merbit_plan* p, const int64_t* graph_ptr, int n_graphs
   HIP_TRY(hipStreamSynchronize(st));
   if (iters_out) *iters_out = t;
   return (tol > 0.0 && !converged) ? MERBIT_NOT_CONVERGED : MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 int merbit_pagerank_adjoint(merbit_plan* p, merbit_plan* pt, double alpha, double tol,
                             int max_iter, int check_every, const void* g, void* lam_inout,
-                            int* iters_out, double* resid_out, void* stream) {
+                            int* iters_out, double* resid_out, void* stream) try {
   if (iters_out) *iters_out = 0;
   if (resid_out) *resid_out = 0.0;
   if (!p || !pt) return fail(MERBIT_EINVAL, "plan is NULL");
@@ -330,12 +334,14 @@ int merbit_pagerank_adjoint(merbit_plan* p, merbit_plan* pt, double alpha, doubl
   if (iters_out) *iters_out = t;
   if (resid_out) *resid_out = resid;
   return (tol > 0.0 && !converged) ? MERBIT_NOT_CONVERGED : MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 // ------------------------------------------------------------ BiCGSTAB --
 
 int merbit_bicgstab(merbit_plan* p, const void* b, void* x_inout, double tol, int max_iter,
-                    int check_every, int* iters_out, double* resid_out, void* stream) {
+                    int check_every, int* iters_out, double* resid_out, void* stream) try {
   if (iters_out) *iters_out = 0;
   if (resid_out) *resid_out = 0.0;
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
@@ -457,6 +463,8 @@ int merbit_bicgstab(merbit_plan* p, const void* b, void* x_inout, double tol, in
   if (iters_out) *iters_out = t;
   if (tol <= 0.0 && status == MERBIT_NOT_CONVERGED) status = MERBIT_OK;
   return status;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 }  // extern "C"

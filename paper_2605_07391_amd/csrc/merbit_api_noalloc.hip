@@ -51,7 +51,7 @@ extern "C" {
 
 int merbit_pagerank_noalloc(merbit_plan* p, double alpha, double tol, int max_iter,
                             int check_every, void* x_inout, int* iters_out, double* resid_out,
-                            void* stream) {
+                            void* stream) try {
   if (iters_out) *iters_out = 0;
   if (resid_out) *resid_out = 0.0;
   if (!p) return fail(MERBIT_EINVAL, "plan is NULL");
@@ -117,6 +117,8 @@ int merbit_pagerank_noalloc(merbit_plan* p, double alpha, double tol, int max_it
   w.host_pairs = host_pairs;
   return pagerank_loop(p, w, alpha, tol, max_iter, check_every, x_inout, iters_out, resid_out,
                        st);
+} catch (...) {
+  return merbit::host_exception();
 }
 
 }  // extern "C"

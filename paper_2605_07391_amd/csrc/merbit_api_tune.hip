@@ -15,7 +15,7 @@ extern "C" {
 int merbit_tune(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* row_ptr,
                 const int32_t* col_ind, const void* values, int dtype, const int32_t* sigmas,
                 int n_sigmas, const int32_t* block_lanes, int n_blocks, int reps,
-                merbit_opts_t* opts_inout, float* us_out, void* stream) {
+                merbit_opts_t* opts_inout, float* us_out, void* stream) try {
   if (!opts_inout) return fail(MERBIT_EINVAL, "opts is NULL");
   if (dtype != MERBIT_F32 && dtype != MERBIT_F64) return fail(MERBIT_EUNSUPPORTED, "dtype");
   if (reps < 1) return fail(MERBIT_EINVAL, "reps < 1");
@@ -115,6 +115,8 @@ int merbit_tune(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t* row_
   opts_inout->sigma = best_sigma;
   opts_inout->block_lanes = best_b;
   return MERBIT_OK;
+} catch (...) {
+  return merbit::host_exception();
 }
 
 }  // extern "C"

@@ -120,6 +120,10 @@ namespace merbit {
 int fail(int code, const std::string& msg);
 // MERBIT_ENOMEM or MERBIT_EHIP with the HIP error string.
 int fail_hip(const char* what, hipError_t e);
+// Called from a catch (...) handler of a C-ABI entry point: no C++ exception
+// leaves the library; a failed host allocation (std::bad_alloc) becomes
+// MERBIT_ENOMEM, anything else MERBIT_EHIP, with the message set.
+int host_exception() noexcept;
 
 #define HIP_TRY(expr)                                  \
   do {                                                 \
