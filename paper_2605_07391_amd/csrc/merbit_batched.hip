@@ -3,7 +3,8 @@
 // per-graph PageRank update for many graphs stored on the diagonal of one
 // matrix.
 //
-// SpMM (one wavefront per tile, lanes = right-hand-side columns).  The
+// SpMM (one wavefront per tile, lanes = right-hand-side columns of a slab;
+// the driver runs one launch per slab of 128 bytes of X row).  The
 // tile's merge-path segment (Sec. 4.1) fixes its nonzeros [x_ws, x_we) and
 // rows [y_ws, y_we]; every nonzero is a 64-wide row operation
 // Y[row, :] += v * X[col, :], so each X access is one coalesced row load.
@@ -66,8 +67,9 @@ constexpr int kSpmmBufferWord3 = 0x00020000;
 // through a buffer resource with the row's byte offset as the scalar offset
 // (X no larger than 2 GiB), or through a 64-bit scalar row address.
 // Every lane loads (no branch, so the group's loads go out back to back):
-// lanes at or past k read a neighbouring element of the same row, or 0 past
-// the end of X (buffer range check), and their values are never stored.
+// lanes at or past k read the row's element k - 1 again (the same line, so a
+// slab narrower than 64 columns fetches no part of X it does not use), and
+// their values are never stored.
 template <typename V, bool BUF>
 __device__ __forceinline__ V load_x_row(__amdgpu_buffer_rsrc_t rx, const V* __restrict__ X,
                                         int64_t ldx, uint32_t off_l, int c_l, int q, int lane) {
@@ -97,8 +99,8 @@ __device__ __forceinline__ void spmm_walk(const SpmmArgs& a, const int32_t* __re
   const __amdgpu_buffer_rsrc_t rx =
       __builtin_amdgcn_make_buffer_rsrc((void*)X, (short)0, bytes, kSpmmBufferWord3);
   const uint32_t row_bytes = (uint32_t)(ldx * (int64_t)sizeof(V));
-  // the 64-bit path keeps lanes past k on the row's last column
-  const int lane = BUF ? lid : min(lid, a.k - 1);
+  // lanes past k stay on the slab's last column
+  const int lane = min(lid, a.k - 1);
   for (int q0 = 0; q0 < x_se; q0 += kOmega) {
     const int ql = q0 + lid;
     const bool valid = ql < x_se;
