@@ -365,8 +365,11 @@ def run_ppr(w, k: int, steps: int, warmup: int, alpha: float):
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                          "kernel": f"merbit::spmm_kernel<float, {best['sigma']}>",
-                         "alg_bytes_per_launch": int(alg),
-                         "mean_launch_us": round(spmm_ms * 1e3, 1)}}
+                         # one SpMM = one launch per 32-column slab (128 bytes of
+                         # X row), timed together
+                         "launches_per_spmm": -(-k // 32),
+                         "alg_bytes_per_spmm": int(alg),
+                         "mean_spmm_us": round(spmm_ms * 1e3, 1)}}
 
 
 def run_multi(steps: int, warmup: int, alpha: float, stripes: int = 0, plan_kw=None,
