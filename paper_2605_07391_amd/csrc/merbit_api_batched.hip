@@ -34,10 +34,10 @@ static SpmmArgs spmm_args(const merbit_plan* p, const void* X, int64_t ldx, void
 
 // One SpMM launch per slab of columns whose part of an X row is one 128-byte
 // line (32 FP32 / 16 FP64 columns), the slabs one after another; the whole
-// call is bracketed by one pair of events when profiling is on.  A launch
-// reads each X row it needs as one line, so L2 holds twice the rows of a
-// 64-column slab: 64 FP32 columns of R-MAT 22 as two 32-column launches took
-// 2.40 ms against 2.90 ms as one.
+// call is bracketed by one pair of events when profiling is on.  Each X-row
+// access of a launch is then one line instead of two: 64 FP32 columns of
+// R-MAT 22 took 2.53 ms as two 32-column launches against 2.89 ms as one,
+// with as many L2 misses and bytes read (the misses are served faster).
 static int run_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy, void* Z,
                     int64_t ldz, int k, hipStream_t st) {
   const size_t vs = vsize(p->dtype);
