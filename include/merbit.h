@@ -268,7 +268,7 @@ int merbit_pagerank_noalloc(merbit_plan* plan, double alpha, double tol, int max
  * tile of the merge path and its lanes carry the columns of a slab, so every
  * X access is one coalesced read of a row's slab; the columns run in slabs of
  * one 128-byte line of X row (32 FP32 / 16 FP64 columns), one launch each,
- * so that L2 holds as many X rows as it can.  Launches: a scatter that zeroes
+ * so that every X-row access is one line.  Launches: a scatter that zeroes
  * Y at every tile's first row, then the SpMM kernel once per slab. */
 int merbit_spmm(merbit_plan* plan, const void* X, int64_t ldx, void* Y, int64_t ldy, int k,
                 void* stream);
