@@ -267,9 +267,9 @@ int merbit_pagerank_noalloc(merbit_plan* plan, double alpha, double tol, int max
  * k >= 1, ldx >= k, ldy >= k; X and Y not aliased.  One wavefront walks one
  * tile of the merge path and its lanes carry the columns of a slab, so every
  * X access is one coalesced read of a row's slab; the columns run in slabs of
- * one 128-byte line of X row (32 FP32 / 16 FP64 columns), one launch each,
- * so that every X-row access is one line.  Launches: a scatter that zeroes
- * Y at every tile's first row, then the SpMM kernel once per slab. */
+ * 32, one launch each (faster than one 64-column launch, FP32 and FP64).
+ * Launches: a scatter that zeroes Y at every tile's first row, then the SpMM
+ * kernel once per slab. */
 int merbit_spmm(merbit_plan* plan, const void* X, int64_t ldx, void* Y, int64_t ldy, int k,
                 void* stream);
 

@@ -32,16 +32,17 @@ static SpmmArgs spmm_args(const merbit_plan* p, const void* X, int64_t ldx, void
   return a;
 }
 
-// One SpMM launch per slab of columns whose part of an X row is one 128-byte
-// line (32 FP32 / 16 FP64 columns), the slabs one after another; the whole
-// call is bracketed by one pair of events when profiling is on.  Each X-row
-// access of a launch is then one line instead of two: 64 FP32 columns of
-// R-MAT 22 took 2.53 ms as two 32-column launches against 2.89 ms as one,
-// with as many L2 misses and bytes read (the misses are served faster).
+// One SpMM launch per slab of at most kSpmmSlab columns, the slabs one after
+// another; the whole call is bracketed by one pair of events when profiling
+// is on.  64 columns of R-MAT 22 took, as 1 / 2 / 4 launches: FP32 2.89 /
+// 2.53 / 13.7 ms (as many L2 misses and bytes read in the 2 launches as in
+// the 1: the misses are served faster), FP64 6.2 / 5.4 / 9.1 ms.
+constexpr int kSpmmSlab = 32;
+
 static int run_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy, void* Z,
                     int64_t ldz, int k, hipStream_t st) {
   const size_t vs = vsize(p->dtype);
-  const int slab = (int)(128 / vs);
+  const int slab = kSpmmSlab;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (p->profiling) {
     if (p->events_used == p->events.size()) {

@@ -4,7 +4,7 @@
 // matrix.
 //
 // SpMM (one wavefront per tile, lanes = right-hand-side columns of a slab;
-// the driver runs one launch per slab of 128 bytes of X row).  The
+// the driver runs one launch per slab of 32 columns).  The
 // tile's merge-path segment (Sec. 4.1) fixes its nonzeros [x_ws, x_we) and
 // rows [y_ws, y_we]; every nonzero is a 64-wide row operation
 // Y[row, :] += v * X[col, :], so each X access is one coalesced row load.
