@@ -41,7 +41,7 @@ def check_spmm(Y_gpu, row_ptr, col, vals64, X64, dtype, label=""):
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
-@pytest.mark.parametrize("k", [1, 13, 64])
+@pytest.mark.parametrize("k", [1, 13, 33, 64])
 @pytest.mark.parametrize("sigma", [3, 12])
 @pytest.mark.parametrize("name", list(CASES))
 def test_spmm_parity(name, sigma, k, dtype):
@@ -96,8 +96,8 @@ def test_spmm_x_beyond_2gib(dtype, k):
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
 def test_spmm_strided_and_many_slabs(dtype):
-    """k = 150 runs as slabs of 64, 64 and 22 columns; X and Y are column
-    windows of wider row-major buffers (leading dimensions > k)."""
+    """k = 150 runs as four slabs of 32 columns and one of 22; X and Y are
+    column windows of wider row-major buffers (leading dimensions > k)."""
     import paper_2605_07391_amd as pkg
     dev = require_gpu()
     rp, col, vals, nc = case_matrix(CASES, "chung_lu_10k", seed=3)
