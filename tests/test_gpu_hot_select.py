@@ -139,3 +139,30 @@ def test_striped_plan_with_room_for_every_column_covers_all():
     # a range takes each of its distinct columns once
     assert np.unique(col).size <= info["hot_columns"] <= info["ranges"] * np.unique(col).size
     plan.close()
+
+
+@pytest.mark.parametrize("stripes", [0, 8], ids=["plain", "striped8"])
+def test_wide_sparse_matrix_hot_set(stripes):
+    """Far more columns than nonzeros (the selection's work space then
+    outgrows what the build reserves from the nonzero count): the hot set is
+    still the rule's and the SpMV matches the oracle."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    n_rows, n_cols = 600, 1_500_000
+    rp, col, vals = _skewed_matrix(n_rows, n_cols, 5.0, seed=21)
+    cap = 64
+    r, c, v = to_device(rp, col, vals, torch.float32, dev)
+    plan = pkg.Plan(r, c, v, n_cols, commit="wave", stripes=stripes, hot_columns=cap)
+    info = plan.info()
+    print(f"wide sparse stripes={stripes}: taken {info['hot_columns']}", flush=True)
+    if stripes == 0:
+        taken, covered = _plain_rule(col, n_cols, cap)
+        assert info["hot_columns"] == taken
+        assert info["hot_coverage"] == pytest.approx(covered / len(col), rel=1e-12, abs=0.0)
+    else:
+        assert 0 < info["hot_columns"] <= cap * info["ranges"]
+    x64 = seeded_x(n_cols, 33, torch.float32)
+    y = plan.spmv(torch.from_numpy(x64).to(torch.float32).to(dev))
+    torch.cuda.synchronize()
+    check_spmv(y, rp, col, host_values(vals, torch.float32), x64, torch.float32, "wide sparse")
+    plan.close()
