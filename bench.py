@@ -364,9 +364,10 @@ def run_ppr(w, k: int, steps: int, warmup: int, alpha: float):
             "max_mass_error": mass_err, "sources_seed": 4,
             "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                         "kernel": f"merbit::spmm_kernel<float, {best['sigma']}>",
-                         # one SpMM = one launch per 32-column slab (128 bytes of
-                         # X row), timed together
+                         # the SpMM of the step, fused with the update of the
+                         # rows inside tiles: one launch per 32-column slab
+                         # (128 bytes of X row), timed together
+                         "kernel": f"merbit::spmm_kernel<float, {best['sigma']}, true>",
                          "launches_per_spmm": -(-k // 32),
                          "alg_bytes_per_spmm": int(alg),
                          "mean_spmm_us": round(spmm_ms * 1e3, 1)}}

@@ -293,6 +293,10 @@ int merbit_spmm_zero_boundary(merbit_plan* plan, void* Y, int64_t ldy, int k, vo
  *              check_every iterations; tol <= 0 runs exactly max_iter
  *   iters_out  host, optional; resid_out host double[k], optional: last l1
  *              change per column
+ * A step is the SpMM (slabs of 32 columns) with the update of every row
+ * strictly inside a tile done in its commit, then one kernel for the tiles'
+ * first rows; the plan keeps two n x k work buffers of its dtype after the
+ * first call (freed by merbit_plan_destroy).
  * Returns MERBIT_OK or MERBIT_NOT_CONVERGED; synchronises `stream`. */
 int merbit_pagerank_personalized(merbit_plan* plan, double alpha, double tol, int max_iter,
                                  int check_every, const int32_t* sources, int k, void* X_inout,

@@ -29,6 +29,14 @@ static SpmmArgs spmm_args(const merbit_plan* p, const void* X, int64_t ldx, void
   a.lane_num = (int32_t)p->lane_num;
   a.path_len = (int32_t)(p->nnz + p->n_rows);
   a.n_rows = (int32_t)p->n_rows;
+  a.Xn = nullptr;  // plain Y = A X
+  a.src = nullptr;
+  a.sums_in = nullptr;
+  a.dmask = nullptr;
+  a.part = nullptr;
+  a.alpha = 0.0;
+  a.col0 = 0;
+  a.dmask_words = 0;
   return a;
 }
 
@@ -127,6 +135,10 @@ int merbit_spmm_zero_boundary(merbit_plan* p, void* Y, int64_t ldy, int k, void*
   return merbit::host_exception();
 }
 
+// Buffers of the personalised PageRank: pbuf[0] holds A X at the tiles'
+// first rows (zero there between steps), pbuf[2] the second iterate; ppart
+// the per-block parts of one step (the SpMM's blocks, then the first-row
+// fix-up's, then the l1 change's).
 static int ensure_ppr_state(merbit_plan* p, int k, hipStream_t st) {
   int rc = ensure_dmask(p, st);
   if (rc != MERBIT_OK) return rc;
@@ -137,17 +149,72 @@ static int ensure_ppr_state(merbit_plan* p, int k, hipStream_t st) {
       p->pbuf[b] = nullptr;
     }
     const size_t bytes = vsize(p->dtype) * (size_t)p->n_rows * (size_t)k;
-    for (int b = 0; b < 3; ++b) HIP_TRY(hipMalloc(&p->pbuf[b], bytes));
+    HIP_TRY(hipMalloc(&p->pbuf[0], bytes));
+    HIP_TRY(hipMalloc(&p->pbuf[2], bytes));
     p->ppr_k = k;
     p->ppr_zeroed = -1;
   }
   if (!p->ppart) {
     p->ppr_grid_n = ppr_grid(p->n_rows);
-    HIP_TRY(hipMalloc(&p->ppart, sizeof(double) * 2 * 64 * (size_t)p->ppr_grid_n));
+    const size_t rows = (size_t)spmm_blocks(p->tile_num) + (size_t)ppr_fixup_grid(p->tile_num) +
+                        (size_t)p->ppr_grid_n;
+    HIP_TRY(hipMalloc(&p->ppart, sizeof(double) * 2 * 64 * rows));
     HIP_TRY(hipMalloc(&p->psums[0], sizeof(double) * 2 * 64));
     HIP_TRY(hipMalloc(&p->psums[1], sizeof(double) * 2 * 64));
     HIP_TRY(hipMalloc(&p->psrc, sizeof(int32_t) * 64));
   }
+  return MERBIT_OK;
+}
+
+// One personalised-PageRank step X -> Xn (kernels in merbit_batched.hip):
+// the SpMM slabs with the rows inside tiles finished in their commit, the
+// tiles' first rows, on request the l1 change, and the per-column sums of
+// the parts into sums_out.  The SpMM launches are bracketed by one pair of
+// events when profiling is on.
+static int ppr_step(merbit_plan* p, const void* X, void* Xn, int k, double alpha,
+                    const double* sums_in, double* sums_out, bool resid, hipStream_t st) {
+  const size_t vs = vsize(p->dtype);
+  const int64_t n = p->n_rows;
+  const int sb = spmm_blocks(p->tile_num), fb = ppr_fixup_grid(p->tile_num);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (p->profiling) {
+    if (p->events_used == p->events.size()) {
+      hipEvent_t a, b;
+      HIP_TRY(hipEventCreate(&a));
+      HIP_TRY(hipEventCreate(&b));
+      p->events.emplace_back(a, b);
+    }
+    e0 = p->events[p->events_used].first;
+    e1 = p->events[p->events_used].second;
+    ++p->events_used;
+    HIP_TRY(hipEventRecord(e0, st));
+  }
+  for (int c0 = 0; c0 < k; c0 += kSpmmSlab) {
+    const int kk = k - c0 < kSpmmSlab ? k - c0 : kSpmmSlab;
+    SpmmArgs a = spmm_args(p, static_cast<const char*>(X) + vs * c0, k,
+                           static_cast<char*>(p->pbuf[0]) + vs * c0, k, nullptr, 0, kk);
+    a.Xn = static_cast<char*>(Xn) + vs * c0;
+    a.src = p->psrc + c0;
+    a.sums_in = sums_in + 2 * c0;
+    a.dmask = p->dmask;
+    a.part = p->ppart;
+    a.alpha = alpha;
+    a.col0 = c0;
+    a.dmask_words = (int32_t)((n + 31) / 32);
+    HIP_TRY(launch_spmm(p->dtype, p->sigma, a, st));
+  }
+  if (p->profiling) HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(launch_ppr_fixup(p->dtype, p->tile_y, (int32_t)p->tile_num, p->pbuf[0], Xn, n, k,
+                           alpha, p->psrc, sums_in, p->dmask, p->ppart + (size_t)sb * 128, fb,
+                           st));
+  int nb = sb + fb;
+  if (resid) {
+    HIP_TRY(launch_ppr_resid(p->dtype, Xn, X, n, k, p->ppart + (size_t)nb * 128, p->ppr_grid_n,
+                             st));
+    nb += p->ppr_grid_n;
+  }
+  HIP_TRY(launch_ppr_sum(p->ppart, nb, k, sums_out, st));
+  p->last_stream = st;
   return MERBIT_OK;
 }
 
@@ -181,10 +248,9 @@ int merbit_pagerank_personalized(merbit_plan* p, double alpha, double tol, int m
                          st));
   HIP_TRY(launch_ppr_dangling(p->dtype, X_inout, p->dmask, n, k, p->ppart, p->psums[0],
                               p->ppr_grid_n, st));
-  int yb = p->ppr_zeroed;
-  if (yb < 0) {
-    yb = 0;
+  if (p->ppr_zeroed < 0) {  // A X's buffer: zero at the tiles' first rows
     HIP_TRY(launch_spmm_zero(p->dtype, p->tile_y, (int32_t)p->tile_num, p->pbuf[0], k, k, st));
+    p->ppr_zeroed = 0;
   }
   void* xs[2] = {X_inout, p->pbuf[2]};
   double host_sums[128];
@@ -193,24 +259,23 @@ int merbit_pagerank_personalized(merbit_plan* p, double alpha, double tol, int m
   while (t < max_iter) {
     int len = check_every - t % check_every;
     if (len > max_iter - t) len = max_iter - t;
-    const int t0 = t, yb0 = yb;
+    const int t0 = t;
+    // the l1 change is computed on the chunk's last step only (the host
+    // reads it after the chunk)
     auto enqueue = [&](hipStream_t s) -> int {
       for (int i = 0; i < len; ++i) {
-        const int cur = (t0 + i) & 1, b = yb0 ^ (i & 1);
-        const int r = run_spmm(p, xs[cur], k, p->pbuf[b], k, p->pbuf[b ^ 1], k, k, s);
+        const int cur = (t0 + i) & 1;
+        const int r = ppr_step(p, xs[cur], xs[cur ^ 1], k, alpha, p->psums[cur],
+                               p->psums[cur ^ 1], i == len - 1, s);
         if (r != MERBIT_OK) return r;
-        HIP_TRY(launch_ppr_update(p->dtype, p->pbuf[b], xs[cur], xs[cur ^ 1], p->dmask, n, k,
-                                  alpha, p->psrc, p->psums[cur], p->ppart, p->psums[cur ^ 1],
-                                  p->ppr_grid_n, s));
       }
       return MERBIT_OK;
     };
     rc = len == check_every
-             ? run_chunk(p, kLoopPersonalized, t0 & 1, yb0, len, k, X_inout, alpha, enqueue, st)
+             ? run_chunk(p, kLoopPersonalized, t0 & 1, 0, len, k, X_inout, alpha, enqueue, st)
              : enqueue(st);
     if (rc != MERBIT_OK) return rc;
     t += len;
-    yb ^= len & 1;
     if (tol > 0.0 || t == max_iter) {
       HIP_TRY(hipMemcpyAsync(host_sums, p->psums[t & 1], sizeof host_sums,
                              hipMemcpyDeviceToHost, st));
@@ -226,7 +291,6 @@ int merbit_pagerank_personalized(merbit_plan* p, double alpha, double tol, int m
       }
     }
   }
-  p->ppr_zeroed = yb;
   p->last_stream = st;
   if (t & 1) HIP_TRY(hipMemcpyAsync(X_inout, p->pbuf[2], bytes, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));

@@ -46,6 +46,60 @@ __device__ __forceinline__ void spmm_commit(V* Y, int64_t ld, int row_abs, int r
   }
 }
 
+// Per-lane state of a fused personalised-PageRank step (SpmmArgs::Xn).
+template <typename V>
+struct PprRow {
+  V* Xn;
+  int64_t ld;
+  V a;          // alpha
+  V tele;       // alpha delta_j + 1 - alpha, added at the column's source row
+  int sj;       // the column's source row (-1: lane past the slab)
+  int w0;       // dmask word of the tile's first row
+  uint32_t dm;  // lane l: dmask word w0 + l (the tile's rows are < 32 words)
+  double dsum;  // dangling mass of the rows this lane finished
+};
+
+// Row row_abs, strictly inside the tile, is complete: its next iterate
+// value, written here instead of Y (called by the whole wavefront).
+template <typename V>
+__device__ __forceinline__ void ppr_finish_row(PprRow<V>& f, int row_abs, V acc, bool lane_on,
+                                               int lid) {
+  V xn = f.a * acc;
+  if (row_abs == f.sj) xn += f.tele;
+  if (lane_on) __builtin_nontemporal_store(xn, f.Xn + (int64_t)row_abs * f.ld + lid);
+  const uint32_t word = (uint32_t)__builtin_amdgcn_readlane((int)f.dm, (row_abs >> 5) - f.w0);
+  if ((word >> (row_abs & 31)) & 1u) f.dsum += (double)xn;
+}
+
+// A finished row of the tile: the first and last rows go to Y (shared with
+// neighbouring tiles); the others are stored (plain SpMM) or finished as
+// the next iterate (fused step).  Called by the whole wavefront.
+template <typename V, bool FUSE>
+__device__ __forceinline__ void spmm_row(V* Y, int64_t ld, int row_abs, int rel, int last_rel,
+                                         int n_rows, V acc, bool lane_on, int lid,
+                                         PprRow<V>& f) {
+  if constexpr (FUSE) {
+    if (rel == 0 || rel == last_rel) {
+      if (lane_on && row_abs < n_rows) global_add(Y + (int64_t)row_abs * ld + lid, acc);
+    } else {
+      ppr_finish_row(f, row_abs, acc, lane_on, lid);
+    }
+  } else {
+    spmm_commit(Y, ld, row_abs, rel, last_rel, n_rows, acc, lane_on, lid);
+  }
+}
+
+// An empty row strictly inside the tile.
+template <typename V, bool FUSE>
+__device__ __forceinline__ void spmm_empty_row(V* Y, int64_t ld, int row_abs, bool lane_on,
+                                               int lid, PprRow<V>& f) {
+  if constexpr (FUSE) {
+    ppr_finish_row(f, row_abs, V(0), lane_on, lid);
+  } else {
+    if (lane_on) Y[(int64_t)row_abs * ld + lid] = V(0);
+  }
+}
+
 // value of lane `lane` of v (lane uniform), in scalar registers
 __device__ __forceinline__ int lane_value(int v, int lane) {
   return __builtin_amdgcn_readlane(v, lane);
@@ -85,10 +139,10 @@ __device__ __forceinline__ V load_x_row(__amdgpu_buffer_rsrc_t rx, const V* __re
   }
 }
 
-template <typename V, int SIGMA, bool BUF>
+template <typename V, int SIGMA, bool BUF, bool FUSE>
 __device__ __forceinline__ void spmm_walk(const SpmmArgs& a, const int32_t* __restrict__ wrow,
                                           int x_ws, int x_se, int y_ws, int last_rel, int lid,
-                                          bool lane_on, V& acc, int& cur) {
+                                          bool lane_on, V& acc, int& cur, PprRow<V>& f) {
   const V* __restrict__ X = static_cast<const V*>(a.X);
   V* __restrict__ Y = static_cast<V*>(a.Y);
   const int32_t* __restrict__ col = a.col + x_ws;
@@ -129,9 +183,9 @@ __device__ __forceinline__ void spmm_walk(const SpmmArgs& a, const int32_t* __re
         if (q < cnt) {
           if ((starts >> q) & 1ull) {
             const int r = lane_value(r_l, q);
-            spmm_commit(Y, ldy, y_ws + cur, cur, last_rel, a.n_rows, acc, lane_on, lid);
+            spmm_row<V, FUSE>(Y, ldy, y_ws + cur, cur, last_rel, a.n_rows, acc, lane_on, lid, f);
             for (int e = cur + 1; e < r; ++e)  // empty rows strictly inside the tile
-              if (lane_on) Y[(int64_t)(y_ws + e) * ldy + lid] = V(0);
+              spmm_empty_row<V, FUSE>(Y, ldy, y_ws + e, lane_on, lid, f);
             cur = r;
             acc = V(0);
           }
@@ -142,7 +196,7 @@ __device__ __forceinline__ void spmm_walk(const SpmmArgs& a, const int32_t* __re
   }
 }
 
-template <typename V, int SIGMA>
+template <typename V, int SIGMA, bool FUSE>
 __global__ __launch_bounds__(kSpmmWaves * 64) void spmm_kernel(SpmmArgs a) {
   constexpr int WLDS = kOmega * SIGMA;
   __shared__ int32_t s_row[kSpmmWaves * WLDS];
@@ -150,41 +204,78 @@ __global__ __launch_bounds__(kSpmmWaves * 64) void spmm_kernel(SpmmArgs a) {
   const int lid = threadIdx.x & (kOmega - 1);
   const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kOmega);
   const int t = blockIdx.x * kSpmmWaves + wid;
-  if (t >= a.tile_num) return;  // no block-wide synchronisation in this kernel
-  int32_t* wrow = s_row + wid * WLDS;
-
-  V* __restrict__ Y = static_cast<V*>(a.Y);
   const bool lane_on = lid < a.k;
-  const int x_ws = a.tile_x[t];
-  const int x_se = a.tile_x[t + 1] - x_ws;
-  const uint32_t tyw = a.tile_y[t];
-  const int y_ws = (int)(tyw & kRowMask);
-  const int y_we = (int)(a.tile_y[t + 1] & kRowMask);
-  const int last_rel = y_we - y_ws;
+  PprRow<V> f{};
+  if constexpr (FUSE) {
+    f.Xn = static_cast<V*>(a.Xn);
+    f.ld = a.ldx;
+    f.a = (V)a.alpha;
+    f.sj = lane_on ? a.src[lid] : -1;
+    f.tele = lane_on ? (V)(a.alpha * a.sums_in[2 * lid] + 1.0 - a.alpha) : V(0);
+    f.dsum = 0.0;
+  }
+  // without the fused step no block-wide synchronisation follows: a
+  // wavefront past the last tile may leave at once
+  if (t < a.tile_num) {
+    int32_t* wrow = s_row + wid * WLDS;
+    V* __restrict__ Y = static_cast<V*>(a.Y);
+    const int x_ws = a.tile_x[t];
+    const int x_se = a.tile_x[t + 1] - x_ws;
+    const uint32_t tyw = a.tile_y[t];
+    const int y_ws = (int)(tyw & kRowMask);
+    const int y_we = (int)(a.tile_y[t + 1] & kRowMask);
+    const int last_rel = y_we - y_ws;
+    if constexpr (FUSE) {
+      // the tile's rows y_ws .. y_we span at most 64 sigma / 32 + 2 words
+      f.w0 = y_ws >> 5;
+      f.dm = f.w0 + lid < a.dmask_words ? a.dmask[f.w0 + lid] : 0u;
+    }
 
-  tile_nz_rows<SIGMA>(a.lane_desc, a.lane_num, a.path_len, t, tyw, x_se, lid, wrow);
-  wave_lds_sync();
+    tile_nz_rows<SIGMA>(a.lane_desc, a.lane_num, a.path_len, t, tyw, x_se, lid, wrow);
+    wave_lds_sync();
 
-  V acc = V(0);
-  int cur = 0;  // current row, relative to y_ws
-  const bool buf = ((int64_t)a.x_rows * a.ldx) * (int64_t)sizeof(V) < ((int64_t)1 << 31);
-  if (buf)
-    spmm_walk<V, SIGMA, true>(a, wrow, x_ws, x_se, y_ws, last_rel, lid, lane_on, acc, cur);
-  else
-    spmm_walk<V, SIGMA, false>(a, wrow, x_ws, x_se, y_ws, last_rel, lid, lane_on, acc, cur);
-  const int64_t ldy = a.ldy;
-  if (x_se > 0) spmm_commit(Y, ldy, y_ws + cur, cur, last_rel, a.n_rows, acc, lane_on, lid);
-  // rows after the last nonzero and strictly inside the tile are empty
-  for (int e = (x_se > 0 ? cur + 1 : 1); e < last_rel; ++e)
-    if (lane_on) Y[(int64_t)(y_ws + e) * ldy + lid] = V(0);
-  if (a.Z != nullptr && lane_on)
-    static_cast<V*>(a.Z)[(int64_t)y_ws * a.ldz + lid] = V(0);
+    V acc = V(0);
+    int cur = 0;  // current row, relative to y_ws
+    const bool buf = ((int64_t)a.x_rows * a.ldx) * (int64_t)sizeof(V) < ((int64_t)1 << 31);
+    if (buf)
+      spmm_walk<V, SIGMA, true, FUSE>(a, wrow, x_ws, x_se, y_ws, last_rel, lid, lane_on, acc,
+                                      cur, f);
+    else
+      spmm_walk<V, SIGMA, false, FUSE>(a, wrow, x_ws, x_se, y_ws, last_rel, lid, lane_on, acc,
+                                       cur, f);
+    const int64_t ldy = a.ldy;
+    if (x_se > 0)
+      spmm_row<V, FUSE>(Y, ldy, y_ws + cur, cur, last_rel, a.n_rows, acc, lane_on, lid, f);
+    // rows after the last nonzero and strictly inside the tile are empty
+    for (int e = (x_se > 0 ? cur + 1 : 1); e < last_rel; ++e)
+      spmm_empty_row<V, FUSE>(Y, ldy, y_ws + e, lane_on, lid, f);
+    if (a.Z != nullptr && lane_on)
+      static_cast<V*>(a.Z)[(int64_t)y_ws * a.ldz + lid] = V(0);
+  }
+  if constexpr (FUSE) {
+    // the block's dangling mass per column, its wavefronts added in order
+    __shared__ double s_d[kSpmmWaves][kOmega];
+    s_d[wid][lid] = f.dsum;
+    __syncthreads();
+    if (wid == 0 && lane_on) {
+      double d = 0.0;
+      for (int w = 0; w < kSpmmWaves; ++w) d += s_d[w][lid];
+      double* o = a.part + ((int64_t)blockIdx.x * kOmega + a.col0 + lid) * 2;
+      o[0] = d;
+      o[1] = 0.0;
+    }
+  }
 }
+
+int spmm_blocks(int64_t tile_num) { return (int)((tile_num + kSpmmWaves - 1) / kSpmmWaves); }
 
 template <typename V, int S>
 static hipError_t spmm_launch_t(const SpmmArgs& a, hipStream_t st) {
-  const unsigned grid = (unsigned)((a.tile_num + kSpmmWaves - 1) / kSpmmWaves);
-  hipLaunchKernelGGL((spmm_kernel<V, S>), dim3(grid), dim3(kSpmmWaves * 64), 0, st, a);
+  const unsigned grid = (unsigned)spmm_blocks(a.tile_num);
+  if (a.Xn != nullptr)
+    hipLaunchKernelGGL((spmm_kernel<V, S, true>), dim3(grid), dim3(kSpmmWaves * 64), 0, st, a);
+  else
+    hipLaunchKernelGGL((spmm_kernel<V, S, false>), dim3(grid), dim3(kSpmmWaves * 64), 0, st, a);
   return hipGetLastError();
 }
 
@@ -236,67 +327,98 @@ hipError_t launch_spmm_zero(int dtype, const uint32_t* tile_y, int32_t tile_num,
 //
 // Column j of X is the rank vector of source src[j]:
 //   X'[r, j] = alpha Y[r, j] + (r == src[j]) (alpha delta_j + 1 - alpha),
-// with delta_j the dangling mass of column j.  Every block writes, per column,
-// its part of the next dangling mass and of the l1 change; a second kernel
-// (one block per column) sums those parts in a fixed order for the next step
-// and the host.  Thread t always handles column t % 64, so each wavefront
-// reads and writes whole rows of X and Y (coalesced); a wavefront takes
-// kPprRows rows per pass with all their loads issued first.
+// with delta_j the dangling mass of column j and Y = A X.  The SpMM finishes
+// every row strictly inside a tile as X' itself (SpmmArgs::Xn) and adds its
+// dangling mass to a per-block, per-column part; ppr_fixup_kernel finishes
+// the tiles' first rows from Y (where neighbouring tiles added into them)
+// and clears those slots of Y for the next step; on the last step of a
+// chunk ppr_resid_kernel adds the l1 change.  A last kernel (one block per
+// column) sums the parts in a fixed order for the next step and the host.
+// Thread t of these kernels always handles column t % 64, so each
+// wavefront reads and writes whole rows (coalesced).
 
 constexpr int kPprThreads = 256;
 constexpr int kPprWaves = kPprThreads / 64;
 constexpr int kPprRows = 4;
 
+// 64 per-thread (a, b) pairs of the block (thread t: column t % 64) summed
+// over its wavefronts in order, written as part_out row blockIdx.x
+__device__ __forceinline__ void ppr_block_part(double a, double b, double* __restrict__ part_out) {
+  __shared__ double s_a[kPprThreads], s_b[kPprThreads];
+  s_a[threadIdx.x] = a;
+  s_b[threadIdx.x] = b;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double x = 0.0, y = 0.0;
+    for (int q = 0; q < kPprWaves; ++q) {
+      x += s_a[q * 64 + threadIdx.x];
+      y += s_b[q * 64 + threadIdx.x];
+    }
+    part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2] = x;
+    part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2 + 1] = y;
+  }
+}
+
+int ppr_fixup_grid(int64_t tile_num) {
+  int64_t g = (tile_num + kPprWaves * 8 - 1) / (kPprWaves * 8);
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
 template <typename V>
-__global__ __launch_bounds__(kPprThreads) void ppr_update_kernel(
-    const V* __restrict__ Y, const V* __restrict__ X_old, V* __restrict__ X_new,
-    const uint32_t* __restrict__ dmask, int64_t n, int k, double alpha,
-    const int32_t* __restrict__ src,
-    const double* __restrict__ delta_in,  // (dangling mass, l1 change) per column
+__global__ __launch_bounds__(kPprThreads) void ppr_fixup_kernel(
+    const uint32_t* __restrict__ tile_y, int32_t tile_num, V* __restrict__ Y,
+    V* __restrict__ Xn, int64_t n, int k, double alpha, const int32_t* __restrict__ src,
+    const double* __restrict__ sums_in, const uint32_t* __restrict__ dmask,
     double* __restrict__ part_out) {
-  __shared__ double s_d[kPprThreads], s_r[kPprThreads];
   const int j = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const bool on = j < k;
-  const V a = (V)alpha;
-  double dsum = 0.0, rsum = 0.0;
   const int sj = on ? src[j] : -1;
-  const V tele = on ? (V)(alpha * delta_in[2 * j] + 1.0 - alpha) : V(0);
+  const V a = (V)alpha;
+  const V tele = on ? (V)(alpha * sums_in[2 * j] + 1.0 - alpha) : V(0);
+  double dsum = 0.0;
+  const int64_t step = (int64_t)gridDim.x * kPprWaves;
+  for (int64_t t = (int64_t)blockIdx.x * kPprWaves + w; t < tile_num; t += step) {
+    const int64_t r = tile_y[t] & kRowMask;
+    // each first row once (a long row is the first row of several tiles)
+    if (r >= n || (t > 0 && (int64_t)(tile_y[t - 1] & kRowMask) == r)) continue;
+    if (on) {
+      V* yp = Y + r * k + j;
+      V xn = a * *yp;
+      *yp = V(0);
+      if (r == sj) xn += tele;
+      Xn[r * k + j] = xn;
+      if ((dmask[r >> 5] >> (r & 31)) & 1u) dsum += (double)xn;
+    }
+  }
+  ppr_block_part(dsum, 0.0, part_out);
+}
+
+template <typename V>
+__global__ __launch_bounds__(kPprThreads) void ppr_resid_kernel(const V* __restrict__ Xn,
+                                                                const V* __restrict__ Xo,
+                                                                int64_t n, int k,
+                                                                double* __restrict__ part_out) {
+  const int j = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  double rsum = 0.0;
   const int64_t step = (int64_t)gridDim.x * kPprWaves * kPprRows;
-  for (int64_t r0 = ((int64_t)blockIdx.x * kPprWaves + w) * kPprRows; on && r0 < n; r0 += step) {
-    V yv[kPprRows], xo[kPprRows];
-    uint32_t mw[kPprRows];
+  for (int64_t r0 = ((int64_t)blockIdx.x * kPprWaves + w) * kPprRows; j < k && r0 < n;
+       r0 += step) {
+    V xn[kPprRows], xo[kPprRows];
 #pragma unroll
     for (int u = 0; u < kPprRows; ++u) {
       const int64_t r = min(r0 + u, n - 1);
-      yv[u] = Y[r * k + j];
-      xo[u] = X_old[r * k + j];
-      mw[u] = dmask[r >> 5];
+      xn[u] = Xn[r * k + j];
+      xo[u] = Xo[r * k + j];
     }
 #pragma unroll
-    for (int u = 0; u < kPprRows; ++u) {
-      const int64_t r = r0 + u;
-      if (r < n) {
-        V xn = a * yv[u];
-        if (r == sj) xn += tele;
-        X_new[r * k + j] = xn;
-        rsum += fabs((double)xn - (double)xo[u]);
-        if ((mw[u] >> (r & 31)) & 1u) dsum += (double)xn;
-      }
-    }
+    for (int u = 0; u < kPprRows; ++u)
+      if (r0 + u < n) rsum += fabs((double)xn[u] - (double)xo[u]);
   }
-  s_d[threadIdx.x] = dsum;
-  s_r[threadIdx.x] = rsum;
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    double d = 0.0, rr = 0.0;
-    for (int q = 0; q < kPprWaves; ++q) {
-      d += s_d[q * 64 + threadIdx.x];
-      rr += s_r[q * 64 + threadIdx.x];
-    }
-    part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2] = d;
-    part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2 + 1] = rr;
-  }
+  ppr_block_part(0.0, rsum, part_out);
 }
 
 // dangling mass of X (per column) -> the same per-block part layout
@@ -304,7 +426,6 @@ template <typename V>
 __global__ __launch_bounds__(kPprThreads) void ppr_dangling_kernel(
     const V* __restrict__ X, const uint32_t* __restrict__ dmask, int64_t n, int k,
     double* __restrict__ part_out) {
-  __shared__ double s_d[kPprThreads];
   const int j = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   double dsum = 0.0;
@@ -317,14 +438,7 @@ __global__ __launch_bounds__(kPprThreads) void ppr_dangling_kernel(
       if (r < n && ((dmask[r >> 5] >> (r & 31)) & 1u)) dsum += (double)X[r * k + j];
     }
   }
-  s_d[threadIdx.x] = dsum;
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    double d = 0.0;
-    for (int q = 0; q < kPprWaves; ++q) d += s_d[q * 64 + threadIdx.x];
-    part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2] = d;
-    part_out[((int64_t)blockIdx.x * 64 + threadIdx.x) * 2 + 1] = 0.0;
-  }
+  ppr_block_part(dsum, 0.0, part_out);
 }
 
 // sums[2j], sums[2j+1] = totals over the blocks of column j's parts: block j
@@ -352,8 +466,9 @@ int ppr_grid(int64_t n) {
   return (int)g;
 }
 
-static hipError_t launch_ppr_sum(const double* part, int grid, double* sums, hipStream_t st) {
-  hipLaunchKernelGGL(ppr_sum_parts_kernel, dim3(64), dim3(kReduceThreads), 0, st, part, grid,
+hipError_t launch_ppr_sum(const double* part, int nblocks, int k, double* sums,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(ppr_sum_parts_kernel, dim3(k), dim3(kReduceThreads), 0, st, part, nblocks,
                      sums);
   return hipGetLastError();
 }
@@ -368,24 +483,34 @@ hipError_t launch_ppr_dangling(int dtype, const void* X, const uint32_t* dmask, 
                        static_cast<const double*>(X), dmask, n, k, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_ppr_sum(part, grid, sums, st);
+  return launch_ppr_sum(part, grid, k, sums, st);
 }
 
-hipError_t launch_ppr_update(int dtype, const void* Y, const void* X_old, void* X_new,
-                             const uint32_t* dmask, int64_t n, int k, double alpha,
-                             const int32_t* src, const double* sums_in, double* part,
-                             double* sums_out, int grid, hipStream_t st) {
+hipError_t launch_ppr_fixup(int dtype, const uint32_t* tile_y, int32_t tile_num, void* Y,
+                            void* Xn, int64_t n, int k, double alpha, const int32_t* src,
+                            const double* sums_in, const uint32_t* dmask, double* part, int grid,
+                            hipStream_t st) {
   if (dtype == 0)
-    hipLaunchKernelGGL(ppr_update_kernel<float>, dim3(grid), dim3(kPprThreads), 0, st,
-                       static_cast<const float*>(Y), static_cast<const float*>(X_old),
-                       static_cast<float*>(X_new), dmask, n, k, alpha, src, sums_in, part);
+    hipLaunchKernelGGL(ppr_fixup_kernel<float>, dim3(grid), dim3(kPprThreads), 0, st, tile_y,
+                       tile_num, static_cast<float*>(Y), static_cast<float*>(Xn), n, k, alpha,
+                       src, sums_in, dmask, part);
   else
-    hipLaunchKernelGGL(ppr_update_kernel<double>, dim3(grid), dim3(kPprThreads), 0, st,
-                       static_cast<const double*>(Y), static_cast<const double*>(X_old),
-                       static_cast<double*>(X_new), dmask, n, k, alpha, src, sums_in, part);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return launch_ppr_sum(part, grid, sums_out, st);
+    hipLaunchKernelGGL(ppr_fixup_kernel<double>, dim3(grid), dim3(kPprThreads), 0, st, tile_y,
+                       tile_num, static_cast<double*>(Y), static_cast<double*>(Xn), n, k, alpha,
+                       src, sums_in, dmask, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_ppr_resid(int dtype, const void* Xn, const void* Xo, int64_t n, int k,
+                            double* part, int grid, hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(ppr_resid_kernel<float>, dim3(grid), dim3(kPprThreads), 0, st,
+                       static_cast<const float*>(Xn), static_cast<const float*>(Xo), n, k, part);
+  else
+    hipLaunchKernelGGL(ppr_resid_kernel<double>, dim3(grid), dim3(kPprThreads), 0, st,
+                       static_cast<const double*>(Xn), static_cast<const double*>(Xo), n, k,
+                       part);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------ PageRank of many graphs --

@@ -72,12 +72,12 @@ struct merbit_plan {
   int zeroed_buf = -1;  // which ybuf is zero at the boundary rows, -1 if none
   // personalised PageRank state (k columns)
   int ppr_k = 0;
-  void* pbuf[3] = {nullptr, nullptr, nullptr};  // two SpMM outputs, one iterate
+  void* pbuf[3] = {nullptr, nullptr, nullptr};  // A X at the tiles' first rows, -, one iterate
   double* ppart = nullptr;                      // per-block, per-column pairs
   double* psums[2] = {nullptr, nullptr};        // per-column (dangling mass, l1 change)
   int32_t* psrc = nullptr;
   int ppr_grid_n = 0;
-  int ppr_zeroed = -1;
+  int ppr_zeroed = -1;  // 0 once pbuf[0] is zero at the tiles' first rows
   // PageRank of the graphs on the diagonal (tables for the last graph_ptr)
   std::vector<int64_t> multi_gp;
   int32_t* multi_chunk_row = nullptr;

@@ -233,6 +233,19 @@ struct SpmmArgs {
   int32_t lane_num;
   int32_t path_len;
   int32_t n_rows;
+  // A personalised-PageRank step finished in the commit (Xn == nullptr: plain
+  // Y = A X).  Rows strictly inside a tile become Xn = alpha (A X) plus the
+  // teleport at their column's source and add their dangling mass to the
+  // block's part; a tile's first and last rows still go to Y, which
+  // ppr_fixup finishes (and clears) after the launch.
+  void* Xn;                // next iterate: the slab's first column, row stride ldx
+  const int32_t* src;      // per column of the slab: its source row
+  const double* sums_in;   // per column of the slab: (dangling mass, l1 change) of X
+  const uint32_t* dmask;   // dangling rows, one bit each
+  double* part;            // [blocks][64][2]: the block's (dangling mass, 0) per column
+  double alpha;
+  int32_t col0;            // the slab's first column (its place among part's 64)
+  int32_t dmask_words;     // ceil(n_rows / 32)
 };
 
 // CSR checks; *flags gets bit 0: row_ptr[0] != 0, bit 1: row_ptr[n] != nnz,
@@ -457,11 +470,23 @@ hipError_t launch_spmm(int dtype, int sigma, const SpmmArgs& a, hipStream_t st);
 hipError_t launch_spmm_zero(int dtype, const uint32_t* tile_y, int32_t tile_num, void* Y,
                             int64_t ld, int k, hipStream_t st);
 int ppr_grid(int64_t n);
+// blocks of one SpMM launch over tile_num tiles (the fused step's part rows)
+int spmm_blocks(int64_t tile_num);
+// blocks of ppr_fixup over tile_num tiles
+int ppr_fixup_grid(int64_t tile_num);
 hipError_t launch_ppr_dangling(int dtype, const void* X, const uint32_t* dmask, int64_t n, int k,
                                double* part, double* sums, int grid, hipStream_t st);
-hipError_t launch_ppr_update(int dtype, const void* Y, const void* X_old, void* X_new,
-                             const uint32_t* dmask, int64_t n, int k, double alpha,
-                             const int32_t* src, const double* sums_in, double* part,
-                             double* sums_out, int grid, hipStream_t st);
+// The tiles' first rows (each once) of a fused personalised-PageRank step:
+// Xn = alpha Y + teleport at the source, Y cleared there for the next step,
+// the dangling mass into part ([grid][64][2]).  All k columns (ld = k).
+hipError_t launch_ppr_fixup(int dtype, const uint32_t* tile_y, int32_t tile_num, void* Y,
+                            void* Xn, int64_t n, int k, double alpha, const int32_t* src,
+                            const double* sums_in, const uint32_t* dmask, double* part, int grid,
+                            hipStream_t st);
+// part ([grid][64][2]) = per block and column (0, sum over rows of |Xn - Xo|)
+hipError_t launch_ppr_resid(int dtype, const void* Xn, const void* Xo, int64_t n, int k,
+                            double* part, int grid, hipStream_t st);
+// sums[2j], sums[2j + 1] = column j's totals over nblocks part rows, j < k
+hipError_t launch_ppr_sum(const double* part, int nblocks, int k, double* sums, hipStream_t st);
 
 }  // namespace merbit
