@@ -310,10 +310,12 @@ def run_gpu(w, dtype_name: str, steps: int, warmup: int, sigma: int, block_lanes
     }
 
 
-def run_ppr(w, k: int, steps: int, warmup: int, alpha: float):
+def run_ppr(w, k: int, steps: int, warmup: int, alpha: float, sigma: int = 0):
     """Personalised PageRank for k sources at once on the workload graph
     (FP32): a step is one SpMM over k right-hand sides plus the per-column
-    update, on a plan whose sigma the autotuner measured fastest for the SpMM.
+    update, on a plan whose sigma the autotuner measured fastest for the SpMM
+    (sigma > 0: that sigma, no tuning; the tuned sigmas are within a few
+    percent of each other, so a profile that must see one kernel fixes it).
     Returns step and SpMM-kernel times and the SpMM's bandwidth against its
     compulsory bytes (A once, X once, Y once, the plan's tiles and
     descriptors)."""
@@ -327,8 +329,11 @@ def run_ppr(w, k: int, steps: int, warmup: int, alpha: float):
     c = torch.from_numpy(w["col"]).to(dev)
     v = torch.from_numpy(w["values"]).float().to(dev)
     # sigma of the SpMM by measurement on this matrix (untimed)
-    best, table = pkg.tune(r, c, v, n, sigmas=list(range(4, 13)), block_lanes=[256], reps=5,
-                           rhs=k)
+    if sigma > 0:
+        best, table = {"sigma": sigma}, {}
+    else:
+        best, table = pkg.tune(r, c, v, n, sigmas=list(range(4, 13)), block_lanes=[256],
+                               reps=5, rhs=k)
     plan = pkg.Plan(r, c, v, n, validate=False, sigma=best["sigma"])
     src = graphgen.ppr_sources(n, k, seed=4)
     # untimed: warm-up iterations in the timed run's chunk shape, so its HIP
@@ -724,6 +729,8 @@ def main():
     ap.add_argument("--no-multi", action="store_true",
                     help="skip the 256-graph block of the batched runs (keep the 64-source PPR)")
     ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--spmm-sigma", type=int, default=0,
+                    help="sigma of the 64-source PPR's SpMM instead of tuning it (4..12)")
     ap.add_argument("--no-adjoint", action="store_true",
                     help="skip the differentiable-PageRank run (R-MAT scale 20)")
     ap.add_argument("--adjoint-scale", type=int, default=20)
@@ -818,7 +825,7 @@ def main():
               f"{r64['spmv_ms'] * 1e3:.1f} us", file=sys.stderr, flush=True)
     batched = None
     if not args.no_batched and w["meta"]["generator"] == "rmat":
-        ppr = run_ppr(w, 64, args.batched_steps, 2, args.alpha)
+        ppr = run_ppr(w, 64, args.batched_steps, 2, args.alpha, sigma=args.spmm_sigma)
         ppr["vs_plain_spmv"] = round(ppr["gnz_rhs_per_s"] / main_run["spmv_gnzs"], 3)
         print(f"[bench] ppr64: step {ppr['ms_per_step']:.3f} ms, spmm {ppr['spmm_us']:.1f} us",
               file=sys.stderr, flush=True)

@@ -295,7 +295,9 @@ int merbit_spmm_zero_boundary(merbit_plan* plan, void* Y, int64_t ldy, int k, vo
  *              change per column
  * A step is the SpMM (slabs of 32 columns) with the update of every row
  * strictly inside a tile done in its commit, then one kernel for the tiles'
- * first rows; the plan keeps two n x k work buffers of its dtype after the
+ * first rows.  For k > 32 the iterates are held as compact 32-column slabs
+ * (X_inout is converted on entry and back on return).  The plan keeps two
+ * (k <= 32) or three (k > 32) n x k work buffers of its dtype after the
  * first call (freed by merbit_plan_destroy).
  * Returns MERBIT_OK or MERBIT_NOT_CONVERGED; synchronises `stream`. */
 int merbit_pagerank_personalized(merbit_plan* plan, double alpha, double tol, int max_iter,

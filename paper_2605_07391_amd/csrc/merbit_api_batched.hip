@@ -40,17 +40,16 @@ static SpmmArgs spmm_args(const merbit_plan* p, const void* X, int64_t ldx, void
   return a;
 }
 
-// One SpMM launch per slab of at most kSpmmSlab columns, the slabs one after
+// One SpMM launch per slab of at most kSlab columns, the slabs one after
 // another; the whole call is bracketed by one pair of events when profiling
 // is on.  64 columns of R-MAT 22 took, as 1 / 2 / 4 launches: FP32 2.89 /
 // 2.53 / 13.7 ms (as many L2 misses and bytes read in the 2 launches as in
 // the 1: the misses are served faster), FP64 6.2 / 5.4 / 9.1 ms.
-constexpr int kSpmmSlab = 32;
 
 static int run_spmm(merbit_plan* p, const void* X, int64_t ldx, void* Y, int64_t ldy, void* Z,
                     int64_t ldz, int k, hipStream_t st) {
   const size_t vs = vsize(p->dtype);
-  const int slab = kSpmmSlab;
+  const int slab = kSlab;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (p->profiling) {
     if (p->events_used == p->events.size()) {
@@ -135,10 +134,12 @@ int merbit_spmm_zero_boundary(merbit_plan* p, void* Y, int64_t ldy, int k, void*
   return merbit::host_exception();
 }
 
-// Buffers of the personalised PageRank: pbuf[0] holds A X at the tiles'
-// first rows (zero there between steps), pbuf[2] the second iterate; ppart
-// the per-block parts of one step (the SpMM's blocks, then the first-row
-// fix-up's, then the l1 change's).
+// Buffers of the personalised PageRank, all in the slab layout of its
+// kernels (merbit_batched.hip): pbuf[0] holds A X at the tiles' first rows
+// (zero there between steps), pbuf[1] (k > kSlab only: the caller's
+// row-major array is then converted) and pbuf[2] the iterates; ppart the
+// per-block parts of one step (the SpMM's blocks, then the first-row
+// fix-up's, then the l1 change's, then the first level of their sum).
 static int ensure_ppr_state(merbit_plan* p, int k, hipStream_t st) {
   int rc = ensure_dmask(p, st);
   if (rc != MERBIT_OK) return rc;
@@ -150,14 +151,16 @@ static int ensure_ppr_state(merbit_plan* p, int k, hipStream_t st) {
     }
     const size_t bytes = vsize(p->dtype) * (size_t)p->n_rows * (size_t)k;
     HIP_TRY(hipMalloc(&p->pbuf[0], bytes));
+    if (k > kSlab) HIP_TRY(hipMalloc(&p->pbuf[1], bytes));
     HIP_TRY(hipMalloc(&p->pbuf[2], bytes));
     p->ppr_k = k;
     p->ppr_zeroed = -1;
   }
   if (!p->ppart) {
     p->ppr_grid_n = ppr_grid(p->n_rows);
+    // the step's parts, then the first level of their sum
     const size_t rows = (size_t)spmm_blocks(p->tile_num) + (size_t)ppr_fixup_grid(p->tile_num) +
-                        (size_t)p->ppr_grid_n;
+                        (size_t)p->ppr_grid_n + (size_t)ppr_sum_scratch_rows();
     HIP_TRY(hipMalloc(&p->ppart, sizeof(double) * 2 * 64 * rows));
     HIP_TRY(hipMalloc(&p->psums[0], sizeof(double) * 2 * 64));
     HIP_TRY(hipMalloc(&p->psums[1], sizeof(double) * 2 * 64));
@@ -189,11 +192,12 @@ static int ppr_step(merbit_plan* p, const void* X, void* Xn, int k, double alpha
     ++p->events_used;
     HIP_TRY(hipEventRecord(e0, st));
   }
-  for (int c0 = 0; c0 < k; c0 += kSpmmSlab) {
-    const int kk = k - c0 < kSpmmSlab ? k - c0 : kSpmmSlab;
-    SpmmArgs a = spmm_args(p, static_cast<const char*>(X) + vs * c0, k,
-                           static_cast<char*>(p->pbuf[0]) + vs * c0, k, nullptr, 0, kk);
-    a.Xn = static_cast<char*>(Xn) + vs * c0;
+  for (int c0 = 0; c0 < k; c0 += kSlab) {
+    const int kk = k - c0 < kSlab ? k - c0 : kSlab;
+    const size_t off = vs * (size_t)c0 * (size_t)n;  // the slab's n x kk block
+    SpmmArgs a = spmm_args(p, static_cast<const char*>(X) + off, kk,
+                           static_cast<char*>(p->pbuf[0]) + off, kk, nullptr, 0, kk);
+    a.Xn = static_cast<char*>(Xn) + off;
     a.src = p->psrc + c0;
     a.sums_in = sums_in + 2 * c0;
     a.dmask = p->dmask;
@@ -213,7 +217,8 @@ static int ppr_step(merbit_plan* p, const void* X, void* Xn, int k, double alpha
                              st));
     nb += p->ppr_grid_n;
   }
-  HIP_TRY(launch_ppr_sum(p->ppart, nb, k, sums_out, st));
+  HIP_TRY(launch_ppr_sum(p->ppart, nb, k, sums_out,
+                         p->ppart + (size_t)(sb + fb + p->ppr_grid_n) * 128, st));
   p->last_stream = st;
   return MERBIT_OK;
 }
@@ -246,13 +251,25 @@ int merbit_pagerank_personalized(merbit_plan* p, double alpha, double tol, int m
   const size_t bytes = vsize(p->dtype) * (size_t)n * (size_t)k;
   HIP_TRY(hipMemcpyAsync(p->psrc, sources, sizeof(int32_t) * (size_t)k, hipMemcpyHostToDevice,
                          st));
-  HIP_TRY(launch_ppr_dangling(p->dtype, X_inout, p->dmask, n, k, p->ppart, p->psums[0],
-                              p->ppr_grid_n, st));
+  // k <= kSlab: the slab layout is the caller's, and X_inout is the first
+  // iterate buffer itself
+  const bool convert = k > kSlab;
+  void* xs[2] = {convert ? p->pbuf[1] : X_inout, p->pbuf[2]};
+  if (convert)
+    HIP_TRY(launch_ppr_to_slabs(p->dtype, X_inout, xs[0], p->dmask, n, k, p->ppart,
+                                p->psums[0], p->ppr_grid_n, st));
+  else
+    HIP_TRY(launch_ppr_dangling(p->dtype, xs[0], p->dmask, n, k, p->ppart, p->psums[0],
+                                p->ppr_grid_n, st));
   if (p->ppr_zeroed < 0) {  // A X's buffer: zero at the tiles' first rows
-    HIP_TRY(launch_spmm_zero(p->dtype, p->tile_y, (int32_t)p->tile_num, p->pbuf[0], k, k, st));
+    for (int c0 = 0; c0 < k; c0 += kSlab) {
+      const int kk = k - c0 < kSlab ? k - c0 : kSlab;
+      HIP_TRY(launch_spmm_zero(p->dtype, p->tile_y, (int32_t)p->tile_num,
+                               static_cast<char*>(p->pbuf[0]) + vsize(p->dtype) * c0 * n, kk,
+                               kk, st));
+    }
     p->ppr_zeroed = 0;
   }
-  void* xs[2] = {X_inout, p->pbuf[2]};
   double host_sums[128];
   int t = 0;
   bool converged = false;
@@ -292,7 +309,10 @@ int merbit_pagerank_personalized(merbit_plan* p, double alpha, double tol, int m
     }
   }
   p->last_stream = st;
-  if (t & 1) HIP_TRY(hipMemcpyAsync(X_inout, p->pbuf[2], bytes, hipMemcpyDeviceToDevice, st));
+  if (convert)
+    HIP_TRY(launch_ppr_from_slabs(p->dtype, xs[t & 1], X_inout, n, k, st));
+  else if (t & 1)
+    HIP_TRY(hipMemcpyAsync(X_inout, p->pbuf[2], bytes, hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (iters_out) *iters_out = t;
   return (tol > 0.0 && !converged) ? MERBIT_NOT_CONVERGED : MERBIT_OK;

@@ -336,6 +336,20 @@ hipError_t launch_spmm_zero(int dtype, const uint32_t* tile_y, int32_t tile_num,
 // column) sums the parts in a fixed order for the next step and the host.
 // Thread t of these kernels always handles column t % 64, so each
 // wavefront reads and writes whole rows (coalesced).
+//
+// The iterates (and A X) are held as slabs of kSlab columns one after
+// another: slab s is the row-major n x W_s block of columns 32 s .. 32 s +
+// W_s - 1 (W_s = min(32, k - 32 s)), so every SpMM launch reads and writes a
+// compact array (for k <= 32 this is the row-major n x k layout).  Compact
+// slabs took the 64-column SpMM of R-MAT 22 from 2.51 to 2.34 ms (FP32)
+// against the two halves of a row-major n x 64 array.
+
+// offset of element (r, j) of an n x k iterate in the slab layout
+__device__ __forceinline__ int64_t ppr_at(int64_t r, int j, int64_t n, int k) {
+  const int c0 = j & ~(kSlab - 1);
+  const int w = min(kSlab, k - c0);
+  return (int64_t)c0 * n + r * w + (j - c0);
+}
 
 constexpr int kPprThreads = 256;
 constexpr int kPprWaves = kPprThreads / 64;
@@ -385,11 +399,11 @@ __global__ __launch_bounds__(kPprThreads) void ppr_fixup_kernel(
     // each first row once (a long row is the first row of several tiles)
     if (r >= n || (t > 0 && (int64_t)(tile_y[t - 1] & kRowMask) == r)) continue;
     if (on) {
-      V* yp = Y + r * k + j;
-      V xn = a * *yp;
-      *yp = V(0);
+      const int64_t e = ppr_at(r, j, n, k);
+      V xn = a * Y[e];
+      Y[e] = V(0);
       if (r == sj) xn += tele;
-      Xn[r * k + j] = xn;
+      Xn[e] = xn;
       if ((dmask[r >> 5] >> (r & 31)) & 1u) dsum += (double)xn;
     }
   }
@@ -410,9 +424,9 @@ __global__ __launch_bounds__(kPprThreads) void ppr_resid_kernel(const V* __restr
     V xn[kPprRows], xo[kPprRows];
 #pragma unroll
     for (int u = 0; u < kPprRows; ++u) {
-      const int64_t r = min(r0 + u, n - 1);
-      xn[u] = Xn[r * k + j];
-      xo[u] = Xo[r * k + j];
+      const int64_t e = ppr_at(min(r0 + u, n - 1), j, n, k);
+      xn[u] = Xn[e];
+      xo[u] = Xo[e];
     }
 #pragma unroll
     for (int u = 0; u < kPprRows; ++u)
@@ -435,7 +449,60 @@ __global__ __launch_bounds__(kPprThreads) void ppr_dangling_kernel(
 #pragma unroll
     for (int u = 0; u < kPprRows; ++u) {
       const int64_t r = r0 + u;
-      if (r < n && ((dmask[r >> 5] >> (r & 31)) & 1u)) dsum += (double)X[r * k + j];
+      if (r < n && ((dmask[r >> 5] >> (r & 31)) & 1u)) dsum += (double)X[ppr_at(r, j, n, k)];
+    }
+  }
+  ppr_block_part(dsum, 0.0, part_out);
+}
+
+// the slab layout back into the caller's row-major n x k (ld k), one
+// wavefront per row
+template <typename V>
+__global__ __launch_bounds__(kPprThreads) void ppr_from_slabs_kernel(const V* __restrict__ src,
+                                                                     V* __restrict__ dst,
+                                                                     int64_t n, int k) {
+  const int j = threadIdx.x & 63;
+  if (j >= k) return;
+  const int64_t step = (int64_t)gridDim.x * kPprWaves;
+  for (int64_t r = (int64_t)blockIdx.x * kPprWaves + (threadIdx.x >> 6); r < n; r += step)
+    dst[r * k + j] = src[ppr_at(r, j, n, k)];
+}
+
+hipError_t launch_ppr_from_slabs(int dtype, const void* Xs, void* X, int64_t n, int k,
+                                 hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const unsigned grid = (unsigned)std::min<int64_t>((n + kPprWaves - 1) / kPprWaves, 8192);
+  if (dtype == 0)
+    hipLaunchKernelGGL(ppr_from_slabs_kernel<float>, dim3(grid), dim3(kPprThreads), 0, st,
+                       static_cast<const float*>(Xs), static_cast<float*>(X), n, k);
+  else
+    hipLaunchKernelGGL(ppr_from_slabs_kernel<double>, dim3(grid), dim3(kPprThreads), 0, st,
+                       static_cast<const double*>(Xs), static_cast<double*>(X), n, k);
+  return hipGetLastError();
+}
+
+// the caller's row-major X into the slab layout, with X's dangling mass per
+// column (the same parts as ppr_dangling_kernel, from the same pass)
+template <typename V>
+__global__ __launch_bounds__(kPprThreads) void ppr_to_slabs_kernel(
+    const V* __restrict__ src, V* __restrict__ dst, const uint32_t* __restrict__ dmask,
+    int64_t n, int k, double* __restrict__ part_out) {
+  const int j = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  double dsum = 0.0;
+  const int64_t step = (int64_t)gridDim.x * kPprWaves * kPprRows;
+  for (int64_t r0 = ((int64_t)blockIdx.x * kPprWaves + w) * kPprRows; j < k && r0 < n;
+       r0 += step) {
+    V v[kPprRows];
+#pragma unroll
+    for (int u = 0; u < kPprRows; ++u) v[u] = src[min(r0 + u, n - 1) * k + j];
+#pragma unroll
+    for (int u = 0; u < kPprRows; ++u) {
+      const int64_t r = r0 + u;
+      if (r < n) {
+        dst[ppr_at(r, j, n, k)] = v[u];
+        if ((dmask[r >> 5] >> (r & 31)) & 1u) dsum += (double)v[u];
+      }
     }
   }
   ppr_block_part(dsum, 0.0, part_out);
@@ -466,8 +533,40 @@ int ppr_grid(int64_t n) {
   return (int)g;
 }
 
-hipError_t launch_ppr_sum(const double* part, int nblocks, int k, double* sums,
+// First level for long part lists (the fused SpMM writes one part row per
+// block: 54K at R-MAT 22, sigma 5): block g adds rows g, g + G, g + 2G, ...
+// with thread t on entry t of a row (rows are read whole, coalesced), in a
+// fixed order (eight running sums, then a fixed tree), into row g of out.
+constexpr int kPartLevelRows = 1024;  // G; out holds G rows
+constexpr int kPartDirectMax = 4096;  // at most this many rows: no first level
+
+__global__ __launch_bounds__(128) void ppr_part_rows_kernel(const double* __restrict__ part,
+                                                            int nblocks,
+                                                            double* __restrict__ out) {
+  const int t = threadIdx.x;
+  const int G = gridDim.x;
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int b = blockIdx.x;
+  for (; b + 7 * G < nblocks; b += 8 * G) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s[u] += part[((int64_t)b + (int64_t)u * G) * 128 + t];
+  }
+  for (; b < nblocks; b += G) s[0] += part[(int64_t)b * 128 + t];
+  out[(int64_t)blockIdx.x * 128 + t] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
+}
+
+int ppr_sum_scratch_rows() { return kPartLevelRows; }
+
+hipError_t launch_ppr_sum(const double* part, int nblocks, int k, double* sums, double* scratch,
                           hipStream_t st) {
+  if (nblocks > kPartDirectMax && scratch != nullptr) {
+    hipLaunchKernelGGL(ppr_part_rows_kernel, dim3(kPartLevelRows), dim3(128), 0, st, part,
+                       nblocks, scratch);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    part = scratch;
+    nblocks = kPartLevelRows;
+  }
   hipLaunchKernelGGL(ppr_sum_parts_kernel, dim3(k), dim3(kReduceThreads), 0, st, part, nblocks,
                      sums);
   return hipGetLastError();
@@ -483,7 +582,22 @@ hipError_t launch_ppr_dangling(int dtype, const void* X, const uint32_t* dmask, 
                        static_cast<const double*>(X), dmask, n, k, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_ppr_sum(part, grid, k, sums, st);
+  return launch_ppr_sum(part, grid, k, sums, nullptr, st);
+}
+
+hipError_t launch_ppr_to_slabs(int dtype, const void* X, void* Xs, const uint32_t* dmask,
+                               int64_t n, int k, double* part, double* sums, int grid,
+                               hipStream_t st) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(ppr_to_slabs_kernel<float>, dim3(grid), dim3(kPprThreads), 0, st,
+                       static_cast<const float*>(X), static_cast<float*>(Xs), dmask, n, k, part);
+  else
+    hipLaunchKernelGGL(ppr_to_slabs_kernel<double>, dim3(grid), dim3(kPprThreads), 0, st,
+                       static_cast<const double*>(X), static_cast<double*>(Xs), dmask, n, k,
+                       part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_ppr_sum(part, grid, k, sums, nullptr, st);
 }
 
 hipError_t launch_ppr_fixup(int dtype, const uint32_t* tile_y, int32_t tile_num, void* Y,

@@ -10,6 +10,7 @@
 namespace merbit {
 
 constexpr int kOmega = 64;                 // lanes per tile = CDNA wavefront size
+constexpr int kSlab = 32;                  // right-hand-side columns per SpMM launch
 constexpr uint32_t kRowMask = 0x7FFFFFFFu; // tile_y: row index
 constexpr uint32_t kFastBit = 0x80000000u; // tile_y: long-row (single-row) tile mark
 constexpr int kMaxSigma = 12;              // 2 ceil(log2(64 sigma)) + sigma <= 32
@@ -487,6 +488,19 @@ hipError_t launch_ppr_fixup(int dtype, const uint32_t* tile_y, int32_t tile_num,
 hipError_t launch_ppr_resid(int dtype, const void* Xn, const void* Xo, int64_t n, int k,
                             double* part, int grid, hipStream_t st);
 // sums[2j], sums[2j + 1] = column j's totals over nblocks part rows, j < k
-hipError_t launch_ppr_sum(const double* part, int nblocks, int k, double* sums, hipStream_t st);
+// per-column totals of per-block part rows (64 columns x 2 doubles each);
+// scratch (ppr_sum_scratch_rows() rows) lets a long list be summed in two
+// levels, in a fixed order either way
+hipError_t launch_ppr_sum(const double* part, int nblocks, int k, double* sums, double* scratch,
+                          hipStream_t st);
+int ppr_sum_scratch_rows();
+// personalised PageRank iterate: the caller's row-major n x k into 32-column
+// slabs (with its per-column dangling mass into sums, like
+// launch_ppr_dangling), and back
+hipError_t launch_ppr_to_slabs(int dtype, const void* X, void* Xs, const uint32_t* dmask,
+                               int64_t n, int k, double* part, double* sums, int grid,
+                               hipStream_t st);
+hipError_t launch_ppr_from_slabs(int dtype, const void* Xs, void* X, int64_t n, int k,
+                                 hipStream_t st);
 
 }  // namespace merbit

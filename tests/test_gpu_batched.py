@@ -198,7 +198,7 @@ def _ppr_check(X_gpu, ref, dtype, label):
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
-@pytest.mark.parametrize("k", [1, 17, 64])
+@pytest.mark.parametrize("k", [1, 17, 40, 64])
 def test_personalized_pagerank_chung_lu(k, dtype):
     """k sources on the Chung-Lu 10K graph, 20 iterations from x_0 = e_s:
     every column against the oracle entry by entry, and mass 1 per column."""
@@ -220,16 +220,18 @@ def test_personalized_pagerank_chung_lu(k, dtype):
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
-def test_personalized_pagerank_convergence_and_reuse(dtype):
+@pytest.mark.parametrize("k", [8, 45])
+def test_personalized_pagerank_convergence_and_reuse(k, dtype):
     """tol stops the iteration; a second call on the same plan (buffers kept)
-    continues from the returned vectors and agrees with one long run."""
+    continues from the returned vectors and agrees with one long run (k = 45:
+    the iterates are converted to and from two column slabs on every call)."""
     import paper_2605_07391_amd as pkg
     dev = require_gpu()
     w = workload("chung_lu_10k")
     rp, col, vals, n = w["row_ptr"], w["col"], w["values"], w["n_rows"]
     r, c, v = to_device(rp, col, vals, dtype, dev)
     plan = pkg.Plan(r, c, v, n)
-    src = graphgen.ppr_sources(n, 8, seed=5)
+    src = graphgen.ppr_sources(n, k, seed=5)
     tol = 1e-5 if dtype == torch.float32 else 1e-10
     X, iters, resid, conv = plan.pagerank_personalized(src, tol=tol, max_iter=500,
                                                        check_every=5)
