@@ -209,11 +209,15 @@ __global__ __launch_bounds__(kReduceThreads) void adj_sum_kernel(const V* __rest
 
 // lam_new = g + alpha y + (alpha / n) S d, S = sum of lam_old (first
 // components of part_in); writes this block's (sum lam_new, l1 change).
+// With hot_n > 0 it also writes the hot-column copy of lam_new that the next
+// SpMV's LDS cache reads (x_hot[s] = lam_new[hot_cols[s]], the same
+// operations on the same operands), so that SpMV needs no gather launch.
 template <typename V>
 __global__ __launch_bounds__(kReduceThreads) void adj_update_kernel(
     const V* __restrict__ y, const V* __restrict__ lam_old, V* __restrict__ lam_new,
     const V* __restrict__ g, const uint32_t* __restrict__ dmask, int64_t n, double alpha,
-    const double* __restrict__ part_in, int n_in, double* __restrict__ part_out) {
+    const double* __restrict__ part_in, int n_in, double* __restrict__ part_out,
+    const int32_t* __restrict__ hot_cols, int32_t hot_n, V* __restrict__ x_hot) {
   __shared__ double total;
   {
     double a = 0.0, z = 0.0;
@@ -227,11 +231,17 @@ __global__ __launch_bounds__(kReduceThreads) void adj_update_kernel(
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   double ssum = 0.0, rsum = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    V v = g[i] + al * y[i];
+    V v = fma(al, y[i], g[i]);
     if ((dmask[i >> 5] >> (i & 31)) & 1u) v += dang;
     lam_new[i] = v;
     ssum += (double)v;
     rsum += fabs((double)v - (double)lam_old[i]);
+  }
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < hot_n; h += stride) {
+    const int64_t c = hot_cols[h];
+    V v = fma(al, y[c], g[c]);
+    if ((dmask[c >> 5] >> (c & 31)) & 1u) v += dang;
+    x_hot[h] = v;
   }
   block_sum2(ssum, rsum);
   if (threadIdx.x == 0) {
@@ -254,17 +264,20 @@ hipError_t launch_adj_sum(int dtype, const void* v, int64_t n, double* part_out,
 hipError_t launch_adj_update(int dtype, const void* y, const void* lam_old, void* lam_new,
                              const void* g, const uint32_t* dmask, int64_t n, double alpha,
                              const double* part_in, int n_in, double* part_out, int grid,
-                             hipStream_t st) {
+                             hipStream_t st, const int32_t* hot_cols, int32_t hot_n,
+                             void* x_hot) {
   if (dtype == 0)
     hipLaunchKernelGGL(adj_update_kernel<float>, dim3(grid), dim3(kReduceThreads), 0, st,
                        static_cast<const float*>(y), static_cast<const float*>(lam_old),
                        static_cast<float*>(lam_new), static_cast<const float*>(g), dmask, n,
-                       alpha, part_in, n_in, part_out);
+                       alpha, part_in, n_in, part_out, hot_cols, hot_n,
+                       static_cast<float*>(x_hot));
   else
     hipLaunchKernelGGL(adj_update_kernel<double>, dim3(grid), dim3(kReduceThreads), 0, st,
                        static_cast<const double*>(y), static_cast<const double*>(lam_old),
                        static_cast<double*>(lam_new), static_cast<const double*>(g), dmask, n,
-                       alpha, part_in, n_in, part_out);
+                       alpha, part_in, n_in, part_out, hot_cols, hot_n,
+                       static_cast<double*>(x_hot));
   return hipGetLastError();
 }
 

@@ -56,7 +56,7 @@ void plan_free_all(merbit_plan* p) {
                   p->colx, p->x_hot, p->pbuf[0], p->pbuf[1], p->pbuf[2], p->ppart, p->psums[0],
                   p->psums[1], p->psrc, p->multi_chunk_row, p->multi_chunk_graph,
                   p->multi_chunk_ptr, p->multi_gsize, p->multi_part, p->multi_gsum[0],
-                  p->multi_gsum[1], p->bvec[0], p->bvec[1], p->bvec[2], p->bvec[3], p->bvec[4],
+                  p->multi_gsum[1], p->multi_hot_graph, p->bvec[0], p->bvec[1], p->bvec[2], p->bvec[3], p->bvec[4],
                   p->bvec[5], p->bvec[6], p->bpart[0], p->bpart[1], p->bpart[2], p->bpart[3],
                   p->bpart[4], p->bpart[5], p->bpart[6], p->sperm, p->scol, p->svals, p->swords,
                   p->yv[0], p->yv[1], p->range_tile, p->hot_off, p->queue};

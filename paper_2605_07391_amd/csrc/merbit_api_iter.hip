@@ -3,6 +3,7 @@
 // (Sec. 5.5.2), each looping over the plan's fused SpMV with iteration chunks
 // recorded into HIP graphs.
 #include <math.h>
+#include <algorithm>
 #include <string.h>
 
 #include "merbit_host.hpp"
@@ -137,14 +138,28 @@ static int ensure_multi_tables(merbit_plan* p, const int64_t* graph_ptr, int n_g
     gsize[g] = (double)(gp[g + 1] - gp[g]);
   }
   chunk_row.push_back((int32_t)gp[n_graphs]);
+  // the graph of each hot column slot, for the update's copy of the hot
+  // values (a partial cache only)
+  std::vector<int32_t> hot_graph;
+  if (p->hot_n > 0 && !p->hot_all) {
+    hot_graph.resize((size_t)p->hot_n);
+    HIP_TRY(hipMemcpy(hot_graph.data(), p->hot_cols, sizeof(int32_t) * (size_t)p->hot_n,
+                      hipMemcpyDeviceToHost));
+    for (int32_t& h : hot_graph) {
+      const int64_t c = h;
+      if (c < 0 || c >= gp[n_graphs]) return fail(MERBIT_EINVAL, "hot column out of range");
+      h = (int32_t)(std::upper_bound(gp.begin(), gp.end(), c) - gp.begin() - 1);
+    }
+  }
   void* old[] = {p->multi_chunk_row, p->multi_chunk_graph, p->multi_chunk_ptr, p->multi_gsize,
-                 p->multi_part, p->multi_gsum[0], p->multi_gsum[1]};
+                 p->multi_part, p->multi_gsum[0], p->multi_gsum[1], p->multi_hot_graph};
   HIP_TRY(hipStreamSynchronize(st));  // earlier calls may still read the old tables
   invalidate_graphs(p);
   for (void* b : old)
     if (b) (void)hipFree(b);
   p->multi_chunk_row = p->multi_chunk_graph = p->multi_chunk_ptr = nullptr;
   p->multi_gsize = p->multi_part = p->multi_gsum[0] = p->multi_gsum[1] = nullptr;
+  p->multi_hot_graph = nullptr;
   p->multi_gp.clear();
   const size_t C = chunk_graph.size();
   HIP_TRY(hipMalloc(&p->multi_chunk_row, sizeof(int32_t) * (C + 1)));
@@ -162,6 +177,11 @@ static int ensure_multi_tables(merbit_plan* p, const int64_t* graph_ptr, int n_g
                     hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(p->multi_gsize, gsize.data(), sizeof(double) * n_graphs,
                     hipMemcpyHostToDevice));
+  if (!hot_graph.empty()) {
+    HIP_TRY(hipMalloc(&p->multi_hot_graph, sizeof(int32_t) * hot_graph.size()));
+    HIP_TRY(hipMemcpy(p->multi_hot_graph, hot_graph.data(), sizeof(int32_t) * hot_graph.size(),
+                      hipMemcpyHostToDevice));
+  }
   p->multi_chunks = (int32_t)C;
   p->multi_gp = gp;
   return MERBIT_OK;
@@ -197,6 +217,7 @@ int merbit_pagerank_multi(merbit_plan* p, const int64_t* graph_ptr, int n_graphs
   mt.chunk_ptr = p->multi_chunk_ptr;
   mt.gsize = p->multi_gsize;
   mt.part = p->multi_part;
+  mt.hot_graph = p->multi_hot_graph;
   mt.n_chunks = p->multi_chunks;
   mt.n_graphs = n_graphs;
   const size_t vb = vsize(p->dtype) * (size_t)p->n_rows;
@@ -216,18 +237,27 @@ int merbit_pagerank_multi(merbit_plan* p, const int64_t* graph_ptr, int n_graphs
     int len = check_every - t % check_every;
     if (len > max_iter - t) len = max_iter - t;
     const int t0 = t, yb0 = yb;
+    // with a partial hot-column cache the update also writes the next
+    // iterate's hot values, so only the call's first SpMV gathers them
+    const bool fuse_hot = p->hot_n > 0 && !p->hot_all;
     auto enqueue = [&](hipStream_t s) -> int {
       for (int i = 0; i < len; ++i) {
         const int cur = (t0 + i) & 1, b = yb0 ^ (i & 1);
-        const int r = run_fused(p, xs[cur], p->ybuf[b], p->ybuf[b ^ 1], s);
+        const int r = run_fused(p, xs[cur], p->ybuf[b], p->ybuf[b ^ 1], s,
+                                fuse_hot && t0 + i > 0);
         if (r != MERBIT_OK) return r;
         HIP_TRY(launch_multi_update(p->dtype, p->ybuf[b], xs[cur], xs[cur ^ 1], p->dmask, mt,
-                                    alpha, p->multi_gsum[cur], p->multi_gsum[cur ^ 1], s));
+                                    alpha, p->multi_gsum[cur], p->multi_gsum[cur ^ 1], s,
+                                    fuse_hot ? p->hot_cols : nullptr, fuse_hot ? p->hot_n : 0,
+                                    fuse_hot ? p->x_hot : nullptr));
       }
       return MERBIT_OK;
     };
+    // the call's first chunk gathers the hot values, later ones do not: a
+    // different graph (the key's count is negated for the first chunk)
     rc = len == check_every
-             ? run_chunk(p, kLoopMulti, t0 & 1, yb0, len, n_graphs, x_inout, alpha, enqueue, st)
+             ? run_chunk(p, kLoopMulti, t0 & 1, yb0, len, t0 == 0 ? -n_graphs : n_graphs,
+                         x_inout, alpha, enqueue, st)
              : enqueue(st);
     if (rc != MERBIT_OK) return rc;
     t += len;
@@ -297,19 +327,26 @@ int merbit_pagerank_adjoint(merbit_plan* p, merbit_plan* pt, double alpha, doubl
     int len = check_every - t % check_every;
     if (len > max_iter - t) len = max_iter - t;
     const int t0 = t, yb0 = yb;
+    // as in PageRank: the update writes the next SpMV's hot values
+    const bool fuse_hot = pt->hot_n > 0 && !pt->hot_all;
     auto enqueue = [&](hipStream_t s) -> int {
       for (int i = 0; i < len; ++i) {
         const int cur = (t0 + i) & 1, b = yb0 ^ (i & 1);
-        const int r = run_fused(pt, ls[cur], pt->ybuf[b], pt->ybuf[b ^ 1], s);
+        const int r = run_fused(pt, ls[cur], pt->ybuf[b], pt->ybuf[b ^ 1], s,
+                                fuse_hot && t0 + i > 0);
         if (r != MERBIT_OK) return r;
         HIP_TRY(launch_adj_update(p->dtype, pt->ybuf[b], ls[cur], ls[cur ^ 1], g, p->dmask, n,
                                   alpha, pt->partials[cur], pt->reduce_grid,
-                                  pt->partials[cur ^ 1], pt->reduce_grid, s));
+                                  pt->partials[cur ^ 1], pt->reduce_grid, s,
+                                  fuse_hot ? pt->hot_cols : nullptr, fuse_hot ? pt->hot_n : 0,
+                                  fuse_hot ? pt->x_hot : nullptr));
       }
       return MERBIT_OK;
     };
-    rc = len == check_every ? run_chunk(pt, kLoopAdjoint, t0 & 1, yb0, len, 0, lam_inout, alpha,
-                                        enqueue, st, g)
+    // the call's first chunk gathers the hot values, later ones do not: a
+    // different graph (key k = 1 for the first chunk)
+    rc = len == check_every ? run_chunk(pt, kLoopAdjoint, t0 & 1, yb0, len, t0 == 0 ? 1 : 0,
+                                        lam_inout, alpha, enqueue, st, g)
                             : enqueue(st);
     if (rc != MERBIT_OK) return rc;
     t += len;

@@ -644,12 +644,17 @@ constexpr int kMultiRows = kReduceThreads * kMultiILP;
 
 int multi_chunk_rows() { return kMultiRows; }
 
+// With hot_n > 0 the kernel also writes the hot-column copy of x' that the
+// next SpMV's LDS cache reads: slot s holds column hot_cols[s] of graph
+// hot_graph[s], computed with the same operations as that row's x'.
 template <typename V>
 __global__ __launch_bounds__(kReduceThreads) void multi_update_kernel(
     const V* __restrict__ y, const V* __restrict__ x_old, V* __restrict__ x_new,
     const uint32_t* __restrict__ dmask, const int32_t* __restrict__ chunk_row,
     const int32_t* __restrict__ chunk_graph, const double* __restrict__ gsum_in,
-    const double* __restrict__ gsize, double alpha, double* __restrict__ part_out) {
+    const double* __restrict__ gsize, double alpha, double* __restrict__ part_out,
+    const int32_t* __restrict__ hot_cols, const int32_t* __restrict__ hot_graph, int32_t hot_n,
+    V* __restrict__ x_hot) {
   const int c = blockIdx.x;
   const int64_t r0 = chunk_row[c], r1 = chunk_row[c + 1];
   const int g = chunk_graph[c];
@@ -669,11 +674,17 @@ __global__ __launch_bounds__(kReduceThreads) void multi_update_kernel(
   for (int u = 0; u < kMultiILP; ++u) {
     const int64_t i = r0 + threadIdx.x + (int64_t)u * kReduceThreads;
     if (i < r1) {
-      const V xn = a * yv[u] + tele;
+      const V xn = fma(a, yv[u], tele);
       x_new[i] = xn;
       rsum += fabs((double)xn - (double)xo[u]);
       if ((mw[u] >> (i & 31)) & 1u) dsum += (double)xn;
     }
+  }
+  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < hot_n;
+       h += (int64_t)gridDim.x * blockDim.x) {
+    const int gh = hot_graph[h];
+    const V th = (V)((alpha * gsum_in[2 * gh] + 1.0 - alpha) / gsize[gh]);
+    x_hot[h] = fma(a, y[hot_cols[h]], th);
   }
   block_sum2(dsum, rsum);
   if (threadIdx.x == 0) {
@@ -744,17 +755,21 @@ hipError_t launch_multi_dangling(int dtype, const void* x, const uint32_t* dmask
 
 hipError_t launch_multi_update(int dtype, const void* y, const void* x_old, void* x_new,
                                const uint32_t* dmask, const MultiTables& mt, double alpha,
-                               const double* gsum_in, double* gsum_out, hipStream_t st) {
+                               const double* gsum_in, double* gsum_out, hipStream_t st,
+                               const int32_t* hot_cols, int32_t hot_n, void* x_hot) {
+  if (hot_n > 0 && mt.hot_graph == nullptr) return hipErrorInvalidValue;
   if (dtype == 0)
     hipLaunchKernelGGL(multi_update_kernel<float>, dim3((unsigned)mt.n_chunks),
                        dim3(kReduceThreads), 0, st, static_cast<const float*>(y),
                        static_cast<const float*>(x_old), static_cast<float*>(x_new), dmask,
-                       mt.chunk_row, mt.chunk_graph, gsum_in, mt.gsize, alpha, mt.part);
+                       mt.chunk_row, mt.chunk_graph, gsum_in, mt.gsize, alpha, mt.part,
+                       hot_cols, mt.hot_graph, hot_n, static_cast<float*>(x_hot));
   else
     hipLaunchKernelGGL(multi_update_kernel<double>, dim3((unsigned)mt.n_chunks),
                        dim3(kReduceThreads), 0, st, static_cast<const double*>(y),
                        static_cast<const double*>(x_old), static_cast<double*>(x_new), dmask,
-                       mt.chunk_row, mt.chunk_graph, gsum_in, mt.gsize, alpha, mt.part);
+                       mt.chunk_row, mt.chunk_graph, gsum_in, mt.gsize, alpha, mt.part,
+                       hot_cols, mt.hot_graph, hot_n, static_cast<double*>(x_hot));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_multi_sum(mt.part, mt.chunk_ptr, mt.n_graphs, gsum_out, st);

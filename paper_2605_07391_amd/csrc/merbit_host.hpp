@@ -86,6 +86,7 @@ struct merbit_plan {
   double* multi_gsize = nullptr;
   double* multi_part = nullptr;
   double* multi_gsum[2] = {nullptr, nullptr};
+  int32_t* multi_hot_graph = nullptr;  // graph of each hot column slot
   int32_t multi_chunks = 0;
   // BiCGSTAB state: r, r^, p, v (two), s, t; pair arrays of the dot products
   void* bvec[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};

@@ -380,10 +380,12 @@ hipError_t launch_column_scale(int dtype, const int32_t* col, const void* a, con
                                const void* s, void* out, int64_t m, hipStream_t st);
 hipError_t launch_adj_sum(int dtype, const void* v, int64_t n, double* part_out, int grid,
                           hipStream_t st);
+// hot_n > 0: also the next SpMV's hot-column copy of lam_new into x_hot
 hipError_t launch_adj_update(int dtype, const void* y, const void* lam_old, void* lam_new,
                              const void* g, const uint32_t* dmask, int64_t n, double alpha,
                              const double* part_in, int n_in, double* part_out, int grid,
-                             hipStream_t st);
+                             hipStream_t st, const int32_t* hot_cols = nullptr,
+                             int32_t hot_n = 0, void* x_hot = nullptr);
 
 // BiCGSTAB.
 enum { kBicgInit = 0, kBicgUpdateP, kBicgDot1, kBicgUpdateS, kBicgDot2, kBicgUpdateXR };
@@ -458,15 +460,19 @@ struct MultiTables {  // device row-chunk tables of a block-diagonal matrix
   const int32_t* chunk_ptr;    // [n_graphs + 1]
   const double* gsize;         // [n_graphs] vertex count of each graph
   double* part;                // [2 n_chunks] per-chunk pairs
+  const int32_t* hot_graph;    // [hot_n] graph of each hot column slot (or null)
   int32_t n_chunks;
   int32_t n_graphs;
 };
 int multi_chunk_rows();
 hipError_t launch_multi_dangling(int dtype, const void* x, const uint32_t* dmask,
                                  const MultiTables& mt, double* gsum_out, hipStream_t st);
+// hot_n > 0 (needs mt.hot_graph): also the next SpMV's hot-column copy of x'
 hipError_t launch_multi_update(int dtype, const void* y, const void* x_old, void* x_new,
                                const uint32_t* dmask, const MultiTables& mt, double alpha,
-                               const double* gsum_in, double* gsum_out, hipStream_t st);
+                               const double* gsum_in, double* gsum_out, hipStream_t st,
+                               const int32_t* hot_cols = nullptr, int32_t hot_n = 0,
+                               void* x_hot = nullptr);
 hipError_t launch_spmm(int dtype, int sigma, const SpmmArgs& a, hipStream_t st);
 hipError_t launch_spmm_zero(int dtype, const uint32_t* tile_y, int32_t tile_num, void* Y,
                             int64_t ld, int k, hipStream_t st);

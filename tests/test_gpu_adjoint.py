@@ -130,6 +130,40 @@ def test_adjoint_fixed_point_chung_lu(dtype, stripes):
     op.close()
 
 
+@pytest.mark.parametrize("stripes", [0, 8], ids=["plain", "striped8"])
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+def test_adjoint_partial_hot_cache(dtype, stripes):
+    """P^T's plan with a partial hot-column cache: the adjoint update writes
+    the next SpMV's hot values, and only each call's first chunk gathers them
+    (a graph of its own).  Chunks of 4 iterations are recorded and replayed
+    over repeated calls, each result against the oracle."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    w = workload("chung_lu_10k")
+    rp, col, vals, n = w["row_ptr"], w["col"], w["values"], w["n_rows"]
+    op = _diff_setup(w, dtype, dev)
+    vh = host_values(vals, dtype)
+    P = torch.from_numpy(vh).to(dtype).to(dev)
+    pkg.gather_values(op.perm, P, out=op.values_t)
+    pt = pkg.Plan(op.row_t, op.col_t, op.values_t, n, commit="wave", hot_columns=100,
+                  stripes=stripes)
+    info = pt.info()
+    assert 0 < info["hot_columns"] < n and info["hot_coverage"] < 1.0
+    g64 = graphgen.uniform(8, 83, n, -1.0, 1.0).astype(_np(dtype)).astype(np.float64)
+    g = torch.from_numpy(g64).to(dtype).to(dev)
+    for iters in (12, 9, 12, 12):
+        lam = g.clone()
+        it, _, _ = op.plan.pagerank_adjoint(pt, g, lam, ALPHA, 0.0, iters, 4)
+        y = pt.spmv(g)  # eager work on the same plan (its own hot gather) between calls
+        torch.cuda.synchronize()
+        assert it == iters and torch.isfinite(y).all()
+        ref = oracle.pagerank_adjoint(rp, col, vh, ALPHA, iters, g64)
+        err = np.abs(lam.double().cpu().numpy() - ref).max() / np.abs(ref).max()
+        assert err <= ADJ_TOL[dtype], f"{iters} iterations: {err:.3e}"
+    pt.close()
+    op.close()
+
+
 def _tiny_graph(n, seed):
     rng = np.random.default_rng(seed)
     edges = {(int(rng.integers(n)), int(rng.integers(n))) for _ in range(3 * n)}

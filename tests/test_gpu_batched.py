@@ -351,6 +351,37 @@ def test_pagerank_multi_convergence_and_errors():
     plan.close()
 
 
+@pytest.mark.parametrize("stripes", [0, 8], ids=["plain", "striped8"])
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+def test_pagerank_multi_partial_hot_cache(dtype, stripes):
+    """A partial hot-column cache on the many-graph plan: the update writes
+    the next SpMV's hot values (each with its own graph's teleport), and only
+    each call's first chunk gathers them (a graph of its own).  Chunks of 4
+    iterations are recorded and replayed over repeated calls, each result
+    against the per-graph oracle."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    rp, col, gp = _small_multi(5, 24)
+    n = int(gp[-1])
+    vals = graphgen.column_stochastic_values(col, n)
+    r, c, v = to_device(rp, col, vals, dtype, dev)
+    plan = pkg.Plan(r, c, v, n, commit="wave", hot_columns=300, stripes=stripes)
+    info = plan.info()
+    assert 0 < info["hot_columns"] < n and info["hot_coverage"] < 1.0
+    x064 = _multi_x0(gp, dtype)
+    vh = host_values(vals, dtype)
+    for iters in (12, 10, 12, 12):
+        x = torch.from_numpy(x064).to(dtype).to(dev)
+        got_iters, _, _ = plan.pagerank_multi(gp, x, alpha=ALPHA, max_iter=iters, check_every=4)
+        y = plan.spmv(x)  # eager work on the same plan (its own hot gather) between calls
+        torch.cuda.synchronize()
+        assert got_iters == iters and torch.isfinite(y).all()
+        ref = oracle.pagerank_multi(rp, col, vh, gp, ALPHA, iters, x064)
+        rel = np.abs(x.double().cpu().numpy() - ref) / ref
+        assert rel.max() <= PR_TOL[dtype], f"{iters} iterations: {rel.max():.3e}"
+    plan.close()
+
+
 def test_pagerank_multi_256_graphs_full_size():
     """The 256-graph workload (log-uniform sizes 1,000 .. 200,000, degree 8),
     FP32, 10 iterations: every vertex against the per-graph oracle."""
