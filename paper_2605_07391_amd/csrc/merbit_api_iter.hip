@@ -46,10 +46,13 @@ int pagerank_loop(merbit_plan* p, PageRankWork& w, double alpha, double tol, int
         const int r = run_fused(p, xs[cur], w.ybuf[b], w.ybuf[b ^ 1], s,
                                 fuse_hot && t0 + i > 0, w.timed);
         if (r != MERBIT_OK) return r;
+        // the l1 change only on the chunk's last step (the host reads it
+        // after the chunk)
         HIP_TRY(launch_pr_update(p->dtype, w.ybuf[b], xs[cur], xs[cur ^ 1], w.dmask, n, alpha,
                                  w.partials[cur], w.reduce_grid, w.partials[cur ^ 1],
                                  w.reduce_grid, s, fuse_hot ? p->hot_cols : nullptr,
-                                 fuse_hot ? p->hot_n : 0, fuse_hot ? p->x_hot : nullptr));
+                                 fuse_hot ? p->hot_n : 0, fuse_hot ? p->x_hot : nullptr,
+                                 i == len - 1));
       }
       return MERBIT_OK;
     };
@@ -249,7 +252,7 @@ int merbit_pagerank_multi(merbit_plan* p, const int64_t* graph_ptr, int n_graphs
         HIP_TRY(launch_multi_update(p->dtype, p->ybuf[b], xs[cur], xs[cur ^ 1], p->dmask, mt,
                                     alpha, p->multi_gsum[cur], p->multi_gsum[cur ^ 1], s,
                                     fuse_hot ? p->hot_cols : nullptr, fuse_hot ? p->hot_n : 0,
-                                    fuse_hot ? p->x_hot : nullptr));
+                                    fuse_hot ? p->x_hot : nullptr, i == len - 1));
       }
       return MERBIT_OK;
     };

@@ -647,7 +647,9 @@ int multi_chunk_rows() { return kMultiRows; }
 // With hot_n > 0 the kernel also writes the hot-column copy of x' that the
 // next SpMV's LDS cache reads: slot s holds column hot_cols[s] of graph
 // hot_graph[s], computed with the same operations as that row's x'.
-template <typename V>
+// Without RESID x_old is not read and the l1 parts are 0 (the host reads
+// the l1 change only after a chunk's last step).
+template <typename V, bool RESID>
 __global__ __launch_bounds__(kReduceThreads) void multi_update_kernel(
     const V* __restrict__ y, const V* __restrict__ x_old, V* __restrict__ x_new,
     const uint32_t* __restrict__ dmask, const int32_t* __restrict__ chunk_row,
@@ -666,7 +668,7 @@ __global__ __launch_bounds__(kReduceThreads) void multi_update_kernel(
   for (int u = 0; u < kMultiILP; ++u) {
     const int64_t i = min(r0 + threadIdx.x + (int64_t)u * kReduceThreads, r1 - 1);
     yv[u] = y[i];
-    xo[u] = x_old[i];
+    if constexpr (RESID) xo[u] = x_old[i];
     mw[u] = dmask[i >> 5];
   }
   double dsum = 0.0, rsum = 0.0;
@@ -676,7 +678,7 @@ __global__ __launch_bounds__(kReduceThreads) void multi_update_kernel(
     if (i < r1) {
       const V xn = fma(a, yv[u], tele);
       x_new[i] = xn;
-      rsum += fabs((double)xn - (double)xo[u]);
+      if constexpr (RESID) rsum += fabs((double)xn - (double)xo[u]);
       if ((mw[u] >> (i & 31)) & 1u) dsum += (double)xn;
     }
   }
@@ -753,23 +755,38 @@ hipError_t launch_multi_dangling(int dtype, const void* x, const uint32_t* dmask
   return launch_multi_sum(mt.part, mt.chunk_ptr, mt.n_graphs, gsum_out, st);
 }
 
+template <typename V>
+static void multi_update_launch(bool resid, const void* y, const void* x_old, void* x_new,
+                                const uint32_t* dmask, const MultiTables& mt, double alpha,
+                                const double* gsum_in, hipStream_t st, const int32_t* hot_cols,
+                                int32_t hot_n, void* x_hot) {
+  const V* yv = static_cast<const V*>(y);
+  const V* xo = static_cast<const V*>(x_old);
+  V* xn = static_cast<V*>(x_new);
+  V* xh = static_cast<V*>(x_hot);
+  if (resid)
+    hipLaunchKernelGGL((multi_update_kernel<V, true>), dim3((unsigned)mt.n_chunks),
+                       dim3(kReduceThreads), 0, st, yv, xo, xn, dmask, mt.chunk_row,
+                       mt.chunk_graph, gsum_in, mt.gsize, alpha, mt.part, hot_cols,
+                       mt.hot_graph, hot_n, xh);
+  else
+    hipLaunchKernelGGL((multi_update_kernel<V, false>), dim3((unsigned)mt.n_chunks),
+                       dim3(kReduceThreads), 0, st, yv, xo, xn, dmask, mt.chunk_row,
+                       mt.chunk_graph, gsum_in, mt.gsize, alpha, mt.part, hot_cols,
+                       mt.hot_graph, hot_n, xh);
+}
+
 hipError_t launch_multi_update(int dtype, const void* y, const void* x_old, void* x_new,
                                const uint32_t* dmask, const MultiTables& mt, double alpha,
                                const double* gsum_in, double* gsum_out, hipStream_t st,
-                               const int32_t* hot_cols, int32_t hot_n, void* x_hot) {
+                               const int32_t* hot_cols, int32_t hot_n, void* x_hot, bool resid) {
   if (hot_n > 0 && mt.hot_graph == nullptr) return hipErrorInvalidValue;
   if (dtype == 0)
-    hipLaunchKernelGGL(multi_update_kernel<float>, dim3((unsigned)mt.n_chunks),
-                       dim3(kReduceThreads), 0, st, static_cast<const float*>(y),
-                       static_cast<const float*>(x_old), static_cast<float*>(x_new), dmask,
-                       mt.chunk_row, mt.chunk_graph, gsum_in, mt.gsize, alpha, mt.part,
-                       hot_cols, mt.hot_graph, hot_n, static_cast<float*>(x_hot));
+    multi_update_launch<float>(resid, y, x_old, x_new, dmask, mt, alpha, gsum_in, st, hot_cols,
+                               hot_n, x_hot);
   else
-    hipLaunchKernelGGL(multi_update_kernel<double>, dim3((unsigned)mt.n_chunks),
-                       dim3(kReduceThreads), 0, st, static_cast<const double*>(y),
-                       static_cast<const double*>(x_old), static_cast<double*>(x_new), dmask,
-                       mt.chunk_row, mt.chunk_graph, gsum_in, mt.gsize, alpha, mt.part,
-                       hot_cols, mt.hot_graph, hot_n, static_cast<double*>(x_hot));
+    multi_update_launch<double>(resid, y, x_old, x_new, dmask, mt, alpha, gsum_in, st, hot_cols,
+                                hot_n, x_hot);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_multi_sum(mt.part, mt.chunk_ptr, mt.n_graphs, gsum_out, st);

@@ -345,11 +345,12 @@ hipError_t launch_dangling_mask(const int32_t* col, int64_t nnz, int64_t n,
                                 unsigned char* scratch_bytes, uint32_t* dmask, hipStream_t st);
 hipError_t launch_dangling_sum(int dtype, const void* x, const uint32_t* dmask, int64_t n,
                                double* partials_out, int grid, hipStream_t st);
+// resid: also the l1 change (second components of partials_out; else 0)
 hipError_t launch_pr_update(int dtype, const void* y, const void* x_old, void* x_new,
                             const uint32_t* dmask, int64_t n, double alpha,
                             const double* partials_in, int n_in, double* partials_out, int grid,
                             hipStream_t st, const int32_t* hot_cols = nullptr,
-                            int32_t hot_n = 0, void* x_hot = nullptr);
+                            int32_t hot_n = 0, void* x_hot = nullptr, bool resid = true);
 int pr_reduce_grid(int64_t n);
 
 // Adjoint pieces.
@@ -468,11 +469,12 @@ int multi_chunk_rows();
 hipError_t launch_multi_dangling(int dtype, const void* x, const uint32_t* dmask,
                                  const MultiTables& mt, double* gsum_out, hipStream_t st);
 // hot_n > 0 (needs mt.hot_graph): also the next SpMV's hot-column copy of x'
+// resid: also the per-graph l1 change (second components of gsum_out; else 0)
 hipError_t launch_multi_update(int dtype, const void* y, const void* x_old, void* x_new,
                                const uint32_t* dmask, const MultiTables& mt, double alpha,
                                const double* gsum_in, double* gsum_out, hipStream_t st,
                                const int32_t* hot_cols = nullptr, int32_t hot_n = 0,
-                               void* x_hot = nullptr);
+                               void* x_hot = nullptr, bool resid = true);
 hipError_t launch_spmm(int dtype, int sigma, const SpmmArgs& a, hipStream_t st);
 hipError_t launch_spmm_zero(int dtype, const uint32_t* tile_y, int32_t tile_num, void* Y,
                             int64_t ld, int k, hipStream_t st);

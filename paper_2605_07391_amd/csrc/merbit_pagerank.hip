@@ -132,11 +132,13 @@ hipError_t launch_dangling_sum(int dtype, const void* x, const uint32_t* dmask, 
 
 // x_new = alpha y + (alpha delta + 1 - alpha) / n, with delta the dangling
 // mass of x_old (summed from the previous kernel's partials).  Writes this
-// block's dangling mass of x_new and ||x_new - x_old||_1 to partials_out.
+// block's dangling mass of x_new and, with RESID, ||x_new - x_old||_1 to
+// partials_out (without RESID x_old is not read and the second component is
+// 0: the l1 change is needed only where the host reads it).
 // With hot_n > 0 it also writes the hot-column copy of x_new that the next
 // SpMV's LDS cache reads (x_hot[s] = x_new[hot_cols[s]], the same fused
 // multiply-add on the same operands), so that SpMV needs no gather launch.
-template <typename V>
+template <typename V, bool RESID>
 __global__ __launch_bounds__(kReduceThreads) void pr_update_kernel(
     const V* __restrict__ y, const V* __restrict__ x_old, V* __restrict__ x_new,
     const uint32_t* __restrict__ dmask, int64_t n, double alpha,
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(kReduceThreads) void pr_update_kernel(
     for (int u = 0; u < ILP; ++u) {
       const int64_t i = min(base + (int64_t)u * kReduceThreads, n - 1);
       yv[u] = y[i];
-      xo[u] = x_old[i];
+      if constexpr (RESID) xo[u] = x_old[i];
       mw[u] = dmask[i >> 5];
     }
 #pragma unroll
@@ -165,7 +167,7 @@ __global__ __launch_bounds__(kReduceThreads) void pr_update_kernel(
       if (i < n) {
         const V xn = fma(a, yv[u], teleport);
         x_new[i] = xn;
-        rsum += fabs((double)xn - (double)xo[u]);
+        if constexpr (RESID) rsum += fabs((double)xn - (double)xo[u]);
         if ((mw[u] >> (i & 31)) & 1u) dsum += (double)xn;
       }
     }
@@ -180,21 +182,37 @@ __global__ __launch_bounds__(kReduceThreads) void pr_update_kernel(
   }
 }
 
+template <typename V>
+static void pr_update_launch(bool resid, const void* y, const void* x_old, void* x_new,
+                             const uint32_t* dmask, int64_t n, double alpha,
+                             const double* partials_in, int n_in, double* partials_out, int grid,
+                             hipStream_t st, const int32_t* hot_cols, int32_t hot_n,
+                             void* x_hot) {
+  const V* yv = static_cast<const V*>(y);
+  const V* xo = static_cast<const V*>(x_old);
+  V* xn = static_cast<V*>(x_new);
+  V* xh = static_cast<V*>(x_hot);
+  if (resid)
+    hipLaunchKernelGGL((pr_update_kernel<V, true>), dim3(grid), dim3(kReduceThreads), 0, st, yv,
+                       xo, xn, dmask, n, alpha, partials_in, n_in, partials_out, hot_cols, hot_n,
+                       xh);
+  else
+    hipLaunchKernelGGL((pr_update_kernel<V, false>), dim3(grid), dim3(kReduceThreads), 0, st,
+                       yv, xo, xn, dmask, n, alpha, partials_in, n_in, partials_out, hot_cols,
+                       hot_n, xh);
+}
+
 hipError_t launch_pr_update(int dtype, const void* y, const void* x_old, void* x_new,
                             const uint32_t* dmask, int64_t n, double alpha,
                             const double* partials_in, int n_in, double* partials_out, int grid,
                             hipStream_t st, const int32_t* hot_cols, int32_t hot_n,
-                            void* x_hot) {
+                            void* x_hot, bool resid) {
   if (dtype == 0)
-    hipLaunchKernelGGL(pr_update_kernel<float>, dim3(grid), dim3(kReduceThreads), 0, st,
-                       static_cast<const float*>(y), static_cast<const float*>(x_old),
-                       static_cast<float*>(x_new), dmask, n, alpha, partials_in, n_in,
-                       partials_out, hot_cols, hot_n, static_cast<float*>(x_hot));
+    pr_update_launch<float>(resid, y, x_old, x_new, dmask, n, alpha, partials_in, n_in,
+                            partials_out, grid, st, hot_cols, hot_n, x_hot);
   else
-    hipLaunchKernelGGL(pr_update_kernel<double>, dim3(grid), dim3(kReduceThreads), 0, st,
-                       static_cast<const double*>(y), static_cast<const double*>(x_old),
-                       static_cast<double*>(x_new), dmask, n, alpha, partials_in, n_in,
-                       partials_out, hot_cols, hot_n, static_cast<double*>(x_hot));
+    pr_update_launch<double>(resid, y, x_old, x_new, dmask, n, alpha, partials_in, n_in,
+                             partials_out, grid, st, hot_cols, hot_n, x_hot);
   return hipGetLastError();
 }
 
