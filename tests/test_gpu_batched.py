@@ -250,6 +250,38 @@ def test_personalized_pagerank_convergence_and_reuse(k, dtype):
     plan.close()
 
 
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+@pytest.mark.parametrize("n,density,empty_frac,long_rows,sigma",
+                         [(1, 1.0, 0.0, (), 1), (2, 0.5, 0.0, (), 2), (7, 0.3, 0.2, (), 3),
+                          (65, 0.05, 0.2, (), 5), (200, 0.01, 0.3, (), 4),
+                          (300, 0.02, 0.2, (17,), 12)],
+                         ids=["n1", "n2", "n7", "n65", "n200", "n300"])
+def test_personalized_pagerank_tiny_graphs(n, density, empty_frac, long_rows, sigma, dtype):
+    """Tiny square graphs (empty rows, dangling vertices, a dense row that
+    fills single-row tiles, tiles of a few rows) with 33 and then 64 sources
+    on the same plan (slabs of 32 + 1 and 32 + 32 columns; sources repeat
+    when n < k), 13 iterations in chunks of 4, every entry against the
+    oracle."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    rp, col, _ = graphgen.random_csr(n, n, density, seed=n, empty_frac=empty_frac,
+                                     long_rows=long_rows)
+    assert len(col) > 0
+    vals = graphgen.column_stochastic_values(col, n)
+    r, c, v = to_device(rp, col, vals, dtype, dev)
+    plan = pkg.Plan(r, c, v, n, sigma=sigma)
+    vh = host_values(vals, dtype)
+    for k in (33, 64):
+        src = ((np.arange(k) * 7 + 3) % n).astype(np.int32)
+        X, iters, resid, _ = plan.pagerank_personalized(src, alpha=ALPHA, max_iter=13,
+                                                        check_every=4)
+        torch.cuda.synchronize()
+        assert iters == 13 and resid.shape == (k,)
+        ref = oracle.personalized_pagerank(rp, col, vh, ALPHA, 13, src)
+        _ppr_check(X, ref, dtype, f"n={n} k={k}")
+    plan.close()
+
+
 def test_personalized_pagerank_rmat22():
     """64 sources on R-MAT scale 22, FP32, 5 iterations; four sampled columns
     are checked in full against the oracle, all 64 columns for mass 1."""
