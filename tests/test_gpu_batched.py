@@ -282,24 +282,28 @@ def test_personalized_pagerank_tiny_graphs(n, density, empty_frac, long_rows, si
     plan.close()
 
 
-def test_personalized_pagerank_rmat22():
-    """64 sources on R-MAT scale 22, FP32, 5 iterations; four sampled columns
-    are checked in full against the oracle, all 64 columns for mass 1."""
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f32", "f64"])
+def test_personalized_pagerank_rmat22(dtype):
+    """64 sources on R-MAT scale 22 (the benchmark's workload: two compact
+    32-column slabs of 4.19M rows), 5 iterations; four sampled columns, two
+    in each slab, are checked in full against the oracle, all 64 columns for
+    mass 1."""
     import paper_2605_07391_amd as pkg
     dev = require_gpu()
     w = workload("rmat22")
     rp, col, vals, n = w["row_ptr"], w["col"], w["values"], w["n_rows"]
-    r, c, v = to_device(rp, col, vals, torch.float32, dev)
+    r, c, v = to_device(rp, col, vals, dtype, dev)
     plan = pkg.Plan(r, c, v, n)
     src = graphgen.ppr_sources(n, 64, seed=4)
     X, iters, _, _ = plan.pagerank_personalized(src, alpha=ALPHA, max_iter=5)
     torch.cuda.synchronize()
+    assert iters == 5
     mass = X.double().sum(0).cpu().numpy()
-    assert np.all(np.abs(mass - 1.0) <= 1e-5)
-    vh = host_values(vals, torch.float32)
+    assert np.all(np.abs(mass - 1.0) <= (1e-5 if dtype == torch.float32 else 1e-12))
+    vh = host_values(vals, dtype)
     for j in (0, 21, 42, 63):
         ref = oracle.personalized_pagerank(rp, col, vh, ALPHA, 5, [src[j]])[:, 0]
-        _ppr_check(X[:, j:j + 1], ref[:, None], torch.float32, f"column {j}")
+        _ppr_check(X[:, j:j + 1], ref[:, None], dtype, f"column {j}")
     plan.close()
 
 
