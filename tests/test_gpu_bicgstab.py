@@ -169,3 +169,37 @@ def test_graph_replays_match_eager():
         assert torch.isfinite(y).all()
     g_plan.close()
     e_plan.close()
+
+
+@pytest.mark.parametrize("config", ["striped8_tuned", "plain"])
+def test_bicgstab_rmat21_benchmark_system(config):
+    """The benchmark's BiCGSTAB system at full size: the symmetric 0/1 R-MAT
+    scale-21 matrix (2.1M rows, 63.5M nonzeros), FP64, b = A x_true computed
+    by the oracle, on the 8-stripe plan with the tuned FP64 options (sigma
+    20, 64-bit descriptors, 512 lanes) and on a plain plan.  The first 3
+    iterates against the oracle's (the system amplifies rounding quickly, as
+    in the smaller construction test), then 30 iterations in chunks of 10:
+    the reported residual against the true residual of the returned x."""
+    import paper_2605_07391_amd as pkg
+    dev = require_gpu()
+    w = graphgen.workload("rmat21_sym")
+    rp, col, vals, n = w["row_ptr"], w["col"], w["values"], w["n_rows"]
+    b = oracle.spmv(rp, col, vals, w["x"])
+    kw = ({"stripes": 8, "sigma": 20, "desc_bits": 64, "block_lanes": 512, "commit": "wave"}
+          if config == "striped8_tuned" else {})
+    plan, keep = _plan(rp, col, vals, torch.float64, dev, validate=False, **kw)
+    bt = torch.from_numpy(b).to(dev)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    plan.bicgstab(bt, x, tol=0.0, max_iter=3)
+    torch.cuda.synchronize()
+    ref, _, _, _ = oracle.bicgstab(rp, col, vals, b, np.zeros(n), 1e-300, 3)
+    err = np.abs(x.cpu().numpy() - ref).max() / np.abs(ref).max()
+    print(f"bicgstab rmat21 {config}: 3-iterate error {err:.3e}", flush=True)
+    assert err <= 1e-9
+    x.zero_()
+    it, res, _ = plan.bicgstab(bt, x, tol=0.0, max_iter=30, check_every=10)
+    torch.cuda.synchronize()
+    assert it == 30 and 0.0 < res < 1.0
+    true_res = np.linalg.norm(b - oracle.spmv(rp, col, vals, x.cpu().numpy())) / np.linalg.norm(b)
+    assert abs(true_res - res) <= 1e-6 * res + 1e-12, (true_res, res)
+    plan.close()
