@@ -145,36 +145,57 @@ __global__ __launch_bounds__(kReduceThreads) void pr_update_kernel(
     const double* __restrict__ partials_in, int n_in, double* __restrict__ partials_out,
     const int32_t* __restrict__ hot_cols, int32_t hot_n, V* __restrict__ x_hot) {
   constexpr int ILP = 4;
-  const double delta = sum_partials_first(partials_in, n_in);
-  const V teleport = (V)((alpha * delta + 1.0 - alpha) / (double)n);
   const V a = (V)alpha;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x * ILP;
-  double dsum = 0.0, rsum = 0.0;
-  for (int64_t base = (int64_t)blockIdx.x * blockDim.x * ILP + threadIdx.x; base < n;
-       base += stride) {
-    V yv[ILP], xo[ILP];
-    uint32_t mw[ILP];
+  const int64_t hstride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t h0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // one pass of ILP elements per thread; the next pass's loads go out before
+  // the current one is used, and the first pass's (with the first hot
+  // column) before the previous step's partials are summed
+  auto load = [&](int64_t b, V (&yv)[ILP], V (&xo)[ILP], uint32_t (&mw)[ILP]) {
 #pragma unroll
     for (int u = 0; u < ILP; ++u) {
-      const int64_t i = min(base + (int64_t)u * kReduceThreads, n - 1);
+      const int64_t i = min(b + (int64_t)u * kReduceThreads, n - 1);
       yv[u] = y[i];
       if constexpr (RESID) xo[u] = x_old[i];
       mw[u] = dmask[i >> 5];
     }
+  };
+  int64_t base = (int64_t)blockIdx.x * blockDim.x * ILP + threadIdx.x;
+  V yv[ILP], xo[ILP];
+  uint32_t mw[ILP];
+  if (base < n) load(base, yv, xo, mw);
+  const int32_t hc0 = h0 < hot_n ? hot_cols[h0] : 0;
+  const double delta = sum_partials_first(partials_in, n_in);
+  const V teleport = (V)((alpha * delta + 1.0 - alpha) / (double)n);
+  double dsum = 0.0, rsum = 0.0;
+  while (base < n) {
+    const int64_t next = base + stride;
+    V yn[ILP], xn[ILP];
+    uint32_t mn[ILP];
+    if (next < n) load(next, yn, xn, mn);
 #pragma unroll
     for (int u = 0; u < ILP; ++u) {
       const int64_t i = base + (int64_t)u * kReduceThreads;
       if (i < n) {
-        const V xn = fma(a, yv[u], teleport);
-        x_new[i] = xn;
-        if constexpr (RESID) rsum += fabs((double)xn - (double)xo[u]);
-        if ((mw[u] >> (i & 31)) & 1u) dsum += (double)xn;
+        const V v = fma(a, yv[u], teleport);
+        x_new[i] = v;
+        if constexpr (RESID) rsum += fabs((double)v - (double)xo[u]);
+        if ((mw[u] >> (i & 31)) & 1u) dsum += (double)v;
+      }
+    }
+    base = next;
+    if (base < n) {
+#pragma unroll
+      for (int u = 0; u < ILP; ++u) {
+        yv[u] = yn[u];
+        if constexpr (RESID) xo[u] = xn[u];
+        mw[u] = mn[u];
       }
     }
   }
-  for (int64_t h = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; h < hot_n;
-       h += (int64_t)gridDim.x * blockDim.x)
-    x_hot[h] = fma(a, y[hot_cols[h]], teleport);
+  for (int64_t h = h0; h < hot_n; h += hstride)
+    x_hot[h] = fma(a, y[h == h0 ? hc0 : hot_cols[h]], teleport);
   block_sum2(dsum, rsum);
   if (threadIdx.x == 0) {
     partials_out[2 * blockIdx.x] = dsum;
