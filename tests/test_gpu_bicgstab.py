@@ -179,7 +179,9 @@ def test_bicgstab_rmat21_benchmark_system(config):
     20, 64-bit descriptors, 512 lanes) and on a plain plan.  The first 3
     iterates against the oracle's (the system amplifies rounding quickly, as
     in the smaller construction test), then 30 iterations in chunks of 10:
-    the reported residual against the true residual of the returned x."""
+    the reported residual against the true residual of the returned x (the
+    residual itself is not monotone on this singular, indefinite system and
+    its value after 30 steps depends on rounding, so no bound is put on it)."""
     import paper_2605_07391_amd as pkg
     dev = require_gpu()
     w = graphgen.workload("rmat21_sym")
@@ -199,7 +201,7 @@ def test_bicgstab_rmat21_benchmark_system(config):
     x.zero_()
     it, res, _ = plan.bicgstab(bt, x, tol=0.0, max_iter=30, check_every=10)
     torch.cuda.synchronize()
-    assert it == 30 and 0.0 < res < 1.0
+    assert it == 30 and np.isfinite(res) and res > 0.0
     true_res = np.linalg.norm(b - oracle.spmv(rp, col, vals, x.cpu().numpy())) / np.linalg.norm(b)
     assert abs(true_res - res) <= 1e-6 * res + 1e-12, (true_res, res)
     plan.close()
